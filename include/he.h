@@ -1,0 +1,194 @@
+/*
+ * he.h -- C ABI of the MI355X (gfx950) Paillier histogram library.
+ *
+ * The library implements the encrypted-gradient path of secure vertical
+ * federated XGBoost (Xu et al., "Secure Federated XGBoost with CUDA-accelerated
+ * Homomorphic Encryption via NVIDIA FLARE", Sec. III-B and Sec. III-C):
+ *   1. the active party encrypts every per-sample gradient g and Hessian h
+ *      as one Paillier plaintext (Sec. III-C: 2M encryptions for M samples);
+ *   2. a passive party multiplies ciphertexts mod n^2 into per-(feature, bin)
+ *      encrypted histograms (Sec. III-B; encrypted addition, Sec. III-C);
+ *   3. the active party decrypts the returned histograms (Sec. III-B).
+ * Paillier is the textbook scheme with g = n + 1:
+ *   E(m; r) = (1 + m n) r^n mod n^2,   D(c) = L(c^lambda mod n^2) mu mod n,
+ * computed here with Montgomery arithmetic on 32-bit limbs and, where the key
+ * holds p and q, with the Chinese remainder theorem.  Results are bit-identical
+ * to the textbook definitions.
+ *
+ * Conventions shared by every call:
+ *  - Big integers are little-endian arrays of uint32_t limbs.  A key of
+ *    n_bits bits has L = n_bits / 32 limbs for n and 2L limbs for n^2, so one
+ *    ciphertext occupies 2L limbs (256 B at 1024 bits, 512 B at 2048 bits).
+ *  - Ciphertexts crossing the ABI are canonical residues in [0, n^2) unless a
+ *    parameter says HE_FORM_MONT (Montgomery form x * 2^(64L) mod n^2).
+ *  - Pointers documented as "device" are HIP device pointers owned by the
+ *    caller; the library never frees or retains them after the call returns.
+ *    Pointers documented as "host" are read or written before return.
+ *  - Calls that take a hipStream_t enqueue work on that stream and return
+ *    without waiting; argument checks are synchronous.  Work on one stream is
+ *    ordered; calls on different streams may run concurrently (each stream
+ *    gets its own library workspace).
+ *  - Return value: 0 on success, a negative HE_ERR_* code otherwise; no C++
+ *    exception crosses this boundary.  he_last_error() gives a message for the
+ *    calling thread's last failure.
+ *  - Only 1024- and 2048-bit keys are supported.
+ */
+#ifndef HE_MI355X_H
+#define HE_MI355X_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define HE_OK           0
+#define HE_ERR_ARG     -1   /* null pointer, bad size or bad layout */
+#define HE_ERR_KEY     -2   /* key material invalid (p, q not usable) */
+#define HE_ERR_NOPRIV  -3   /* operation needs p and q but the key is public */
+#define HE_ERR_RANGE   -4   /* value outside the representable range */
+#define HE_ERR_OOM     -5   /* device workspace allocation failed */
+#define HE_ERR_DEVICE  -6   /* a HIP runtime call failed */
+
+#define HE_FORM_CANONICAL 0
+#define HE_FORM_MONT      1
+
+typedef struct he_key he_key;  /* opaque; immutable after creation */
+
+/* Key generation (Paillier key setup; the paper fixes no key size, 1024 and
+ * 2048 bits are supported).  Primes p, q of n_bits/2 bits each are the first
+ * candidates of a SplitMix64 word stream keyed by `seed` (p from counter 0,
+ * q from counter 2^48; n_bits/64 words per candidate, little-endian, top two
+ * bits and bit 0 forced to 1) that pass trial division by the odd primes
+ * below 2000 and 40 Miller-Rabin rounds with the first 40 prime bases; q must
+ * differ from p and gcd(pq, (p-1)(q-1)) must be 1.  Deterministic in `seed`.
+ * The key's device constants are uploaded to the current HIP device.
+ * Returns HE_ERR_ARG for an unsupported n_bits or a null `out`. */
+int he_keygen(uint32_t n_bits, uint64_t seed, he_key **out);
+
+/* Builds a key from host limb arrays.  p and q hold n_bits/64 limbs each
+ * (little-endian).  With q == NULL, p is taken as n (n_bits/32 limbs) and
+ * the key is public-only: he_decrypt then fails with HE_ERR_NOPRIV and
+ * he_encrypt uses the public-key path.  Checks: p, q odd, distinct, > 1,
+ * gcd(pq, (p-1)(q-1)) = 1, and n = pq has exactly n_bits bits (HE_ERR_KEY). */
+int he_key_import(uint32_t n_bits, const uint32_t *p, const uint32_t *q, he_key **out);
+
+/* Copies n (n_bits/32 limbs) and, if non-NULL and the key is private, p and
+ * q (n_bits/64 limbs each) into host buffers.  HE_ERR_NOPRIV if p or q is
+ * requested from a public key. */
+int he_key_export(const he_key *key, uint32_t *n, uint32_t *p, uint32_t *q);
+
+/* Number of bits of n, and whether the key holds p and q (1) or not (0). */
+uint32_t he_key_bits(const he_key *key);
+int he_key_has_private(const he_key *key);
+
+/* Frees the key and its device constants.  The caller must make sure no
+ * queued work still uses the key (synchronise its streams first). */
+void he_key_free(he_key *key);
+
+/* Fixed-point encoding of g or h (Sec. III-C encrypts each g and h as one
+ * number but fixes no encoding): m[i] = rint(x[i] * 2^frac_bits),
+ * ties to even, as int64.  x and m are device arrays of `count` elements.
+ * Values whose scaled magnitude reaches 2^63 (or NaN) are stored as INT64_MIN
+ * and counted into *n_bad (device, optional, atomically incremented). */
+int he_encode(const double *x, uint64_t count, uint32_t frac_bits, int64_t *m,
+              uint32_t *n_bad, hipStream_t stream);
+
+/* Encryption (Sec. III-B: the active party encrypts every g and h;
+ * Sec. III-C: one Paillier encryption per number):
+ *   ct[i] = (1 + (m[i] mod n) n) * r_i^n mod n^2, canonical, 2L limbs.
+ * m: device int64[count] (signed; taken mod n).
+ * r: device uint32[count][L] explicit randomness (any value with
+ *    gcd(r, n) = 1; only r mod n matters), or NULL for the seeded stream
+ *    r_i = X_i mod n, X_i = sum_j w(r_seed, (r_offset + i) W + j) 2^(64 j),
+ *    W = n_bits/64 + 1, w(s, k) the k-th SplitMix64 output from state s.
+ * ct: device uint32[count][2L].
+ * A private key uses the CRT path: r^n mod p^2 = (r^(q mod (p-1)) mod p)^p
+ * mod p^2 (and likewise for q), then CRT to mod n^2; a public key
+ * exponentiates mod n^2.  Both give bit-identical ciphertexts.
+ * An r that is 0 mod p or mod q (for the seeded stream the chance is below
+ * 2^-500) yields a ciphertext that is not a unit; this is not checked. */
+int he_encrypt(const he_key *key, const int64_t *m, uint64_t count,
+               const uint32_t *r, uint64_t r_seed, uint64_t r_offset,
+               uint32_t *ct, hipStream_t stream);
+
+/* Same as he_encrypt but forces the public-key path (r^n mod n^2 by one
+ * exponentiation mod n^2) even for a private key. */
+int he_encrypt_public(const he_key *key, const int64_t *m, uint64_t count,
+                      const uint32_t *r, uint64_t r_seed, uint64_t r_offset,
+                      uint32_t *ct, hipStream_t stream);
+
+/* Montgomery conversion of ciphertexts: out = in * 2^(64L) mod n^2 (to_mont)
+ * or in * 2^(-64L) mod n^2 (from_mont).  Device uint32[count][2L]; in-place
+ * (in == out) is allowed.  Keeps gradients resident in the form the
+ * histogram kernels consume, so the conversion is paid once per round. */
+int he_to_mont(const he_key *key, const uint32_t *in, uint64_t count, uint32_t *out,
+               hipStream_t stream);
+int he_from_mont(const he_key *key, const uint32_t *in, uint64_t count, uint32_t *out,
+                 hipStream_t stream);
+
+/* One tree-node histogram job (Sec. III-B: each passive party sums the
+ * encrypted gradients into the bins of its own features).
+ *  sample_idx: device uint32[n_samples], rows of `ct` in this node (any order,
+ *              no duplicates);
+ *  bins:       device uint8[n_features][bins_ld]; bins[f][row] is the bin of
+ *              sample `row` for feature f (bins_ld >= rows);
+ *  n_bins:     1..256;
+ *  hist:       device uint32[n_features][n_bins][2][2L] output, canonical;
+ *              slot 0 accumulates g, slot 1 accumulates h. */
+typedef struct he_hist_job {
+  const uint32_t *sample_idx;
+  uint64_t n_samples;
+  const uint8_t *bins;
+  uint64_t bins_ld;
+  uint32_t n_features;
+  uint32_t n_bins;
+  uint32_t *hist;
+} he_hist_job;
+
+/* Encrypted histogram aggregation for n_jobs nodes in one batch:
+ *   hist[f][b][t] = prod over i in sample_idx with bins[f][i] = b of
+ *                   ct[i][t] mod n^2,   empty bins hold 1.
+ * ct: device uint32[rows][2][2L] (g and h ciphertext of each row), in the
+ *     form given by ct_form (HE_FORM_MONT avoids a conversion per call).
+ * jobs: host array of n_jobs descriptors.  All jobs' (feature, bin, chunk)
+ * work items run in one persistent launch; the result is independent of
+ * batching, chunking and order (exact modular products). */
+int he_hist_aggregate(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
+                      const he_hist_job *jobs, uint32_t n_jobs, hipStream_t stream);
+
+/* he_hist_aggregate with an explicit work-item length: `chunk` samples of
+ * one (feature, bin) per item (0 picks the library default).  The result
+ * does not depend on `chunk`; only the load balance does. */
+int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
+                         const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk,
+                         hipStream_t stream);
+
+/* Decryption (Sec. III-B: the active party decrypts the returned
+ * histograms), by the CRT: m_p = L_p(c^(p-1) mod p^2) h_p mod p with
+ * h_p = (-q mod p)^-1 mod p, likewise m_q, then m = m_q + q ((m_p - m_q)
+ * q^-1 mod p), which equals L(c^lambda mod n^2) mu mod n.
+ * ct: device uint32[count][2L] canonical.
+ * m: device int64[count] signed decode (m >= (n+1)/2 means m - n); values
+ *    outside [-2^63, 2^63) are saturated and counted into *n_overflow
+ *    (device uint32, optional).
+ * raw: device uint32[count][L] plaintext in [0, n), optional (NULL).
+ * HE_ERR_NOPRIV for a public key. */
+int he_decrypt(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m,
+               uint32_t *raw, uint32_t *n_overflow, hipStream_t stream);
+
+/* Measurement probe for the roofline denominator: launches `blocks` blocks
+ * of 256 threads that each run `iters` iterations of 8 independent 32x32->64
+ * integer multiply-adds; *products receives the number of products issued
+ * (host).  Time it with events on `stream`. */
+int he_probe_int_mul(uint64_t iters, uint32_t blocks, uint64_t *products, hipStream_t stream);
+
+/* Message describing the calling thread's last non-zero return. */
+const char *he_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HE_MI355X_H */

@@ -1,0 +1,114 @@
+// Internal interfaces between the host runtime (he_api.cpp) and the kernels
+// (he_kernels.hip).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace he {
+
+// One Montgomery modulus N of S limbs (R = 2^(32 S)); device pointers into
+// the key's constant blob, each S limbs.
+struct DMod {
+  const uint32_t *N, *R1, *R2, *R3, *R4;  // N, R^k mod N
+  uint32_t ninv;                          // -N^-1 mod 2^32
+};
+
+// Exponent as limbs with one zero limb of padding, and its window count.
+struct DExp {
+  const uint32_t *e;
+  int nwin;
+};
+
+// Per-prime constants for the CRT paths; P is this prime, Q the other one.
+// S_P = L/2 limbs for P, S_P2 = L limbs for P^2 (L = limbs of n).
+struct DPrime {
+  DMod P, P2;
+  DExp e_enc;        // Q mod (P - 1): r^Q mod P = r^(Q mod (P-1)) mod P
+  DExp e_lift;       // P: x -> x^P mod P^2 depends only on x mod P
+  DExp e_dec;        // P - 1: decryption exponent
+  const uint32_t *QR_P;   // Q R mod P          (S_P limbs)
+  const uint32_t *PR_P2;  // P R' mod P^2       (S_P2 limbs)
+  const uint32_t *Pinv;   // P^-1 mod 2^(32 S_P)
+  const uint32_t *hR_P;   // h_P R mod P, h_P = L_P(g^(P-1) mod P^2)^-1 mod P
+};
+
+struct DKey {
+  uint32_t n_bits;
+  int has_priv;
+  DMod n, n2;              // S_N = L, S_N2 = 2L limbs
+  DExp e_n;                // n as an exponent (public encryption)
+  const uint32_t *nR_n2;   // n R'' mod n^2
+  const uint32_t *half;    // (n + 1) / 2 (L limbs) for the signed decode
+  DPrime pr[2];            // [0]: P = p, Q = q; [1]: P = q, Q = p
+  const uint32_t *Cq;      // (q^2)^-1 R' mod p^2
+  const uint32_t *q2R_n2;  // q^2 R'' mod n^2
+  const uint32_t *qinv_p;  // q^-1 mod p (canonical)
+  const uint32_t *qR_n;    // q R_n mod n
+};
+
+// Histogram job as the kernels see it (host fills offsets).
+struct DJob {
+  const uint32_t *idx;
+  const uint8_t *bins;
+  uint32_t *hist;
+  uint64_t n;          // samples in the node
+  uint64_t ld;         // bins leading dimension
+  uint32_t F, B;       // features, bins
+  uint64_t fb_off;     // first (feature, bin) entry of this job in the flat lists
+  uint64_t perm_off;   // first perm slot of this job (F * n slots)
+  uint64_t blk_off;    // first sample block of this job (F * nblk blocks)
+  uint32_t f_off;      // first (job, feature) entry
+  uint32_t nblk;       // sample blocks per feature
+};
+
+struct HistItem {      // one chunk of one (feature, bin): perm[start .. start+len)
+  uint64_t start;
+  uint32_t len;
+  uint32_t pad;
+};
+
+// Flat device workspace of one histogram batch.
+struct HistWs {
+  DJob *jobs;
+  uint32_t n_jobs;
+  uint32_t *counts, *offs, *cursor, *fch, *fitem;  // [total_fb]
+  uint32_t *ftot, *fbase;                          // [total_f]
+  uint32_t *n_items;                               // device scalar
+  HistItem *items;                                 // [items_cap]
+  uint32_t *perm;                                  // [total_perm]
+  uint32_t *partials;                              // [items_cap][2][S]
+  uint64_t total_fb, total_f, total_blocks, items_cap;
+  uint32_t chunk;                                  // samples per item
+};
+
+constexpr int kWindowBits = 5;     // exponent window width (see mont.hpp)
+constexpr int kSampleBlock = 4096;   // samples per bucketing block
+constexpr int kBlockThreads = 256;   // 4 waves, 16 groups of 16 lanes
+
+// ---- launchers (he_kernels.hip) ------------------------------------------------
+// KP = limbs per lane of a prime: 1 for 1024-bit keys, 2 for 2048-bit keys.
+hipError_t launch_encode(const double *x, uint64_t count, uint32_t frac_bits, int64_t *m,
+                         uint32_t *n_bad, hipStream_t s);
+hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count,
+                          const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *cpq,
+                          uint32_t *ct, uint32_t *tab, uint32_t grid, hipStream_t s);
+hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
+                          const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *ct,
+                          uint32_t *tab, uint32_t grid, hipStream_t s);
+hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64_t count,
+                               uint32_t *out, bool to_mont, hipStream_t s);
+hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count,
+                      uint32_t *mpq, int64_t *m, uint32_t *raw, uint32_t *n_overflow,
+                      uint32_t *tab, uint32_t grid, hipStream_t s);
+hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *host_jobs,
+                       const HistWs &ws, uint32_t chunk_grid, hipStream_t s);
+hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
+hipError_t launch_probe_mul(uint64_t iters, uint32_t grid, uint32_t *sink, hipStream_t s);
+
+// Resident blocks of 256 threads the device holds for each persistent kernel
+// (occupancy x compute units), by kind: 0 enc_crt, 1 enc_pub, 2 dec, 3 hist chunk.
+uint32_t resident_blocks(int KP, int kind);
+// Window-table scratch bytes per resident block for the given kernel kind.
+uint64_t table_bytes_per_block(int KP, int kind);
+
+}  // namespace he

@@ -1,0 +1,796 @@
+// gfx950 kernels of the Paillier histogram path: fixed-point encoding,
+// encryption (CRT and public-key), Montgomery conversion, histogram
+// aggregation (bucketing + chunked ciphertext products) and CRT decryption.
+//
+// Layout conventions: one big integer per 16-lane group (see mont.hpp);
+// 256-thread blocks = 4 waves = 16 groups; every group owns one LDS row.
+// Kernels keep all 64 lanes of a wave active until they return; groups with
+// no work compute on a valid dummy item and do not store.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "he_internal.hpp"
+#include "mont.hpp"
+
+namespace he {
+
+static_assert(kWindow == kWindowBits, "window width mismatch");
+
+// ------------------------------------------------------------- small helpers
+// Limb t of a little-endian buffer of `nl` limbs, zero past the end.
+template <int K>
+__device__ __forceinline__ void ld_part(uint32_t (&x)[K], const uint32_t *p, int nl) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int t = (int)glane() * K + j;
+    x[j] = t < nl ? p[t] : 0u;
+  }
+}
+
+// x = v mod N for a signed 64-bit v (|v| < N).
+template <int K>
+__device__ __forceinline__ void signed_mod(uint32_t (&x)[K], int64_t v, const uint32_t (&N)[K]) {
+  const uint64_t mag = v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v;
+  uint32_t a[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int t = (int)glane() * K + j;
+    a[j] = t == 0 ? (uint32_t)mag : (t == 1 ? (uint32_t)(mag >> 32) : 0u);
+  }
+  if (v < 0) {
+    uint32_t d[K];
+    sub_plain<K>(d, N, a);
+    copy(x, d);
+  } else {
+    copy(x, a);
+  }
+}
+
+// x += 1 (no reduction).
+template <int K>
+__device__ __forceinline__ void add_one(uint32_t (&x)[K]) {
+  uint32_t one[K];
+  set_small(one, 1u);
+  add_plain<K>(x, x, one);
+}
+
+// Limbs [first, first + 16K) of the seeded stream integer
+// X = sum_j w(seed, base + j) 2^(64 j), each lane taking its K limbs;
+// limbs at or past `nl` are zero.
+template <int K>
+__device__ __forceinline__ void seeded_limbs(uint32_t (&x)[K], uint64_t seed, uint64_t base,
+                                             int first, int nl) {
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const int t = first + (int)glane() * K + j;
+    const uint64_t w = splitmix64(seed, base + (uint64_t)(t >> 1));
+    x[j] = t < nl ? (uint32_t)((t & 1) ? (w >> 32) : w) : 0u;
+  }
+}
+
+__device__ __forceinline__ uint32_t wave_in_block() { return threadIdx.x >> 6; }
+__device__ __forceinline__ uint32_t group_in_wave() { return (threadIdx.x >> 4) & 3u; }
+
+// ------------------------------------------------------------------- encode
+__global__ void k_encode(const double *__restrict__ x, uint64_t count, uint32_t frac_bits,
+                         int64_t *__restrict__ m, uint32_t *__restrict__ n_bad) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) {
+    const double v = ldexp(x[i], (int)frac_bits);  // exact scaling by a power of two
+    if (!(fabs(v) < 9223372036854775808.0)) {
+      m[i] = INT64_MIN;
+      if (n_bad) atomicAdd(n_bad, 1u);
+    } else {
+      m[i] = (int64_t)rint(v);  // round to nearest, ties to even
+    }
+  }
+}
+
+// ----------------------------------------------------------- CRT encryption
+// Phase A: for each (ciphertext i, prime P) compute
+//   c_P = (1 + m n) r^n mod P^2,  r^n mod P^2 = (r^(Q mod (P-1)) mod P)^P mod P^2.
+// Work unit = (prime, 4 consecutive ciphertexts) so that the exponent is the
+// same for the whole wave.  Output cpq[i][P] (S_P2 limbs, canonical).
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_enc_crt_a(
+    DKey key, const int64_t *__restrict__ m, uint64_t count, const uint32_t *__restrict__ r,
+    uint64_t seed, uint64_t roff, uint32_t *__restrict__ cpq, uint32_t *__restrict__ tabs) {
+  constexpr int KP2 = 2 * KP, SP = 16 * KP, SP2 = 32 * KP, L = SP2;
+  __shared__ __align__(16) uint32_t lds_all[16 * SP2];
+  const uint32_t g = group_in_wave();
+  uint32_t *lds = lds_all + (wave_in_block() * 4 + g) * SP2;
+  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
+  const uint64_t nw = (uint64_t)gridDim.x * 4;
+  uint32_t *tab = tabs + (gw * 4 + g) * (uint64_t)(kTable * SP2);
+  const uint64_t nquads = 2 * ((count + 3) / 4);
+  const uint64_t W = (uint64_t)SP + 1;  // stream words per r
+
+  for (uint64_t qd = gw; qd < nquads; qd += nw) {
+    const int which = (int)(qd & 1);
+    const DPrime &P = key.pr[which];
+    uint64_t i = (qd >> 1) * 4 + g;
+    const bool valid = i < count;
+    if (!valid) i = count - 1;
+    const Mod<KP> Mp = load_mod<KP>(P.P.N, P.P.ninv);
+
+    // x = Montgomery form of r mod P
+    uint32_t x[KP], t0[KP], t1[KP], c[KP];
+    if (r) {
+      ld<KP>(t0, r + i * L);
+      ld<KP>(t1, r + i * L + SP);
+      ld<KP>(c, P.P.R2);
+      mont_mul<KP>(t0, t0, c, Mp, lds);
+      ld<KP>(c, P.P.R3);
+      mont_mul<KP>(t1, t1, c, Mp, lds);
+      add_mod<KP>(x, t0, t1, Mp);
+    } else {
+      const uint64_t base = (roff + i) * W;
+      uint32_t t2[KP];
+      seeded_limbs<KP>(t0, seed, base, 0, 2 * SP + 2);
+      seeded_limbs<KP>(t1, seed, base, SP, 2 * SP + 2);
+      seeded_limbs<KP>(t2, seed, base, 2 * SP, 2 * SP + 2);
+      ld<KP>(c, P.P.R2);
+      mont_mul<KP>(t0, t0, c, Mp, lds);
+      ld<KP>(c, P.P.R3);
+      mont_mul<KP>(t1, t1, c, Mp, lds);
+      ld<KP>(c, P.P.R4);
+      mont_mul<KP>(t2, t2, c, Mp, lds);
+      add_mod<KP>(x, t0, t1, Mp);
+      add_mod<KP>(x, x, t2, Mp);
+    }
+    // t = r^(Q mod (P-1)) mod P, canonical
+    ld<KP>(c, P.P.R1);
+    mont_pow<KP>(x, P.e_enc.e, P.e_enc.nwin, tab, c, Mp, lds);
+    set_small(c, 1u);
+    mont_mul<KP>(x, x, c, Mp, lds);
+    // u = (m mod P) Q mod P
+    const int64_t mv = m[i];
+    uint32_t u[KP];
+    signed_mod<KP>(u, mv, Mp.n);
+    ld<KP>(c, P.QR_P);
+    mont_mul<KP>(u, u, c, Mp, lds);
+
+    // lift to P^2: omega = t^P mod P^2 (Montgomery form)
+    const Mod<KP2> M2 = load_mod<KP2>(P.P2.N, P.P2.ninv);
+    uint32_t w[KP2], c2[KP2], f[KP2];
+    relayout<KP, KP2>(w, x, lds);
+    ld<KP2>(c2, P.P2.R2);
+    mont_mul<KP2>(w, w, c2, M2, lds);
+    ld<KP2>(c2, P.P2.R1);
+    mont_pow<KP2>(w, P.e_lift.e, P.e_lift.nwin, tab, c2, M2, lds);
+    // f = 1 + m n mod P^2 = 1 + P (m Q mod P)
+    relayout<KP, KP2>(f, u, lds);
+    ld<KP2>(c2, P.PR_P2);
+    mont_mul<KP2>(f, f, c2, M2, lds);
+    add_one<KP2>(f);
+    // c_P = omega f mod P^2 (the Montgomery factor of omega cancels)
+    mont_mul<KP2>(w, w, f, M2, lds);
+    if (valid) st<KP2>(cpq + (i * 2 + which) * SP2, w);
+  }
+}
+
+// Phase B: c = c_q + q^2 ((c_p - c_q) (q^2)^-1 mod p^2), the CRT to mod n^2.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_enc_crt_b(DKey key, const uint32_t *__restrict__ cpq,
+                                                            uint64_t count, uint32_t *__restrict__ ct) {
+  constexpr int KP2 = 2 * KP, KN2 = 4 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SN2;
+  uint64_t i = (uint64_t)blockIdx.x * 16 + gi;
+  const bool valid = i < count;
+  if (!valid) i = count - 1;
+  const DPrime &Pp = key.pr[0];
+  const Mod<KP2> M2 = load_mod<KP2>(Pp.P2.N, Pp.P2.ninv);
+  uint32_t cp[KP2], cq[KP2], c[KP2], a[KP2], b[KP2];
+  ld<KP2>(cp, cpq + (i * 2 + 0) * SP2);
+  ld<KP2>(cq, cpq + (i * 2 + 1) * SP2);
+  ld<KP2>(c, key.Cq);
+  mont_mul<KP2>(a, cp, c, M2, lds);
+  mont_mul<KP2>(b, cq, c, M2, lds);
+  sub_mod<KP2>(a, a, b, M2);
+  const Mod<KN2> Mn2 = load_mod<KN2>(key.n2.N, key.n2.ninv);
+  uint32_t u[KN2], cq4[KN2], k4[KN2];
+  relayout<KP2, KN2>(u, a, lds);
+  relayout<KP2, KN2>(cq4, cq, lds);
+  ld<KN2>(k4, key.q2R_n2);
+  mont_mul<KN2>(u, u, k4, Mn2, lds);
+  add_plain<KN2>(u, u, cq4);
+  if (valid) st<KN2>(ct + i * SN2, u);
+}
+
+// ------------------------------------------------------ public-key encryption
+// c = (1 + (m mod n) n) r^n mod n^2 by one exponentiation mod n^2.  The seeded
+// X (L + 2 limbs) is used as is: r^n mod n^2 depends only on r mod n.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
+    DKey key, const int64_t *__restrict__ m, uint64_t count, const uint32_t *__restrict__ r,
+    uint64_t seed, uint64_t roff, uint32_t *__restrict__ ct, uint32_t *__restrict__ tabs) {
+  constexpr int KN2 = 4 * KP, SN2 = 64 * KP, L = 32 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  const uint32_t g = group_in_wave();
+  uint32_t *lds = lds_all + (wave_in_block() * 4 + g) * SN2;
+  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
+  const uint64_t nw = (uint64_t)gridDim.x * 4;
+  uint32_t *tab = tabs + (gw * 4 + g) * (uint64_t)(kTable * SN2);
+  const uint64_t nquads = (count + 3) / 4;
+  const uint64_t W = (uint64_t)L / 2 + 1;
+  const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
+  for (uint64_t qd = gw; qd < nquads; qd += nw) {
+    uint64_t i = qd * 4 + g;
+    const bool valid = i < count;
+    if (!valid) i = count - 1;
+    uint32_t x[KN2], c[KN2], f[KN2];
+    if (r)
+      ld_part<KN2>(x, r + i * L, L);
+    else
+      seeded_limbs<KN2>(x, seed, (roff + i) * W, 0, L + 2);
+    ld<KN2>(c, key.n2.R2);
+    mont_mul<KN2>(x, x, c, M, lds);
+    ld<KN2>(c, key.n2.R1);
+    mont_pow<KN2>(x, key.e_n.e, key.e_n.nwin, tab, c, M, lds);
+    // f = 1 + (m mod n) n, exact (< n^2)
+    ld_part<KN2>(c, key.n.N, L);
+    signed_mod<KN2>(f, m[i], c);
+    ld<KN2>(c, key.nR_n2);
+    mont_mul<KN2>(f, f, c, M, lds);
+    add_one<KN2>(f);
+    mont_mul<KN2>(x, x, f, M, lds);
+    if (valid) st<KN2>(ct + i * SN2, x);
+  }
+}
+
+// ------------------------------------------------------ Montgomery conversion
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_mont_convert(DKey key, const uint32_t *in, uint64_t count,
+                                                               uint32_t *out, int to_mont) {
+  constexpr int KN2 = 4 * KP, SN2 = 64 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SN2;
+  uint64_t i = (uint64_t)blockIdx.x * 16 + gi;
+  const bool valid = i < count;
+  if (!valid) i = count - 1;
+  const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
+  uint32_t x[KN2], c[KN2];
+  ld<KN2>(x, in + i * SN2);
+  if (to_mont)
+    ld<KN2>(c, key.n2.R2);
+  else
+    set_small(c, 1u);
+  mont_mul<KN2>(x, x, c, M, lds);
+  if (valid) st<KN2>(out + i * SN2, x);
+}
+
+// -------------------------------------------------------------- decryption
+// Phase A: for (ciphertext i, prime P):
+//   x = c^(P-1) mod P^2,  m_P = ((x - 1) / P) h_P mod P.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_dec_a(DKey key, const uint32_t *__restrict__ ct,
+                                                        uint64_t count, uint32_t *__restrict__ mpq,
+                                                        uint32_t *__restrict__ tabs) {
+  constexpr int KP2 = 2 * KP, SP = 16 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SP2];
+  const uint32_t g = group_in_wave();
+  uint32_t *lds = lds_all + (wave_in_block() * 4 + g) * SP2;
+  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
+  const uint64_t nw = (uint64_t)gridDim.x * 4;
+  uint32_t *tab = tabs + (gw * 4 + g) * (uint64_t)(kTable * SP2);
+  const uint64_t nquads = 2 * ((count + 3) / 4);
+  for (uint64_t qd = gw; qd < nquads; qd += nw) {
+    const int which = (int)(qd & 1);
+    const DPrime &P = key.pr[which];
+    uint64_t i = (qd >> 1) * 4 + g;
+    const bool valid = i < count;
+    if (!valid) i = count - 1;
+    const Mod<KP2> M2 = load_mod<KP2>(P.P2.N, P.P2.ninv);
+    uint32_t x[KP2], y[KP2], c[KP2];
+    // c mod P^2 in Montgomery form: c = c0 + c1 R'
+    ld<KP2>(x, ct + i * SN2);
+    ld<KP2>(y, ct + i * SN2 + SP2);
+    ld<KP2>(c, P.P2.R2);
+    mont_mul<KP2>(x, x, c, M2, lds);
+    ld<KP2>(c, P.P2.R3);
+    mont_mul<KP2>(y, y, c, M2, lds);
+    add_mod<KP2>(x, x, y, M2);
+    ld<KP2>(c, P.P2.R1);
+    mont_pow<KP2>(x, P.e_dec.e, P.e_dec.nwin, tab, c, M2, lds);
+    set_small(c, 1u);
+    mont_mul<KP2>(x, x, c, M2, lds);  // canonical, = 1 mod P
+    set_small(c, 1u);
+    sub_plain<KP2>(x, x, c);          // x - 1 = k P
+    // k = (x - 1) P^-1 mod 2^(32 S_P) (exact division)
+    uint32_t lo[KP], k[KP], pinv[KP];
+    relayout<KP2, KP>(lo, x, lds);
+    ld<KP>(pinv, P.Pinv);
+    st<KP>(lds, lo);
+    __builtin_amdgcn_wave_barrier();
+    mul_lo_lds<KP>(k, lds, pinv);
+    __builtin_amdgcn_wave_barrier();
+    const Mod<KP> Mp = load_mod<KP>(P.P.N, P.P.ninv);
+    ld<KP>(pinv, P.hR_P);
+    mont_mul<KP>(k, k, pinv, Mp, lds);  // m_P = k h_P mod P
+    if (valid) st<KP>(mpq + (i * 2 + which) * SP, k);
+  }
+}
+
+// Phase B: m = m_q + q ((m_p - m_q) q^-1 mod p), then the signed decode.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_dec_b(DKey key, const uint32_t *__restrict__ mpq,
+                                                        uint64_t count, int64_t *__restrict__ mout,
+                                                        uint32_t *__restrict__ raw,
+                                                        uint32_t *__restrict__ n_overflow) {
+  constexpr int KN = 2 * KP, SP = 16 * KP, SN = 32 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SN];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SN;
+  uint64_t i = (uint64_t)blockIdx.x * 16 + gi;
+  const bool valid = i < count;
+  if (!valid) i = count - 1;
+  const DPrime &Pp = key.pr[0];
+  const Mod<KP> Mp = load_mod<KP>(Pp.P.N, Pp.P.ninv);
+  uint32_t mp[KP], mq[KP], c[KP];
+  ld<KP>(mp, mpq + (i * 2 + 0) * SP);
+  ld<KP>(mq, mpq + (i * 2 + 1) * SP);
+  ld<KP>(c, Pp.P.R2);
+  mont_mul<KP>(mp, mp, c, Mp, lds);
+  uint32_t mqr[KP];
+  mont_mul<KP>(mqr, mq, c, Mp, lds);
+  sub_mod<KP>(mp, mp, mqr, Mp);
+  ld<KP>(c, key.qinv_p);
+  mont_mul<KP>(mp, mp, c, Mp, lds);  // u = (m_p - m_q) q^-1 mod p
+  const Mod<KN> Mn = load_mod<KN>(key.n.N, key.n.ninv);
+  uint32_t u[KN], v[KN], cn[KN];
+  relayout<KP, KN>(u, mp, lds);
+  relayout<KP, KN>(v, mq, lds);
+  ld<KN>(cn, key.qR_n);
+  mont_mul<KN>(u, u, cn, Mn, lds);  // q u (exact, < n)
+  add_plain<KN>(u, u, v);           // m in [0, n)
+  if (raw && valid) st<KN>(raw + i * SN, u);
+  // signed decode: m >= (n + 1) / 2 means m - n
+  ld<KN>(cn, key.half);
+  const bool below_half = bcast_last(sub_plain<KN>(v, u, cn) ? 1u : 0u) != 0u;
+  uint32_t mag[KN];
+  sub_plain<KN>(mag, Mn.n, u);
+  select(mag, below_half, u, mag);
+  bool high = false;
+#pragma unroll
+  for (int j = 0; j < KN; ++j) high = high || ((glane() * KN + j) >= 2 && mag[j] != 0u);
+  high = row_any(high);
+  const uint64_t lo64 = (uint64_t)bcast_first(mag[0]) | ((uint64_t)bcast_first(mag[1]) << 32);
+  int64_t val;
+  bool ovf;
+  if (below_half) {
+    ovf = high || (lo64 >> 63);
+    val = ovf ? INT64_MAX : (int64_t)lo64;
+  } else {
+    ovf = high || lo64 > (1ull << 63);
+    val = ovf ? INT64_MIN : (int64_t)((uint64_t)0 - lo64);
+  }
+  if (valid && glane() == 0) {
+    mout[i] = val;
+    if (ovf && n_overflow) atomicAdd(n_overflow, 1u);
+  }
+}
+
+// ------------------------------------------------------------ histograms
+__global__ void k_fill(uint32_t *p, uint64_t n, uint32_t v) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) p[i] = v;
+}
+
+constexpr int kJobsPerSetup = 24;
+struct JobPack {
+  DJob j[kJobsPerSetup];
+};
+__global__ void k_job_setup(JobPack pack, uint32_t n, DJob *dst) {
+  if (threadIdx.x < n) dst[threadIdx.x] = pack.j[threadIdx.x];
+}
+
+__device__ __forceinline__ uint32_t find_job_by_blk(const DJob *jobs, uint32_t n_jobs, uint64_t blk) {
+  uint32_t j = 0;
+  while (j + 1 < n_jobs && jobs[j + 1].blk_off <= blk) ++j;
+  return j;
+}
+__device__ __forceinline__ uint32_t find_job_by_f(const DJob *jobs, uint32_t n_jobs, uint64_t f) {
+  uint32_t j = 0;
+  while (j + 1 < n_jobs && jobs[j + 1].f_off <= f) ++j;
+  return j;
+}
+__device__ __forceinline__ uint32_t find_job_by_fb(const DJob *jobs, uint32_t n_jobs, uint64_t e) {
+  uint32_t j = 0;
+  while (j + 1 < n_jobs && jobs[j + 1].fb_off <= e) ++j;
+  return j;
+}
+
+// Bin counts of one (job, feature, sample block) into counts[fb].
+__global__ __launch_bounds__(256) void k_hist_count(HistWs ws) {
+  __shared__ uint32_t h[256];
+  const uint64_t blk = blockIdx.x;
+  const uint32_t jn = find_job_by_blk(ws.jobs, ws.n_jobs, blk);
+  const DJob J = ws.jobs[jn];
+  const uint64_t local = blk - J.blk_off;
+  const uint32_t f = (uint32_t)(local / J.nblk);
+  const uint64_t s0 = (local % J.nblk) * kSampleBlock;
+  const uint64_t s1 = min(J.n, s0 + kSampleBlock);
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint8_t *bf = J.bins + (uint64_t)f * J.ld;
+  for (uint64_t s = s0 + threadIdx.x; s < s1; s += 256) atomicAdd(&h[bf[J.idx[s]]], 1u);
+  __syncthreads();
+  if (threadIdx.x < J.B && h[threadIdx.x])
+    atomicAdd(&ws.counts[J.fb_off + (uint64_t)f * J.B + threadIdx.x], h[threadIdx.x]);
+}
+
+// Per (job, feature): exclusive scan of the bin counts, chunk counts per bin
+// and their local prefix; ftot = chunks of this feature.
+__global__ __launch_bounds__(256) void k_hist_scan(HistWs ws) {
+  __shared__ uint32_t sc[256], sh[256];
+  const uint64_t jf = blockIdx.x;
+  const uint32_t jn = find_job_by_f(ws.jobs, ws.n_jobs, jf);
+  const DJob J = ws.jobs[jn];
+  const uint32_t f = (uint32_t)(jf - J.f_off);
+  const uint64_t e = J.fb_off + (uint64_t)f * J.B + threadIdx.x;
+  const uint32_t t = threadIdx.x;
+  const uint32_t cnt = t < J.B ? ws.counts[e] : 0u;
+  const uint32_t nch = (cnt + ws.chunk - 1) / ws.chunk;
+  sc[t] = cnt;
+  sh[t] = nch;
+  __syncthreads();
+  for (uint32_t d = 1; d < 256; d <<= 1) {  // inclusive Hillis-Steele scans
+    const uint32_t a = t >= d ? sc[t - d] : 0u, b = t >= d ? sh[t - d] : 0u;
+    __syncthreads();
+    sc[t] += a;
+    sh[t] += b;
+    __syncthreads();
+  }
+  if (t < J.B) {
+    ws.offs[e] = sc[t] - cnt;
+    ws.cursor[e] = sc[t] - cnt;
+    ws.fch[e] = nch;
+    ws.fitem[e] = sh[t] - nch;  // local; made global by k_hist_items
+  }
+  if (t == 255) ws.ftot[jf] = sh[255];
+}
+
+// Exclusive scan of ftot over all (job, feature) pairs; total item count.
+__global__ __launch_bounds__(1024) void k_hist_base(HistWs ws) {
+  __shared__ uint32_t s[1024];
+  __shared__ uint32_t carry;
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint64_t b0 = 0; b0 < ws.total_f; b0 += 1024) {
+    const uint64_t i = b0 + threadIdx.x;
+    const uint32_t v = i < ws.total_f ? ws.ftot[i] : 0u;
+    s[threadIdx.x] = v;
+    __syncthreads();
+    for (uint32_t d = 1; d < 1024; d <<= 1) {
+      const uint32_t a = threadIdx.x >= d ? s[threadIdx.x - d] : 0u;
+      __syncthreads();
+      s[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (i < ws.total_f) ws.fbase[i] = carry + s[threadIdx.x] - v;
+    __syncthreads();
+    if (threadIdx.x == 1023) carry += s[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *ws.n_items = carry;
+}
+
+// Items of one (job, feature): every bin's sample run split into chunks.
+__global__ __launch_bounds__(256) void k_hist_items(HistWs ws) {
+  const uint64_t jf = blockIdx.x;
+  const uint32_t jn = find_job_by_f(ws.jobs, ws.n_jobs, jf);
+  const DJob J = ws.jobs[jn];
+  const uint32_t f = (uint32_t)(jf - J.f_off);
+  const uint32_t b = threadIdx.x;
+  if (b >= J.B) return;
+  const uint64_t e = J.fb_off + (uint64_t)f * J.B + b;
+  const uint32_t first = ws.fbase[jf] + ws.fitem[e];
+  ws.fitem[e] = first;
+  const uint32_t nch = ws.fch[e], cnt = ws.counts[e];
+  const uint64_t start = J.perm_off + (uint64_t)f * J.n + ws.offs[e];
+  for (uint32_t c = 0; c < nch; ++c) {
+    HistItem it;
+    it.start = start + (uint64_t)c * ws.chunk;
+    it.len = min(ws.chunk, cnt - c * ws.chunk);
+    it.pad = 0;
+    ws.items[first + c] = it;
+  }
+}
+
+// Scatter of sample rows into per-(feature, bin) runs of perm.
+__global__ __launch_bounds__(256) void k_hist_scatter(HistWs ws) {
+  __shared__ uint32_t h[256], base[256];
+  const uint64_t blk = blockIdx.x;
+  const uint32_t jn = find_job_by_blk(ws.jobs, ws.n_jobs, blk);
+  const DJob J = ws.jobs[jn];
+  const uint64_t local = blk - J.blk_off;
+  const uint32_t f = (uint32_t)(local / J.nblk);
+  const uint64_t s0 = (local % J.nblk) * kSampleBlock;
+  const uint64_t s1 = min(J.n, s0 + kSampleBlock);
+  h[threadIdx.x] = 0;
+  __syncthreads();
+  const uint8_t *bf = J.bins + (uint64_t)f * J.ld;
+  constexpr int kPer = kSampleBlock / 256;
+  uint32_t rows[kPer], bn[kPer], rk[kPer];
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint64_t s = s0 + threadIdx.x + (uint64_t)k * 256;
+    if (s < s1) {
+      rows[k] = J.idx[s];
+      bn[k] = bf[rows[k]];
+      rk[k] = atomicAdd(&h[bn[k]], 1u);
+    }
+  }
+  __syncthreads();
+  const uint64_t e0 = J.fb_off + (uint64_t)f * J.B;
+  if (threadIdx.x < J.B && h[threadIdx.x]) base[threadIdx.x] = atomicAdd(&ws.cursor[e0 + threadIdx.x], h[threadIdx.x]);
+  __syncthreads();
+  uint32_t *pf = ws.perm + J.perm_off + (uint64_t)f * J.n;
+#pragma unroll
+  for (int k = 0; k < kPer; ++k) {
+    const uint64_t s = s0 + threadIdx.x + (uint64_t)k * 256;
+    if (s < s1) pf[base[bn[k]] + rk[k]] = rows[k];
+  }
+}
+
+// Product of the ciphertexts of one item (chunk), one item per wave: groups
+// 0/1 take slot g/h of the first half of the chunk, groups 2/3 of the second
+// half; the halves are combined at the end.  Output in Montgomery form.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_hist_chunk(DKey key, const uint32_t *__restrict__ ctm,
+                                                             HistWs ws) {
+  constexpr int K = 4 * KP, S = 64 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * S];
+  const uint32_t g = group_in_wave();
+  const uint32_t wrow = wave_in_block() * 4;
+  uint32_t *lds = lds_all + (wrow + g) * S;
+  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
+  const uint64_t nw = (uint64_t)gridDim.x * 4;
+  const uint32_t slot = g & 1u, half = g >> 1;
+  const Mod<K> M = load_mod<K>(key.n2.N, key.n2.ninv);
+  uint32_t one[K];
+  ld<K>(one, key.n2.R1);
+  const uint64_t n_items = *ws.n_items;
+  for (uint64_t it = gw; it < n_items; it += nw) {
+    const HistItem item = ws.items[it];
+    const uint32_t len_lo = (item.len + 1) >> 1, len_hi = item.len >> 1;
+    const uint32_t my_len = half ? len_hi : len_lo;
+    const uint32_t *pp = ws.perm + item.start + (half ? len_lo : 0u);
+    uint32_t acc[K], b[K];
+    if (my_len) {
+      ld<K>(acc, ctm + ((uint64_t)pp[0] * 2 + slot) * S);
+    } else {
+      copy(acc, one);
+    }
+    if (len_lo > 1) ld<K>(b, ctm + ((uint64_t)pp[min(1u, my_len ? my_len - 1 : 0u)] * 2 + slot) * S);
+#pragma unroll 1
+    for (uint32_t k = 1; k < len_lo; ++k) {
+      uint32_t nb[K];
+      const uint32_t kn = min(k + 1, my_len ? my_len - 1 : 0u);
+      if (k + 1 < len_lo) ld<K>(nb, ctm + ((uint64_t)pp[kn] * 2 + slot) * S);
+      uint32_t t[K];
+      mont_mul<K>(t, acc, b, M, lds);
+      select(acc, k < my_len, t, acc);
+      if (k + 1 < len_lo) copy(b, nb);
+    }
+    // combine the two halves
+    st<K>(lds, acc);
+    __builtin_amdgcn_wave_barrier();
+    uint32_t other[K];
+    ld<K>(other, lds_all + (wrow + (g ^ 2u)) * S);
+    __builtin_amdgcn_wave_barrier();
+    mont_mul<K>(acc, acc, other, M, lds);
+    if (half == 0) st<K>(ws.partials + (it * 2 + slot) * S, acc);
+  }
+}
+
+// Final product over the chunks of one (job, feature, bin), conversion out of
+// Montgomery form, and the store into the job's histogram.  One entry per
+// wave, chunks split between the two group pairs like k_hist_chunk.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_hist_final(DKey key, HistWs ws) {
+  constexpr int K = 4 * KP, S = 64 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * S];
+  const uint32_t g = group_in_wave();
+  const uint32_t wrow = wave_in_block() * 4;
+  uint32_t *lds = lds_all + (wrow + g) * S;
+  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
+  const uint64_t nw = (uint64_t)gridDim.x * 4;
+  const uint32_t slot = g & 1u, half = g >> 1;
+  const Mod<K> M = load_mod<K>(key.n2.N, key.n2.ninv);
+  uint32_t one[K];
+  ld<K>(one, key.n2.R1);
+  for (uint64_t e = gw; e < ws.total_fb; e += nw) {
+    const uint32_t jn = find_job_by_fb(ws.jobs, ws.n_jobs, e);
+    const DJob J = ws.jobs[jn];
+    const uint64_t fb = e - J.fb_off;
+    const uint32_t nch = ws.fch[e], first = ws.fitem[e];
+    const uint32_t n_lo = (nch + 1) >> 1, n_hi = nch >> 1;
+    const uint32_t my_n = half ? n_hi : n_lo;
+    const uint64_t p0 = (uint64_t)first + (half ? n_lo : 0u);
+    uint32_t acc[K], b[K];
+    if (my_n)
+      ld<K>(acc, ws.partials + (p0 * 2 + slot) * S);
+    else
+      copy(acc, one);
+#pragma unroll 1
+    for (uint32_t k = 1; k < n_lo; ++k) {
+      const uint32_t kk = min(k, my_n ? my_n - 1 : 0u);
+      ld<K>(b, ws.partials + ((p0 + kk) * 2 + slot) * S);
+      uint32_t t[K];
+      mont_mul<K>(t, acc, b, M, lds);
+      select(acc, k < my_n, t, acc);
+    }
+    st<K>(lds, acc);
+    __builtin_amdgcn_wave_barrier();
+    uint32_t other[K];
+    ld<K>(other, lds_all + (wrow + (g ^ 2u)) * S);
+    __builtin_amdgcn_wave_barrier();
+    mont_mul<K>(acc, acc, other, M, lds);
+    set_small(b, 1u);
+    mont_mul<K>(acc, acc, b, M, lds);  // out of Montgomery form
+    if (half == 0) st<K>(J.hist + (fb * 2 + slot) * S, acc);
+  }
+}
+
+// ------------------------------------------------ integer multiply probe
+// Independent 32x32->64 multiply-adds, 8 chains per lane, for the measured
+// peak of the VALU integer multiplier (the roofline denominator).
+__global__ __launch_bounds__(256) void k_probe_mul(uint64_t iters, uint32_t *sink) {
+  uint64_t a0 = threadIdx.x, a1 = a0 + 1, a2 = a0 + 2, a3 = a0 + 3, a4 = a0 + 4, a5 = a0 + 5,
+           a6 = a0 + 6, a7 = a0 + 7;
+  uint32_t x = 0x9E3779B9u ^ blockIdx.x, y = 0x85EBCA6Bu + threadIdx.x;
+  for (uint64_t i = 0; i < iters; ++i) {
+    a0 = (uint64_t)x * y + a0;
+    a1 = (uint64_t)x * (y + 1) + a1;
+    a2 = (uint64_t)x * (y + 2) + a2;
+    a3 = (uint64_t)x * (y + 3) + a3;
+    a4 = (uint64_t)x * (y + 4) + a4;
+    a5 = (uint64_t)x * (y + 5) + a5;
+    a6 = (uint64_t)x * (y + 6) + a6;
+    a7 = (uint64_t)x * (y + 7) + a7;
+    x = (uint32_t)a0;
+  }
+  const uint64_t s = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
+  if (s == 0x123456789ull) sink[0] = (uint32_t)s;  // keeps the chains alive
+}
+
+// ================================================================ launchers
+static inline uint32_t blocks_for(uint64_t n, uint64_t per) { return (uint32_t)((n + per - 1) / per); }
+
+hipError_t launch_encode(const double *x, uint64_t count, uint32_t frac_bits, int64_t *m,
+                         uint32_t *n_bad, hipStream_t s) {
+  if (!count) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(blocks_for(count, 256), 65536);
+  hipLaunchKernelGGL(k_encode, dim3(grid), dim3(256), 0, s, x, count, frac_bits, m, n_bad);
+  return hipGetLastError();
+}
+
+template <int KP>
+static hipError_t enc_crt(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r,
+                          uint64_t seed, uint64_t roff, uint32_t *cpq, uint32_t *ct, uint32_t *tab,
+                          uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_enc_crt_a<KP>, dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed,
+                     roff, cpq, tab);
+  hipLaunchKernelGGL(k_enc_crt_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k,
+                     (const uint32_t *)cpq, count, ct);
+  return hipGetLastError();
+}
+hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count,
+                          const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *cpq,
+                          uint32_t *ct, uint32_t *tab, uint32_t grid, hipStream_t s) {
+  if (!count) return hipSuccess;
+  return KP == 1 ? enc_crt<1>(k, m, count, r, seed, roff, cpq, ct, tab, grid, s)
+                 : enc_crt<2>(k, m, count, r, seed, roff, cpq, ct, tab, grid, s);
+}
+
+hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
+                          const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *ct,
+                          uint32_t *tab, uint32_t grid, hipStream_t s) {
+  if (!count) return hipSuccess;
+  if (KP == 1)
+    hipLaunchKernelGGL(k_enc_pub<1>, dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff, ct, tab);
+  else
+    hipLaunchKernelGGL(k_enc_pub<2>, dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff, ct, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64_t count,
+                               uint32_t *out, bool to_mont, hipStream_t s) {
+  if (!count) return hipSuccess;
+  const dim3 grid(blocks_for(count, 16));
+  if (KP == 1)
+    hipLaunchKernelGGL(k_mont_convert<1>, grid, dim3(kBlockThreads), 0, s, k, in, count, out, (int)to_mont);
+  else
+    hipLaunchKernelGGL(k_mont_convert<2>, grid, dim3(kBlockThreads), 0, s, k, in, count, out, (int)to_mont);
+  return hipGetLastError();
+}
+
+template <int KP>
+static hipError_t dec(const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *mpq, int64_t *m,
+                      uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL(k_dec_a<KP>, dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
+  hipLaunchKernelGGL(k_dec_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k,
+                     (const uint32_t *)mpq, count, m, raw, n_overflow);
+  return hipGetLastError();
+}
+hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *mpq,
+                      int64_t *m, uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, uint32_t grid,
+                      hipStream_t s) {
+  if (!count) return hipSuccess;
+  return KP == 1 ? dec<1>(k, ct, count, mpq, m, raw, n_overflow, tab, grid, s)
+                 : dec<2>(k, ct, count, mpq, m, raw, n_overflow, tab, grid, s);
+}
+
+hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
+  if (!n) return hipSuccess;
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(blocks_for(n, 256), 4096);
+  hipLaunchKernelGGL(k_fill, dim3(grid), dim3(256), 0, s, p, n, v);
+  return hipGetLastError();
+}
+
+template <int KP>
+static hipError_t hist(const DKey &k, const uint32_t *ctm, const DJob *host_jobs, const HistWs &ws,
+                       uint32_t chunk_grid, hipStream_t s) {
+  hipError_t e = launch_fill(ws.counts, ws.total_fb, 0u, s);
+  if (e != hipSuccess) return e;
+  for (uint32_t j0 = 0; j0 < ws.n_jobs; j0 += kJobsPerSetup) {
+    JobPack pack;
+    const uint32_t n = std::min<uint32_t>(kJobsPerSetup, ws.n_jobs - j0);
+    for (uint32_t j = 0; j < n; ++j) pack.j[j] = host_jobs[j0 + j];
+    hipLaunchKernelGGL(k_job_setup, dim3(1), dim3(64), 0, s, pack, n, ws.jobs + j0);
+  }
+  if (ws.total_blocks)
+    hipLaunchKernelGGL(k_hist_count, dim3((uint32_t)ws.total_blocks), dim3(256), 0, s, ws);
+  hipLaunchKernelGGL(k_hist_scan, dim3((uint32_t)ws.total_f), dim3(256), 0, s, ws);
+  hipLaunchKernelGGL(k_hist_base, dim3(1), dim3(1024), 0, s, ws);
+  hipLaunchKernelGGL(k_hist_items, dim3((uint32_t)ws.total_f), dim3(256), 0, s, ws);
+  if (ws.total_blocks)
+    hipLaunchKernelGGL(k_hist_scatter, dim3((uint32_t)ws.total_blocks), dim3(256), 0, s, ws);
+  hipLaunchKernelGGL(k_hist_chunk<KP>, dim3(chunk_grid), dim3(kBlockThreads), 0, s, k, ctm, ws);
+  const uint32_t fgrid = (uint32_t)std::min<uint64_t>(blocks_for(ws.total_fb, 4), 1u << 20);
+  hipLaunchKernelGGL(k_hist_final<KP>, dim3(fgrid), dim3(kBlockThreads), 0, s, k, ws);
+  return hipGetLastError();
+}
+hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *host_jobs,
+                       const HistWs &ws, uint32_t chunk_grid, hipStream_t s) {
+  return KP == 1 ? hist<1>(k, ctm, host_jobs, ws, chunk_grid, s) : hist<2>(k, ctm, host_jobs, ws, chunk_grid, s);
+}
+
+hipError_t launch_probe_mul(uint64_t iters, uint32_t grid, uint32_t *sink, hipStream_t s) {
+  hipLaunchKernelGGL(k_probe_mul, dim3(grid), dim3(256), 0, s, iters, sink);
+  return hipGetLastError();
+}
+
+static uint32_t occupancy_blocks(const void *fn) {
+  int dev = 0, cus = 0, nb = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 1;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlockThreads, 0) != hipSuccess || nb < 1) nb = 1;
+  return (uint32_t)(nb * std::max(cus, 1));
+}
+
+uint32_t resident_blocks(int KP, int kind) {
+  static uint32_t cache[2][4] = {};
+  uint32_t &c = cache[KP - 1][kind];
+  if (c) return c;
+  const void *fn = nullptr;
+  switch (kind) {
+    case 0: fn = KP == 1 ? (const void *)k_enc_crt_a<1> : (const void *)k_enc_crt_a<2>; break;
+    case 1: fn = KP == 1 ? (const void *)k_enc_pub<1> : (const void *)k_enc_pub<2>; break;
+    case 2: fn = KP == 1 ? (const void *)k_dec_a<1> : (const void *)k_dec_a<2>; break;
+    default: fn = KP == 1 ? (const void *)k_hist_chunk<1> : (const void *)k_hist_chunk<2>; break;
+  }
+  c = occupancy_blocks(fn);
+  return c;
+}
+
+uint64_t table_bytes_per_block(int KP, int kind) {
+  const uint64_t S = kind == 1 ? 64 * KP : 32 * KP;  // public path tables are mod n^2
+  return 16ull * kTable * S * sizeof(uint32_t);
+}
+
+}  // namespace he

@@ -1,0 +1,271 @@
+"""Python binding of the gfx950 Paillier histogram library (include/he.h).
+
+Argument marshalling only: every step runs in the HIP kernels of
+``libhe_mi355x.so``.  Device buffers are torch tensors on a ROCm device;
+uint32 limb arrays travel as int32 tensors (same bits).  Calls enqueue on the
+current torch stream unless a stream is passed.  There is no CPU fallback: if
+the shared library is missing, importing this module raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libhe_mi355x.so")
+
+HE_OK = 0
+HE_ERR_ARG, HE_ERR_KEY, HE_ERR_NOPRIV, HE_ERR_RANGE, HE_ERR_OOM, HE_ERR_DEVICE = -1, -2, -3, -4, -5, -6
+HE_FORM_CANONICAL, HE_FORM_MONT = 0, 1
+
+EXPORTED = (
+    "he_keygen", "he_key_import", "he_key_export", "he_key_bits", "he_key_has_private",
+    "he_key_free", "he_encode", "he_encrypt", "he_encrypt_public", "he_to_mont", "he_from_mont",
+    "he_hist_aggregate", "he_hist_aggregate_ex", "he_decrypt", "he_probe_int_mul", "he_last_error",
+)
+
+
+class HEError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"he error {code}: {msg}")
+        self.code = code
+
+
+def _load() -> ctypes.CDLL:
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(
+            f"{_LIB_PATH} is missing: build it with `python -m paper_2504_03909_amd.build` "
+            "(there is no CPU fallback)")
+    return ctypes.CDLL(_LIB_PATH)
+
+
+_lib = _load()
+_vp, _u32, _u64, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int
+
+
+class HistJob(ctypes.Structure):
+    _fields_ = [("sample_idx", _vp), ("n_samples", _u64), ("bins", _vp), ("bins_ld", _u64),
+                ("n_features", _u32), ("n_bins", _u32), ("hist", _vp)]
+
+
+def _sig(name, res, args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = args
+    return f
+
+
+_keygen = _sig("he_keygen", _i32, [_u32, _u64, ctypes.POINTER(_vp)])
+_key_import = _sig("he_key_import", _i32, [_u32, _vp, _vp, ctypes.POINTER(_vp)])
+_key_export = _sig("he_key_export", _i32, [_vp, _vp, _vp, _vp])
+_key_bits = _sig("he_key_bits", _u32, [_vp])
+_key_priv = _sig("he_key_has_private", _i32, [_vp])
+_key_free = _sig("he_key_free", None, [_vp])
+_encode = _sig("he_encode", _i32, [_vp, _u64, _u32, _vp, _vp, _vp])
+_encrypt = _sig("he_encrypt", _i32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp])
+_encrypt_pub = _sig("he_encrypt_public", _i32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp])
+_to_mont = _sig("he_to_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
+_from_mont = _sig("he_from_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
+_hist = _sig("he_hist_aggregate_ex", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32, _u32, _vp])
+_decrypt = _sig("he_decrypt", _i32, [_vp, _vp, _u64, _vp, _vp, _vp, _vp])
+_probe = _sig("he_probe_int_mul", _i32, [_u64, _u32, ctypes.POINTER(_u64), _vp])
+_last_error = _sig("he_last_error", ctypes.c_char_p, [])
+
+
+def _check(rc: int) -> None:
+    if rc != HE_OK:
+        raise HEError(rc, (_last_error() or b"").decode())
+
+
+def _stream(stream) -> int:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    return getattr(stream, "cuda_stream", stream)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+# ----------------------------------------------------------- limb conversion
+def ints_to_limbs(values: Sequence[int], n_limbs: int) -> np.ndarray:
+    """Python ints -> int32 array [len, n_limbs] of little-endian 32-bit limbs."""
+    out = np.zeros((len(values), n_limbs), dtype=np.uint32)
+    nbytes = 4 * n_limbs
+    for i, v in enumerate(values):
+        out[i] = np.frombuffer(int(v).to_bytes(nbytes, "little"), dtype=np.uint32)
+    return out.view(np.int32)
+
+
+def limbs_to_ints(arr) -> List[int]:
+    """int32/uint32 array [..., n_limbs] -> flat list of Python ints."""
+    a = np.ascontiguousarray(np.asarray(arr).view(np.uint32))
+    a = a.reshape(-1, a.shape[-1])
+    return [int.from_bytes(row.tobytes(), "little") for row in a]
+
+
+# -------------------------------------------------------------------- keys
+class Key:
+    """A Paillier key resident on the current device (n, n^2, p, q, p^2, q^2
+    Montgomery constants and CRT constants)."""
+
+    def __init__(self, handle: int):
+        self._h = ctypes.c_void_p(handle)
+
+    @classmethod
+    def generate(cls, n_bits: int, seed: int) -> "Key":
+        h = _vp()
+        _check(_keygen(n_bits, seed, ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def from_primes(cls, n_bits: int, p: int, q: int) -> "Key":
+        half = n_bits // 64
+        pa = np.frombuffer(int(p).to_bytes(4 * half, "little"), dtype=np.uint32).copy()
+        qa = np.frombuffer(int(q).to_bytes(4 * half, "little"), dtype=np.uint32).copy()
+        h = _vp()
+        _check(_key_import(n_bits, pa.ctypes.data, qa.ctypes.data, ctypes.byref(h)))
+        return cls(h.value)
+
+    @classmethod
+    def public(cls, n_bits: int, n: int) -> "Key":
+        na = np.frombuffer(int(n).to_bytes(n_bits // 8, "little"), dtype=np.uint32).copy()
+        h = _vp()
+        _check(_key_import(n_bits, na.ctypes.data, None, ctypes.byref(h)))
+        return cls(h.value)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def bits(self) -> int:
+        return int(_key_bits(self._h))
+
+    @property
+    def limbs(self) -> int:
+        """Limbs of n (a ciphertext has 2 * limbs)."""
+        return self.bits // 32
+
+    @property
+    def has_private(self) -> bool:
+        return bool(_key_priv(self._h))
+
+    def export(self):
+        L = self.limbs
+        n = np.zeros(L, dtype=np.uint32)
+        if self.has_private:
+            p = np.zeros(L // 2, dtype=np.uint32)
+            q = np.zeros(L // 2, dtype=np.uint32)
+            _check(_key_export(self._h, n.ctypes.data, p.ctypes.data, q.ctypes.data))
+            return (int.from_bytes(n.tobytes(), "little"), int.from_bytes(p.tobytes(), "little"),
+                    int.from_bytes(q.tobytes(), "little"))
+        _check(_key_export(self._h, n.ctypes.data, None, None))
+        return int.from_bytes(n.tobytes(), "little"), None, None
+
+    def close(self):
+        if self._h and self._h.value:
+            _key_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ------------------------------------------------------------------ calls
+def encode(x: torch.Tensor, frac_bits: int = 32, stream=None, n_bad: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """rint(x * 2^frac_bits) as int64 (device)."""
+    assert x.dtype == torch.float64
+    m = torch.empty(x.shape, dtype=torch.int64, device=x.device)
+    _check(_encode(_ptr(x), x.numel(), frac_bits, _ptr(m), _ptr(n_bad), _stream(stream)))
+    return m
+
+
+def encrypt(key: Key, m: torch.Tensor, r: Optional[torch.Tensor] = None, seed: int = 0,
+            offset: int = 0, public: bool = False, out: Optional[torch.Tensor] = None,
+            stream=None) -> torch.Tensor:
+    """Ciphertexts of the int64 plaintexts m (any shape) -> int32 [..., 2L]."""
+    assert m.dtype == torch.int64
+    m = m.contiguous()
+    count = m.numel()
+    L = key.limbs
+    if r is not None:
+        assert r.dtype == torch.int32 and r.shape[-1] == L and r.numel() == count * L
+    if out is None:
+        out = torch.empty((*m.shape, 2 * L), dtype=torch.int32, device=m.device)
+    fn = _encrypt_pub if public else _encrypt
+    _check(fn(key.handle, _ptr(m), count, _ptr(r), seed, offset, _ptr(out), _stream(stream)))
+    return out
+
+
+def to_mont(key: Key, ct: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    out = torch.empty_like(ct) if out is None else out
+    _check(_to_mont(key.handle, _ptr(ct), ct.numel() // (2 * key.limbs), _ptr(out), _stream(stream)))
+    return out
+
+
+def from_mont(key: Key, ct: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    out = torch.empty_like(ct) if out is None else out
+    _check(_from_mont(key.handle, _ptr(ct), ct.numel() // (2 * key.limbs), _ptr(out), _stream(stream)))
+    return out
+
+
+@dataclass
+class Job:
+    """One node's histogram job; tensors on the device."""
+    sample_idx: torch.Tensor   # int32 [n] (row indices, uint32 bits)
+    bins: torch.Tensor         # uint8 [F, ld]
+    n_bins: int
+    hist: Optional[torch.Tensor] = None  # int32 [F, B, 2, 2L], allocated if None
+
+    def as_c(self, key: Key) -> HistJob:
+        F, ld = self.bins.shape
+        if self.hist is None:
+            self.hist = torch.empty((F, self.n_bins, 2, 2 * key.limbs), dtype=torch.int32,
+                                    device=self.bins.device)
+        return HistJob(_ptr(self.sample_idx) if self.sample_idx.numel() else None,
+                       self.sample_idx.numel(), _ptr(self.bins), ld, F, self.n_bins, _ptr(self.hist))
+
+
+def hist_aggregate(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = HE_FORM_CANONICAL,
+                   chunk: int = 0, stream=None) -> List[torch.Tensor]:
+    """Encrypted histograms of all jobs in one batch; ct is int32 [rows, 2, 2L]."""
+    rows = ct.shape[0]
+    arr = (HistJob * len(jobs))(*[j.as_c(key) for j in jobs])
+    _check(_hist(key.handle, _ptr(ct), rows, form, arr, len(jobs), chunk, _stream(stream)))
+    return [j.hist for j in jobs]
+
+
+def decrypt(key: Key, ct: torch.Tensor, raw: bool = False, stream=None):
+    """Signed int64 plaintexts of ct (int32 [..., 2L]); optionally the raw
+    plaintexts int32 [..., L] and the overflow count tensor."""
+    count = ct.numel() // (2 * key.limbs)
+    shape = ct.shape[:-1]
+    m = torch.empty(shape, dtype=torch.int64, device=ct.device)
+    rw = torch.empty((*shape, key.limbs), dtype=torch.int32, device=ct.device) if raw else None
+    ovf = torch.zeros(1, dtype=torch.int32, device=ct.device)
+    _check(_decrypt(key.handle, _ptr(ct.contiguous()), count, _ptr(m), _ptr(rw), _ptr(ovf), _stream(stream)))
+    return m, rw, ovf
+
+
+def probe_int_mul(iters: int, blocks: int, stream=None) -> int:
+    prod = _u64()
+    _check(_probe(iters, blocks, ctypes.byref(prod), _stream(stream)))
+    return int(prod.value)
+
+
+def library_path() -> str:
+    return _LIB_PATH

@@ -1,0 +1,250 @@
+"""CPU-side checks of the C ABI library: it loads, exports every function
+include/he.h declares, and its host-side argument checks reject bad input
+without touching a GPU.  The host bignum that derives the per-key constants is
+checked through a small g++ harness against Python integer arithmetic."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "he.h")
+LIB = os.path.join(ROOT, "paper_2504_03909_amd", "libhe_mi355x.so")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(he_[a-z0-9_]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(LIB):
+        pytest.fail("libhe_mi355x.so is not built (run python -m paper_2504_03909_amd.build)")
+    return ctypes.CDLL(LIB)
+
+
+def test_header_declares_the_boundary():
+    fns = declared_functions()
+    for name in ("he_keygen", "he_key_import", "he_encrypt", "he_hist_aggregate", "he_decrypt",
+                 "he_encode", "he_last_error"):
+        assert name in fns
+
+
+def test_library_exports_every_declared_symbol(lib):
+    missing = [f for f in declared_functions() if not hasattr(lib, f)]
+    assert not missing, missing
+
+
+def test_binding_lists_every_declared_symbol():
+    from paper_2504_03909_amd import he  # loads the library, no GPU call
+    assert sorted(he.EXPORTED) == declared_functions()
+
+
+def test_host_side_argument_errors(lib):
+    # Rejections that happen before any device work.
+    lib.he_keygen.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.POINTER(ctypes.c_void_p)]
+    lib.he_last_error.restype = ctypes.c_char_p
+    h = ctypes.c_void_p()
+    assert lib.he_keygen(1000, 1, ctypes.byref(h)) == -1
+    assert b"1024 or 2048" in lib.he_last_error()
+    assert lib.he_keygen(1024, 1, None) == -1
+    lib.he_encrypt.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64,
+                                                       ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.he_encrypt(None, None, 0, None, 0, 0, None, None) == -1
+    lib.he_decrypt.argtypes = [ctypes.c_void_p] * 7
+    assert lib.he_decrypt(None, None, None, None, None, None, None) == -1
+    lib.he_probe_int_mul.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    assert lib.he_probe_int_mul(0, 0, None, None) == -1
+
+
+def test_key_import_rejects_bad_primes(lib):
+    import numpy as np
+    lib.he_key_import.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                  ctypes.POINTER(ctypes.c_void_p)]
+    h = ctypes.c_void_p()
+    even = np.zeros(16, dtype=np.uint32)
+    even[15] = 0xC0000000
+    odd = even.copy()
+    odd[0] = 1
+    assert lib.he_key_import(1024, even.ctypes.data, odd.ctypes.data, ctypes.byref(h)) == -2  # even p
+    assert lib.he_key_import(1024, odd.ctypes.data, odd.ctypes.data, ctypes.byref(h)) == -2   # p == q
+    small = np.zeros(16, dtype=np.uint32)
+    small[0] = 7
+    assert lib.he_key_import(1024, small.ctypes.data, odd.ctypes.data, ctypes.byref(h)) == -2  # n too short
+
+
+# ------------------------------------------------------------ host bignum
+HARNESS = r"""
+#include <cstdio>
+#include <string>
+#include "hostbn.hpp"
+using namespace hebn;
+static Limbs parse(const char *hex) {
+  Limbs r; std::string s(hex); size_t n = s.size();
+  for (size_t end = n; end > 0;) { size_t beg = end >= 8 ? end - 8 : 0;
+    r.push_back((uint32_t)std::stoul(s.substr(beg, end - beg), nullptr, 16)); end = beg; }
+  norm(r); return r;
+}
+static void out(const char *tag, const Limbs &x) {
+  printf("%s ", tag); if (x.empty()) { printf("0\n"); return; }
+  printf("%x", x.back()); for (size_t i = x.size() - 1; i-- > 0;) printf("%08x", x[i]); printf("\n");
+}
+int main(int argc, char **argv) {
+  Limbs a = parse(argv[1]), b = parse(argv[2]), m = parse(argv[3]);
+  Limbs q, r; divmod(a, b, &q, &r);
+  out("mul", mul(a, b)); out("q", q); out("r", r);
+  out("powmod", powmod(a, b, m)); out("inv", invmod(a, m)); out("gcd", gcd(a, b));
+  out("inv2", inv_pow2(m, 1024)); printf("ninv %x\n", neg_inv32(m[0]));
+  printf("prime %d\n", (int)is_probable_prime(m));
+  out("cand", prime_candidate(5, 1, 3, 512));
+  return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("hostbn")
+    src = d / "h.cpp"
+    src.write_text(HARNESS)
+    exe = d / "h"
+    r = subprocess.run(["g++", "-O1", "-std=c++17", "-fsanitize=address,undefined",
+                        f"-I{os.path.join(ROOT, 'paper_2504_03909_amd', 'csrc')}", str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return str(exe)
+
+
+def run_harness(exe, a, b, m):
+    r = subprocess.run([exe, format(a, "x"), format(b, "x"), format(m, "x")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return {k: int(v, 16) for k, v in (line.split() for line in r.stdout.split("\n") if line)}
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_host_bignum_against_python_ints(harness, seed):
+    import random
+    import math
+    import oracle.paillier as P
+    rng = random.Random(seed)
+    m = rng.getrandbits(1024) | (1 << 1023) | 1  # odd modulus
+    a = rng.getrandbits(rng.choice([64, 700, 2048, 4096])) % (m * m) or 3
+    while math.gcd(a, m) != 1:
+        a += 1
+    b = rng.getrandbits(rng.choice([33, 512, 1023, 2000])) | 1
+    got = run_harness(harness, a, b, m)
+    assert got["mul"] == a * b
+    assert got["q"] == a // b and got["r"] == a % b
+    assert got["powmod"] == pow(a, b, m)
+    assert got["inv"] == pow(a, -1, m)
+    assert got["gcd"] == math.gcd(a, b)
+    assert got["inv2"] == pow(m, -1, 1 << 1024)
+    assert got["ninv"] == (-pow(m, -1, 1 << 32)) % (1 << 32)
+    assert got["prime"] == int(P.is_probable_prime(m))
+    assert got["cand"] == P.prime_candidate(5, 1, 3, 512)
+
+
+def test_host_bignum_primes(harness):
+    import oracle.paillier as P
+    p, q = P.keygen(1024, 1)
+    for x in (p, q, (1 << 521) - 1):
+        assert run_harness(harness, 3, 5, x)["prime"] == 1
+    assert run_harness(harness, 3, 5, p * q)["prime"] == 0
+    assert run_harness(harness, 3, 5, 3215031751)["prime"] == 0
+
+
+KEY_HARNESS = r"""
+#include <cstdio>
+#include <string>
+#include "keysetup.hpp"
+using namespace hebn;
+static Limbs parse(const char *hex) {
+  Limbs r; std::string s(hex); size_t n = s.size();
+  for (size_t end = n; end > 0;) { size_t beg = end >= 8 ? end - 8 : 0;
+    r.push_back((uint32_t)std::stoul(s.substr(beg, end - beg), nullptr, 16)); end = beg; }
+  norm(r); return r;
+}
+static const hekey::Blob *B;
+static void out(const char *tag, size_t off, size_t limbs) {
+  printf("%s ", tag);
+  for (size_t i = limbs; i-- > 0;) printf("%08x", B->words[off + i]);
+  printf("\n");
+}
+static void mod(const char *t, const hekey::ModOff &m, size_t S) {
+  std::string s(t);
+  out((s + ".N").c_str(), m.N, S); out((s + ".R1").c_str(), m.R1, S); out((s + ".R2").c_str(), m.R2, S);
+  out((s + ".R3").c_str(), m.R3, S); out((s + ".R4").c_str(), m.R4, S); printf("%s.ninv %x\n", t, m.ninv);
+}
+int main(int argc, char **argv) {
+  uint32_t bits = std::stoul(argv[1]);
+  Limbs p = parse(argv[2]), q = parse(argv[3]);
+  hekey::KeyConsts k = hekey::derive(bits, mul(p, q), p, q, true);
+  B = &k.blob;
+  size_t L = bits / 32, SP = L / 2;
+  mod("n", k.n, L); mod("n2", k.n2, 2 * L);
+  out("e_n", k.e_n.e, L + 1); printf("e_n.nwin %x\n", k.e_n.nwin);
+  out("nR_n2", k.nR_n2, 2 * L); out("half", k.half, L);
+  for (int w = 0; w < 2; ++w) {
+    std::string s = w ? "q" : "p";
+    const hekey::PrimeOff &o = k.pr[w];
+    mod((s + ".P").c_str(), o.P, SP); mod((s + ".P2").c_str(), o.P2, 2 * SP);
+    out((s + ".e_enc").c_str(), o.e_enc.e, SP + 1); printf("%s.e_enc.nwin %x\n", s.c_str(), o.e_enc.nwin);
+    out((s + ".e_lift").c_str(), o.e_lift.e, SP + 1); out((s + ".e_dec").c_str(), o.e_dec.e, SP + 1);
+    out((s + ".QR_P").c_str(), o.QR_P, SP); out((s + ".PR_P2").c_str(), o.PR_P2, 2 * SP);
+    out((s + ".Pinv").c_str(), o.Pinv, SP); out((s + ".hR_P").c_str(), o.hR_P, SP);
+  }
+  out("Cq", k.Cq, L); out("q2R_n2", k.q2R_n2, 2 * L); out("qinv_p", k.qinv_p, SP); out("qR_n", k.qR_n, L);
+  return 0;
+}
+"""
+
+
+@pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
+def test_key_constants_against_definitions(tmp_path, bits, seed):
+    import oracle.paillier as P
+    src = tmp_path / "k.cpp"
+    src.write_text(KEY_HARNESS)
+    exe = tmp_path / "k"
+    r = subprocess.run(["g++", "-O1", "-std=c++17", "-fsanitize=address,undefined",
+                        f"-I{os.path.join(ROOT, 'paper_2504_03909_amd', 'csrc')}", str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    p, q = P.keygen(bits, seed)
+    r = subprocess.run([str(exe), str(bits), format(p, "x"), format(q, "x")], capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    c = {a: int(b, 16) for a, b in (line.split() for line in r.stdout.splitlines())}
+    n, L = p * q, bits // 32
+    n2, g = n * n, n + 1
+
+    def check_mod(tag, N, S):
+        R = 1 << (32 * S)
+        assert c[tag + ".N"] == N
+        for k in range(1, 5):
+            assert c[f"{tag}.R{k}"] == pow(R, k, N)
+        assert (c[tag + ".ninv"] * N) % (1 << 32) == (1 << 32) - 1
+
+    check_mod("n", n, L)
+    check_mod("n2", n2, 2 * L)
+    assert c["e_n"] == n and c["e_n.nwin"] == -(-n.bit_length() // 5)
+    assert c["nR_n2"] == n * (1 << (64 * L)) % n2
+    assert c["half"] == (n + 1) // 2
+    SP = L // 2
+    for tag, A, Bq in (("p", p, q), ("q", q, p)):
+        check_mod(tag + ".P", A, SP)
+        check_mod(tag + ".P2", A * A, 2 * SP)
+        assert c[tag + ".e_enc"] == Bq % (A - 1)
+        assert c[tag + ".e_enc.nwin"] == -(-(Bq % (A - 1)).bit_length() // 5)
+        assert c[tag + ".e_lift"] == A and c[tag + ".e_dec"] == A - 1
+        assert c[tag + ".QR_P"] == Bq * (1 << (32 * SP)) % A
+        assert c[tag + ".PR_P2"] == A * (1 << (64 * SP)) % (A * A)
+        assert c[tag + ".Pinv"] * A % (1 << (32 * SP)) == 1
+        h = pow((pow(g, A - 1, A * A) - 1) // A, -1, A)
+        assert c[tag + ".hR_P"] == h * (1 << (32 * SP)) % A
+    assert c["Cq"] == pow(q * q, -1, p * p) * (1 << (32 * L)) % (p * p)
+    assert c["q2R_n2"] == q * q * (1 << (64 * L)) % n2
+    assert c["qinv_p"] == pow(q, -1, p)
+    assert c["qR_n"] == q * (1 << (32 * L)) % n

@@ -1,0 +1,315 @@
+"""GPU parity of the gfx950 Paillier path against the CPU oracle.
+
+Every expected value comes from ``oracle/`` on the same seeded inputs (from
+``synth``); the HIP library is called through its C ABI binding.  Ciphertexts
+and histograms must match bit for bit, decrypted values exactly.
+"""
+import functools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle.paillier as P
+from oracle import pool
+from synth import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def he():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_2504_03909_amd import he as H
+    return H
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_key(bits, seed):
+    p, q = P.keygen(bits, seed)
+    return P.PrivateKey(p, q)
+
+
+@functools.lru_cache(maxsize=None)
+def gpu_key(bits, seed):
+    from paper_2504_03909_amd import he as H
+    sk = oracle_key(bits, seed)
+    return H.Key.from_primes(bits, sk.p, sk.q)
+
+
+def dev(a, dtype=None):
+    import torch
+    t = torch.from_numpy(np.ascontiguousarray(a))
+    if dtype is not None:
+        t = t.to(dtype)
+    return t.cuda()
+
+
+def host(t):
+    import torch
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+# ------------------------------------------------------------- keys
+@pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
+def test_keygen_matches_oracle(he, bits, seed):
+    say(f"keygen {bits} seed={seed}")
+    k = he.Key.generate(bits, seed)
+    n, p, q = k.export()
+    sk = oracle_key(bits, seed)
+    assert (p, q) == (sk.p, sk.q) and n == sk.p * sk.q
+
+
+def test_public_key_refuses_decrypt(he):
+    import torch
+    sk = oracle_key(1024, 1)
+    k = he.Key.public(1024, sk.public.n)
+    assert not k.has_private
+    ct = torch.zeros((1, 64), dtype=torch.int32, device="cuda")
+    with pytest.raises(he.HEError) as e:
+        he.decrypt(k, ct)
+    assert e.value.code == he.HE_ERR_NOPRIV
+
+
+# ---------------------------------------------------------- encoding
+def test_encode_bit_exact(he):
+    say("encode")
+    rng = np.random.default_rng(3)
+    g = W.gradients(5000, rng).reshape(-1)
+    s = 2.0 ** -32
+    g = np.concatenate([g, [0.5 * s, 1.5 * s, 2.5 * s, -1.5 * s, -0.5 * s, 1.0, -1.0, 0.0, 2.0 ** 30, -(2.0 ** 30)]])
+    m = host(he.encode(dev(g)))
+    assert m.tolist() == [P.encode(x) for x in g]
+
+
+def test_encode_out_of_range_flagged(he):
+    import torch
+    bad = torch.zeros(1, dtype=torch.int32, device="cuda")
+    x = dev(np.array([1.0, 2.0 ** 40, -(2.0 ** 31), float("nan"), 2.0 ** 31 - 2.0 ** -20]))
+    m = host(he.encode(x, n_bad=bad))
+    lo = np.iinfo(np.int64).min
+    assert m.tolist() == [1 << 32, lo, lo, lo, (1 << 63) - (1 << 12)]
+    assert int(host(bad)[0]) == 3
+
+
+# ---------------------------------------------------------- encryption
+def plaintexts(n, rng):
+    """Encoded gradients plus the edge plaintexts."""
+    g = W.gradients(n, rng).reshape(-1)
+    ms = [P.encode(x) for x in g]
+    edge = [0, 1, -1, (1 << 32) - 1, -((1 << 32) - 1), (1 << 63) - 1, -(1 << 63)]
+    return ms[: max(0, 2 * n - len(edge))] + edge
+
+
+@pytest.mark.parametrize("bits,seed,count", [(1024, 1, 2000), (1024, 1, 37), (2048, 2, 96)])
+@pytest.mark.parametrize("path", ["crt", "public"])
+def test_encrypt_explicit_r_bit_exact(he, bits, seed, count, path):
+    say(f"encrypt explicit r {bits} count={count} path={path}")
+    sk = oracle_key(bits, seed)
+    pk = sk.public
+    rng = np.random.default_rng(count + bits)
+    ms = plaintexts(count // 2 + 4, rng)[:count]
+    rs = W.random_units(pk.n, len(ms), rng)
+    k = gpu_key(bits, seed)
+    ct = he.encrypt(k, dev(np.array(ms, dtype=np.int64)), r=dev(he.ints_to_limbs(rs, k.limbs)),
+                    public=(path == "public"))
+    got = he.limbs_to_ints(host(ct))
+    want = pool.encrypt_many(pk, ms, rs)
+    assert got == want
+
+
+@pytest.mark.parametrize("bits,seed,count,offset", [(1024, 1, 2000, 0), (1024, 1, 19, 12345), (2048, 2, 64, 7)])
+@pytest.mark.parametrize("path", ["crt", "public"])
+def test_encrypt_seeded_r_bit_exact(he, bits, seed, count, offset, path):
+    say(f"encrypt seeded r {bits} count={count} path={path}")
+    sk = oracle_key(bits, seed)
+    pk = sk.public
+    rng = np.random.default_rng(count)
+    ms = plaintexts(count // 2 + 4, rng)[:count]
+    r_seed = 0xC0FFEE + count
+    rs = [P.seeded_r(pk.n, bits, r_seed, offset + i) for i in range(count)]
+    k = gpu_key(bits, seed)
+    ct = he.encrypt(k, dev(np.array(ms, dtype=np.int64)), seed=r_seed, offset=offset,
+                    public=(path == "public"))
+    assert he.limbs_to_ints(host(ct)) == pool.encrypt_many(pk, ms, rs)
+
+
+# ---------------------------------------------------------- decryption
+@pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
+def test_decrypt_exact(he, bits, seed):
+    say(f"decrypt {bits}")
+    sk = oracle_key(bits, seed)
+    pk = sk.public
+    rng = np.random.default_rng(bits)
+    ms = plaintexts(40, rng)
+    # near the decode boundary and outside int64
+    big = [(pk.n - 1) // 2, (pk.n + 1) // 2, 1 << 63, -(1 << 63) - 1, 1 << 200]
+    rs = W.random_units(pk.n, len(ms) + len(big), rng)
+    cts = pool.encrypt_many(pk, ms + big, rs)
+    k = gpu_key(bits, seed)
+    m, raw, ovf = he.decrypt(k, dev(he.ints_to_limbs(cts, 2 * k.limbs)), raw=True)
+    m, raw = host(m), he.limbs_to_ints(host(raw))
+    assert raw == [x % pk.n for x in ms + big]
+    assert m[: len(ms)].tolist() == ms
+    i64 = np.iinfo(np.int64)
+    assert m[len(ms):].tolist() == [i64.max, i64.min, i64.max, i64.min, i64.max]
+    assert int(host(ovf)[0]) == 5
+
+
+def test_decrypt_unit_ciphertext_is_zero(he):
+    # The empty-bin value 1 decrypts to 0.
+    k = gpu_key(2048, 2)
+    ct = np.zeros((3, 2 * k.limbs), dtype=np.int32)
+    ct[:, 0] = 1
+    m, _, _ = he.decrypt(k, dev(ct))
+    assert host(m).tolist() == [0, 0, 0]
+
+
+# ---------------------------------------------------------- aggregation
+def c1_inputs(M=1000, J=8, K=32, seed=0):
+    s = W.streams(seed)
+    g = W.gradients(M, s[1])
+    bins = W.bins_uniform(J, M, K, s[2])
+    return g, bins
+
+
+@functools.lru_cache(maxsize=None)
+def c1_oracle(bits=1024, kseed=1, M=1000, J=8, K=32):
+    sk = oracle_key(bits, kseed)
+    pk = sk.public
+    g, bins = c1_inputs(M, J, K)
+    m = [[P.encode(a), P.encode(b)] for a, b in g]
+    r_seed = 77
+    rs = [P.seeded_r(pk.n, bits, r_seed, i) for i in range(2 * M)]
+    flat = pool.encrypt_many(pk, [v for row in m for v in row], rs)
+    ct = [[flat[2 * i], flat[2 * i + 1]] for i in range(M)]
+    return m, ct, rs, r_seed, bins
+
+
+def test_c1_full_path_bit_exact(he):
+    """1024-bit key, 1000 samples, 8 features x 32 uniform bins, root node:
+    GPU encode -> encrypt (seeded r) -> histogram -> decrypt, against the
+    oracle at every stage."""
+    say("c1 full path")
+    import torch
+    bits, M, J, K = 1024, 1000, 8, 32
+    sk = oracle_key(bits, 1)
+    pk = sk.public
+    m, ct_o, rs, r_seed, bins = c1_oracle()
+    g, _ = c1_inputs(M, J, K)
+    k = gpu_key(bits, 1)
+    mg = he.encode(dev(g.reshape(-1)))
+    assert host(mg).tolist() == [v for row in m for v in row]
+    ct = he.encrypt(k, mg, seed=r_seed).view(M, 2, 2 * k.limbs)
+    assert he.limbs_to_ints(host(ct)) == [v for row in ct_o for v in row]
+    idx = np.arange(M, dtype=np.uint32)
+    job = he.Job(dev(idx.view(np.int32)), dev(bins), K)
+    (hist,) = he.hist_aggregate(k, ct, [job])
+    want = pool.aggregate_many(pk, ct_o, idx, bins, J, K)
+    got = he.limbs_to_ints(host(hist))
+    assert got == [want[f][b][t] for f in range(J) for b in range(K) for t in range(2)]
+    dm, _, ovf = he.decrypt(k, hist)
+    plain = P.plaintext_histogram(m, idx, bins, J, K)
+    assert host(dm).reshape(-1).tolist() == [plain[f][b][t] for f in range(J) for b in range(K) for t in range(2)]
+    assert int(host(ovf)[0]) == 0
+    # resident Montgomery form gives the same histogram
+    ctm = he.to_mont(k, ct)
+    (hist2,) = he.hist_aggregate(k, ctm, [he.Job(dev(idx.view(np.int32)), dev(bins), K)], form=he.HE_FORM_MONT)
+    assert torch.equal(hist, hist2)
+    assert torch.equal(he.from_mont(k, ctm), ct)
+
+
+@pytest.mark.parametrize("chunk", [1, 2, 3, 7, 64, 5000])
+def test_hist_independent_of_chunking_order_and_batching(he, chunk):
+    """Subsets (ragged sizes, empty bins, an empty node, a single sample) in
+    one batch equal the oracle histograms, for any chunk length and order."""
+    say(f"hist chunk={chunk}")
+    import torch
+    bits, M, J, K = 1024, 1000, 8, 32
+    sk = oracle_key(bits, 1)
+    pk = sk.public
+    m, ct_o, _, r_seed, bins = c1_oracle()
+    k = gpu_key(bits, 1)
+    ct = dev(he.ints_to_limbs([v for row in ct_o for v in row], 2 * k.limbs)).view(M, 2, 2 * k.limbs)
+    rng = np.random.default_rng(chunk)
+    subsets = [np.sort(rng.choice(M, size=s, replace=False)).astype(np.uint32) for s in (513, 1, 0, 77, 1000)]
+    subsets[3] = rng.permutation(subsets[3]).astype(np.uint32)  # any order
+    kbins = [K, 5, 3, 256, 17]
+    jb = []
+    for s, kb in zip(subsets, kbins):
+        b = (bins.astype(np.int64) % kb).astype(np.uint8)
+        if kb == 256:
+            b = rng.integers(0, 256, size=bins.shape, dtype=np.uint8)
+        jb.append(b)
+    jobs = [he.Job(dev(s.view(np.int32)), dev(b), kb) for s, b, kb in zip(subsets, jb, kbins)]
+    hists = he.hist_aggregate(k, ct, jobs, chunk=chunk)
+    for s, b, kb, h in zip(subsets, jb, kbins, hists):
+        want = P.aggregate(pk, ct_o, s, b, J, kb)
+        got = he.limbs_to_ints(host(h))
+        assert got == [want[f][x][t] for f in range(J) for x in range(kb) for t in range(2)]
+    # each job alone gives the same bits as in the batch
+    for s, b, kb, h in zip(subsets, jb, kbins, hists):
+        (alone,) = he.hist_aggregate(k, ct, [he.Job(dev(s.view(np.int32)), dev(b), kb)], chunk=chunk)
+        assert torch.equal(alone, h)
+
+
+# ---------------------------------------------------------- 2048-bit, GPU scale
+def test_c2_scale_sampled_parity(he):
+    """2048-bit key, 100,000 samples, 32 features x 256 Zipf(1.1) bins, root
+    node: sampled ciphertexts bit-exact, sampled histogram slots bit-exact via
+    the closed form prod E(m_i; r_i) = E(sum m_i; prod r_i), and every
+    decrypted histogram slot equal to the oracle's plaintext sum."""
+    say("c2 scale")
+    bits, M, J, K = 2048, 100_000, 32, 256
+    sk = oracle_key(bits, 2)
+    pk = sk.public
+    s = W.streams(1)
+    g = W.gradients(M, s[1])
+    bins = W.bins_zipf(J, M, K, s[2])
+    r_seed = 2024
+    k = gpu_key(bits, 2)
+    mg = he.encode(dev(g.reshape(-1)))
+    m = host(mg).reshape(M, 2)
+    ct = he.encrypt(k, mg, seed=r_seed).view(M, 2, 2 * k.limbs)
+    idx = np.arange(M, dtype=np.uint32)
+    (hist,) = he.hist_aggregate(k, ct, [he.Job(dev(idx.view(np.int32)), dev(bins), K)])
+    dm, _, ovf = he.decrypt(k, hist)
+    dm = host(dm).reshape(J, K, 2)
+    # plaintext sums from the oracle's own encoding
+    mo = np.array([[P.encode(a), P.encode(b)] for a, b in g], dtype=np.int64)
+    assert np.array_equal(m, mo)
+    for f in range(J):
+        for t in range(2):
+            ref = np.zeros(K, dtype=np.int64)
+            np.add.at(ref, bins[f].astype(np.int64), mo[:, t])
+            assert dm[f, :, t].tolist() == ref.tolist()
+    assert int(host(ovf)[0]) == 0
+    # sampled ciphertexts
+    rng = np.random.default_rng(9)
+    pick = rng.choice(2 * M, size=48, replace=False)
+    cth = host(ct).reshape(2 * M, -1)
+    got = he.limbs_to_ints(cth[pick])
+    want = pool.encrypt_many(pk, [int(mo.reshape(-1)[i]) for i in pick],
+                             [P.seeded_r(pk.n, bits, r_seed, int(i)) for i in pick])
+    assert got == want
+    # sampled histogram slots: hot, cold and one empty if present
+    hh = host(hist).reshape(J, K, 2, -1)
+    counts = np.stack([np.bincount(bins[f], minlength=K) for f in range(J)])
+    f0 = 3
+    order = np.argsort(counts[f0])
+    slots = [(f0, int(order[-1]), 0), (f0, int(order[-1]), 1), (f0, int(order[len(order) // 2]), 0),
+             (11, int(np.argsort(counts[11])[0]), 1)]
+    for f, b, t in slots:
+        members = np.nonzero(bins[f] == b)[0]
+        rp = 1
+        for i in members:
+            rp = rp * P.seeded_r(pk.n, bits, r_seed, 2 * int(i) + t) % pk.n
+        want = P.encrypt(pk, int(mo[members, t].sum()), rp) if len(members) else 1
+        assert he.limbs_to_ints(hh[f, b, t][None])[0] == want

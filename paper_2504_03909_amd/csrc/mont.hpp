@@ -10,11 +10,12 @@
 // pick the quotient digit that clears the lowest limb, add q * N, shift down
 // one limb).  The multiplier's limbs are read from LDS with one address per
 // group, so the 16 lanes get a broadcast; the multiplicand b and the modulus
-// N stay in registers.  Carries between lanes are deferred: each lane keeps a
-// small pending word for the column just above its limbs, which the shift
-// hands to the lane's own top limb on the next step, so no step waits on a
-// cross-lane carry chain.  The final carry resolution and the conditional
-// subtraction use a ballot carry-lookahead over the 16 lanes.
+// N stay in registers.  The accumulator is kept as per-column 64-bit words
+// with overflow counters (see "column accumulators" below), so a product costs
+// one multiply-add and one carry add, and only the lowest column is folded per
+// step; no step waits on a cross-lane carry chain.  The final carry
+// resolution and the conditional subtraction use a ballot carry-lookahead over
+// the 16 lanes.
 //
 // Every function here must be called by all 64 lanes of the wave (ballots and
 // DPP read all of them); callers predicate results, never control flow.
@@ -134,27 +135,8 @@ __device__ __forceinline__ Mod<K> load_mod(const uint32_t *N, uint32_t ninv) {
 }
 
 // ---- carry resolution and reduction ----------------------------------------
-// Turns the redundant accumulator (limbs + pending word per lane; lane 15's
-// pending word is the top limb S) into plain limbs; returns the top word in
-// lane 15 (0 or 1 for a Montgomery result below 2N < 2^(32S+1)).
-template <int K>
-__device__ __forceinline__ uint32_t resolve(uint32_t (&t)[K], uint32_t pc) {
-  const uint32_t in = from_prev(pc);
-  unsigned c;
-  t[0] = __builtin_addc(t[0], in, 0u, &c);
-#pragma unroll
-  for (int j = 1; j < K; ++j) t[j] = __builtin_addc(t[j], 0u, c, &c);
-  const bool gen = c;
-  bool prop = true;
-#pragma unroll
-  for (int j = 0; j < K; ++j) prop = prop && (t[j] == 0xFFFFFFFFu);
-  unsigned c2 = carry_in(gen, prop);
-#pragma unroll
-  for (int j = 0; j < K; ++j) t[j] = __builtin_addc(t[j], 0u, c2, &c2);
-  return pc + (uint32_t)gen + c2;
-}
-
-// If top:t >= N then t -= N (t < 2N on entry).  Result in [0, N).
+// If top:t >= N then t -= N (t < 2N on entry, top = bits at and above limb S,
+// meaningful in lane 15).  Result in [0, N).
 template <int K>
 __device__ __forceinline__ void cond_sub(uint32_t (&t)[K], uint32_t top, const Mod<K> &M) {
   uint32_t d[K];
@@ -174,36 +156,151 @@ __device__ __forceinline__ void cond_sub(uint32_t (&t)[K], uint32_t top, const M
   select(t, ge, d, t);
 }
 
-// ---- Montgomery product -----------------------------------------------------
-// One CIOS step for multiplier limb ai.
+// ---- column accumulators ------------------------------------------------------
+// The Montgomery accumulator is kept per column as a 64-bit word C plus an
+// overflow word O: column c holds V_c = C_c + O_c 2^64 and the accumulator is
+// sum_c V_c 2^(32 c).  A product a*b is added to a column by one
+// v_mad_u64_u32 (64-bit addend = C, carry-out into a lane mask) and one
+// v_addc_co_u32 of that mask into O, so no product needs its high half moved
+// to the next column.  The compiler does not form the mad carry-out from C++,
+// hence the inline assembly; the K mads come before their K carry adds so
+// every carry mask is read at least K-1 VALU instructions after it is written
+// (an s_nop covers K <= 2).
+
+// C[j] += a * b[j], O[j] += carry, for 4 columns.
+__device__ __forceinline__ void mac4(uint64_t &c0, uint64_t &c1, uint64_t &c2, uint64_t &c3,
+                                     uint32_t &o0, uint32_t &o1, uint32_t &o2, uint32_t &o3,
+                                     uint32_t a, uint32_t b0, uint32_t b1, uint32_t b2, uint32_t b3) {
+  uint64_t k0, k1, k2, k3;
+  asm("v_mad_u64_u32 %0, %8, %12, %13, %0\n\t"
+      "v_mad_u64_u32 %1, %9, %12, %14, %1\n\t"
+      "v_mad_u64_u32 %2, %10, %12, %15, %2\n\t"
+      "v_mad_u64_u32 %3, %11, %12, %16, %3\n\t"
+      "v_addc_co_u32_e64 %4, %8, %4, 0, %8\n\t"
+      "v_addc_co_u32_e64 %5, %9, %5, 0, %9\n\t"
+      "v_addc_co_u32_e64 %6, %10, %6, 0, %10\n\t"
+      "v_addc_co_u32_e64 %7, %11, %7, 0, %11"
+      : "+v"(c0), "+v"(c1), "+v"(c2), "+v"(c3), "+v"(o0), "+v"(o1), "+v"(o2), "+v"(o3),
+        "=&s"(k0), "=&s"(k1), "=&s"(k2), "=&s"(k3)
+      : "v"(a), "v"(b0), "v"(b1), "v"(b2), "v"(b3));
+}
+__device__ __forceinline__ void mac2(uint64_t &c0, uint64_t &c1, uint32_t &o0, uint32_t &o1,
+                                     uint32_t a, uint32_t b0, uint32_t b1) {
+  uint64_t k0, k1;
+  asm("v_mad_u64_u32 %0, %4, %6, %7, %0\n\t"
+      "v_mad_u64_u32 %1, %5, %6, %8, %1\n\t"
+      "s_nop 1\n\t"
+      "v_addc_co_u32_e64 %2, %4, %2, 0, %4\n\t"
+      "v_addc_co_u32_e64 %3, %5, %3, 0, %5"
+      : "+v"(c0), "+v"(c1), "+v"(o0), "+v"(o1), "=&s"(k0), "=&s"(k1)
+      : "v"(a), "v"(b0), "v"(b1));
+}
+__device__ __forceinline__ void mac1(uint64_t &c0, uint32_t &o0, uint32_t a, uint32_t b0) {
+  uint64_t k0;
+  asm("v_mad_u64_u32 %0, %2, %3, %4, %0\n\t"
+      "s_nop 2\n\t"
+      "v_addc_co_u32_e64 %1, %2, %1, 0, %2"
+      : "+v"(c0), "+v"(o0), "=&s"(k0)
+      : "v"(a), "v"(b0));
+}
+
 template <int K>
-__device__ __forceinline__ void mont_step(uint32_t (&acc)[K], uint32_t &pc, uint32_t ai,
+__device__ __forceinline__ void row_mac(uint64_t (&C)[K], uint32_t (&O)[K], uint32_t a,
+                                        const uint32_t (&b)[K]) {
+  if constexpr (K == 1) {
+    mac1(C[0], O[0], a, b[0]);
+  } else if constexpr (K == 2) {
+    mac2(C[0], C[1], O[0], O[1], a, b[0], b[1]);
+  } else {
+    static_assert(K % 4 == 0, "K must be 1, 2 or a multiple of 4");
+#pragma unroll
+    for (int j = 0; j < K; j += 4)
+      mac4(C[j], C[j + 1], C[j + 2], C[j + 3], O[j], O[j + 1], O[j + 2], O[j + 3], a, b[j], b[j + 1],
+           b[j + 2], b[j + 3]);
+  }
+}
+
+// Low 32 bits of x * y through the full-rate multiplier.
+__device__ __forceinline__ uint32_t mul_lo32(uint32_t x, uint32_t y) {
+  uint64_t r, k;
+  asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(r), "=s"(k) : "v"(x), "v"(y));
+  return (uint32_t)r;
+}
+
+// One CIOS step for multiplier limb ai: add ai*b, pick q that clears the
+// lowest column, add q*N, divide by 2^32.  The division moves the upper part
+// (high word and overflow) of column 0 into column 1 -- the same weight after
+// the shift -- and hands the low word of column 0 to the previous lane, whose
+// new top column it becomes (lane 0's low word is zero and is dropped).
+template <int K>
+__device__ __forceinline__ void mont_step(uint64_t (&C)[K], uint32_t (&O)[K], uint32_t ai,
                                           const uint32_t (&b)[K], const Mod<K> &M) {
-  uint64_t x[K];
+  row_mac<K>(C, O, ai, b);
+  const uint32_t q = bcast_first(mul_lo32((uint32_t)C[0], M.ninv));
+  row_mac<K>(C, O, q, M.n);
+  const uint32_t lo0 = (uint32_t)C[0], hi0 = (uint32_t)(C[0] >> 32);
+  const uint32_t nb = from_next(lo0);
+  if constexpr (K == 1) {
+    // the lane's new column = low word from the next lane + own upper part
+    unsigned c;
+    const uint32_t l = __builtin_addc(hi0, nb, 0u, &c);
+    const uint32_t h = __builtin_addc(O[0], 0u, c, &c);
+    C[0] = ((uint64_t)h << 32) | l;
+    O[0] = c;
+  } else {
+    unsigned c;
+    const uint32_t l1 = __builtin_addc((uint32_t)C[1], hi0, 0u, &c);
+    const uint32_t h1 = __builtin_addc((uint32_t)(C[1] >> 32), O[0], c, &c);
+    const uint32_t o1 = O[1] + c;
+    C[0] = ((uint64_t)h1 << 32) | l1;
+    O[0] = o1;
 #pragma unroll
-  for (int j = 0; j < K; ++j) x[j] = (uint64_t)ai * b[j] + acc[j];
-  uint32_t u[K];
-  unsigned c = 0;
-  u[0] = (uint32_t)x[0];
+    for (int j = 1; j + 1 < K; ++j) {
+      C[j] = C[j + 1];
+      O[j] = O[j + 1];
+    }
+    C[K - 1] = nb;
+    O[K - 1] = 0;
+  }
+}
+
+// Turns the column accumulators into plain limbs t (columns 0..S-1 of the
+// group) and returns, in lane 15, the part at and above limb S.
+template <int K>
+__device__ __forceinline__ uint32_t resolve(uint32_t (&t)[K], const uint64_t (&C)[K],
+                                            const uint32_t (&O)[K]) {
+  // Column c receives lo(C_c), hi(C_{c-1}) and O_{c-2}; the terms of the
+  // lane's lowest columns come from the previous lane(s).
+  const uint32_t in_hi = from_prev((uint32_t)(C[K - 1] >> 32));
+  const uint32_t in_o1 = from_prev(O[K - 1]);
+  const uint32_t in_o2 = K >= 2 ? from_prev(O[K >= 2 ? K - 2 : 0]) : from_prev(in_o1);
+  uint32_t carry = 0;
 #pragma unroll
-  for (int j = 1; j < K; ++j) u[j] = __builtin_addc((uint32_t)x[j], (uint32_t)(x[j - 1] >> 32), c, &c);
-  const uint32_t top1 = (uint32_t)(x[K - 1] >> 32) + c;
-  const uint32_t q = bcast_first(u[0] * M.ninv);
-  uint64_t y[K];
+  for (int j = 0; j < K; ++j) {
+    const uint32_t h = j >= 1 ? (uint32_t)(C[j >= 1 ? j - 1 : 0] >> 32) : in_hi;
+    const uint32_t o = j >= 2 ? O[j >= 2 ? j - 2 : 0] : (j == 1 ? in_o1 : in_o2);
+    const uint64_t s = (uint64_t)(uint32_t)C[j] + h + o + carry;
+    t[j] = (uint32_t)s;
+    carry = (uint32_t)(s >> 32);
+  }
+  // the lane's carry (at most 3) goes to the next lane's lowest limb
+  const uint32_t cin = from_prev(carry);
+  unsigned c;
+  t[0] = __builtin_addc(t[0], cin, 0u, &c);
 #pragma unroll
-  for (int j = 0; j < K; ++j) y[j] = (uint64_t)q * M.n[j] + u[j];
-  uint32_t v[K];
-  unsigned c2 = 0;
-  v[0] = (uint32_t)y[0];
+  for (int j = 1; j < K; ++j) t[j] = __builtin_addc(t[j], 0u, c, &c);
+  const bool gen = c;
+  bool prop = true;
 #pragma unroll
-  for (int j = 1; j < K; ++j) v[j] = __builtin_addc((uint32_t)y[j], (uint32_t)(y[j - 1] >> 32), c2, &c2);
-  const uint32_t top2 = (uint32_t)(y[K - 1] >> 32) + c2;
-  const uint32_t nb = from_next(v[0]);
-  const uint64_t s = (uint64_t)nb + top1 + top2 + pc;
+  for (int j = 0; j < K; ++j) prop = prop && (t[j] == 0xFFFFFFFFu);
+  unsigned c2 = carry_in(gen, prop);
 #pragma unroll
-  for (int j = 0; j + 1 < K; ++j) acc[j] = v[j + 1];
-  acc[K - 1] = (uint32_t)s;
-  pc = (uint32_t)(s >> 32);
+  for (int j = 0; j < K; ++j) t[j] = __builtin_addc(t[j], 0u, c2, &c2);
+  // lane 15: everything at and above limb S.  The result is below 2N < 2^(32S+1),
+  // so this is 0 or 1; any nonzero part counts.
+  const uint32_t top_hi = (uint32_t)(C[K - 1] >> 32);
+  const uint32_t top_o2 = K >= 2 ? O[K >= 2 ? K - 2 : 0] : in_o1;
+  return (top_hi | top_o2 | O[K - 1]) != 0u ? 1u : (carry + (uint32_t)gen + c2);
 }
 
 template <int K>
@@ -227,19 +324,32 @@ __device__ __forceinline__ void lds_limbs(uint32_t (&a)[K], const uint32_t *p) {
 template <int K>
 __device__ __forceinline__ void mont_mul_lds(uint32_t (&t)[K], const uint32_t *a_lds,
                                              const uint32_t (&b)[K], const Mod<K> &M) {
-  uint32_t acc[K];
-  set_zero(acc);
-  uint32_t pc = 0;
-#pragma unroll 1
-  for (int i0 = 0; i0 < kGroupLanes * K; i0 += K) {
-    uint32_t av[K];
-    lds_limbs<K>(av, a_lds + i0);
+  uint64_t C[K];
+  uint32_t O[K];
 #pragma unroll
-    for (int s = 0; s < K; ++s) mont_step<K>(acc, pc, av[s], b, M);
+  for (int j = 0; j < K; ++j) {
+    C[j] = 0;
+    O[j] = 0;
   }
-  const uint32_t top = resolve<K>(acc, pc);
-  cond_sub<K>(acc, top, M);
-  copy(t, acc);
+  // U steps per loop iteration (at least 8 and two full rotations of the
+  // lane's columns) so the loop-carried registers rotate back less often.
+  constexpr int U = K >= 4 ? 2 * K : 8;
+  static_assert((kGroupLanes * K) % U == 0, "unroll must divide S");
+#pragma unroll 1
+  for (int i0 = 0; i0 < kGroupLanes * K; i0 += U) {
+    uint32_t av[U];
+#pragma unroll
+    for (int h = 0; h < U; h += 4) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(a_lds + i0 + h);
+      av[h] = v.x; av[h + 1] = v.y; av[h + 2] = v.z; av[h + 3] = v.w;
+    }
+#pragma unroll
+    for (int s = 0; s < U; ++s) mont_step<K>(C, O, av[s], b, M);
+  }
+  uint32_t r[K];
+  const uint32_t top = resolve<K>(r, C, O);
+  cond_sub<K>(r, top, M);
+  copy(t, r);
 }
 
 // t = a * b * 2^(-32 S) mod N, both operands in registers; `lds` is this

@@ -8,6 +8,14 @@ ciphertexts.  Inputs (gradients, bins, sample list, key) are resident in HBM
 before timing starts.  Prints one JSON line.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+
+Other workloads (each prints its own JSON line; not the default):
+    --workload tree      2048-bit, 1,000,000 samples, 64 x 256 Zipf bins, depth-6
+                         tree: one job per launch vs one captured plan per level
+    --workload batched   64 uneven node jobs over 200,000 resident samples:
+                         one launch per job vs one batched launch vs graph replay
+    --workload served    request loop (Poisson arrivals, two keys, four parties):
+                         continuous batching vs FIFO one-request-per-launch
 """
 from __future__ import annotations
 
@@ -138,6 +146,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", default="pass", choices=("pass", "tree", "batched", "served"))
+    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--rate", type=float, default=200.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -150,6 +161,10 @@ def main():
     from synth import workloads as W
 
     torch.cuda.set_device(0)
+    if args.workload != "pass":
+        line = {"tree": bench_tree, "batched": bench_batched, "served": bench_served}[args.workload](args)
+        print(json.dumps(line), flush=True)
+        return
     stream = torch.cuda.current_stream()
     key = he.Key.generate(KEY_BITS, KEY_SEED)
     n, p, q = key.export()
@@ -263,6 +278,147 @@ def main():
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, q, grads_h, bins_h)
     print(json.dumps(line), flush=True)
+
+
+def _timed(fn):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    out = fn()
+    torch.cuda.synchronize()
+    return out, time.perf_counter() - t0
+
+
+def bench_tree(args):
+    """2048-bit key, 1,000,000 samples, 64 features x 256 Zipf(1.1) bins,
+    depth-6 tree (63 nodes, seeded splits, direct aggregation of every node)."""
+    import numpy as np
+    import torch
+    from paper_2504_03909_amd import he, pipeline
+    from synth import workloads as W
+    Mt, Jt, Kt, depth = 1_000_000, 64, 256, 6
+    key = he.Key.generate(KEY_BITS, KEY_SEED)
+    st = W.streams(3)
+    g = torch.from_numpy(W.gradients(Mt, st[1])).cuda()
+    bins = torch.from_numpy(W.bins_zipf(Jt, Mt, Kt, st[2])).cuda()
+    levels = [[torch.from_numpy(n.view(np.int32)).cuda() for n in lvl] for lvl in W.tree_levels(Mt, depth, st[4])]
+    pipeline.encrypt_gradients(key, g[:1000].contiguous(), R_SEED)  # warm-up
+    res, t_enc = _timed(lambda: pipeline.encrypt_gradients(key, g, R_SEED))
+    pipeline.aggregate_levels(res, levels[:1], bins, Kt, mode="per_node")  # warm-up / workspace
+    run_plain, t_plain = _timed(lambda: pipeline.aggregate_levels(res, levels, bins, Kt, mode="per_node"))
+    run_batched, t_batched = _timed(lambda: pipeline.aggregate_levels(res, levels, bins, Kt, mode="per_level"))
+    plans = pipeline.aggregate_levels(res, levels, bins, Kt, mode="per_level_graph")
+    torch.cuda.synchronize()
+    _, t_graph = _timed(lambda: [p.launch() for p in plans.plans])
+    same = all(torch.equal(a, b) for la, lb in zip(run_plain.hists, plans.hists) for a, b in zip(la, lb))
+    _, t_dec = _timed(lambda: pipeline.decrypt_levels(key, run_plain))
+    contrib = 2 * Jt * sum(int(n.numel()) for lvl in levels for n in lvl)
+    n_dec = 63 * Jt * Kt * 2
+    return {
+        "metric": "Paillier encryptions/s + encrypted hist sample-adds/s at 2048-bit key",
+        "workload": "2048-bit key, 1000000 samples, 64 features x 256 Zipf(1.1) bins, depth-6 tree "
+                    "(63 nodes), direct aggregation of every node",
+        "encrypt_s": round(t_enc, 3), "encryptions_per_s": round(2 * Mt / t_enc, 1),
+        "aggregate_one_job_per_launch_s": round(t_plain, 3),
+        "aggregate_per_level_batched_s": round(t_batched, 3),
+        "aggregate_per_level_graph_s": round(t_graph, 3),
+        "sample_adds_per_s_one_job_per_launch": round(contrib / t_plain, 1),
+        "sample_adds_per_s_graph": round(contrib / t_graph, 1),
+        "contributions": contrib,
+        "decrypt_s": round(t_dec, 3), "decryptions_per_s": round(n_dec / t_dec, 1),
+        "graph_equals_plain": bool(same),
+        "total_s_one_job_per_launch": round(t_enc + t_plain + t_dec, 3),
+    }
+
+
+def bench_batched(args):
+    """64 uneven tree-node jobs (|S| log-uniform in [1e3, 2e5], F in [8, 128],
+    B in {16, 64, 256}) over 200,000 resident 2048-bit encrypted samples."""
+    import numpy as np
+    import torch
+    from paper_2504_03909_amd import he
+    from synth import workloads as W
+    Mp = 200_000
+    key = he.Key.generate(KEY_BITS, KEY_SEED)
+    st = W.streams(4)
+    m = he.encode(torch.from_numpy(W.gradients(Mp, st[1]).reshape(-1)).cuda())
+    ctm = he.to_mont(key, he.encrypt(key, m, seed=R_SEED).view(Mp, 2, -1))
+    tables = {b: torch.from_numpy(t).cuda() for b, t in W.bins_tables(Mp, 128, (16, 64, 256), st[2]).items()}
+    shapes = W.batched_jobs(64, st[5], Mp)
+
+    def jobs():
+        return [he.Job(torch.from_numpy(sh["sample_idx"].view(np.int32)).cuda(),
+                       tables[sh["n_bins"]][sh["f0"]:sh["f0"] + sh["n_features"]], sh["n_bins"]) for sh in shapes]
+    contrib = sum(2 * sh["n_features"] * sh["sample_idx"].size for sh in shapes)
+    ja = jobs()
+    for j in ja[:2]:
+        he.hist_aggregate(key, ctm, [j], form=he.HE_FORM_MONT, chunk=64)
+    _, t_single = _timed(lambda: [he.hist_aggregate(key, ctm, [j], form=he.HE_FORM_MONT, chunk=64) for j in ja])
+    jb = jobs()
+    he.hist_aggregate(key, ctm, jb, form=he.HE_FORM_MONT, chunk=64)
+    _, t_batch64 = _timed(lambda: he.hist_aggregate(key, ctm, jb, form=he.HE_FORM_MONT, chunk=64))
+    chunk, split, tune_ms = he.hist_autotune(key, ctm, jb, form=he.HE_FORM_MONT)
+    _, t_tuned = _timed(lambda: he.hist_aggregate(key, ctm, jb, form=he.HE_FORM_MONT))
+    jc = jobs()
+    plan = he.HistPlan(key, ctm, jc, form=he.HE_FORM_MONT)
+    plan.launch()
+    _, t_graph = _timed(lambda: plan.launch())
+    same = all(torch.equal(a.hist, b.hist) and torch.equal(a.hist, c.hist) for a, b, c in zip(ja, jb, jc))
+    L = key.limbs
+    prod = contrib * (2 * (2 * L) ** 2 + 2 * L)
+    return {
+        "metric": "encrypted hist sample-adds/s at 2048-bit key",
+        "workload": "64 node jobs, |S| log-uniform [1e3, 2e5], F uniform [8, 128], B in {16, 64, 256}, "
+                    "200000 resident samples",
+        "contributions": contrib,
+        "one_job_per_launch_ms": round(t_single * 1e3, 3),
+        "batched_chunk64_ms": round(t_batch64 * 1e3, 3),
+        "batched_autotuned_ms": round(t_tuned * 1e3, 3),
+        "graph_replay_ms": round(t_graph * 1e3, 3),
+        "autotuned": {"chunk": chunk, "split": split, "ms": round(tune_ms, 3)},
+        "sample_adds_per_s": {"one_job_per_launch": round(contrib / t_single, 1),
+                              "graph_replay": round(contrib / t_graph, 1)},
+        "alu_frac_graph_replay": round(prod / t_graph / PEAK_MUL32_PER_S, 4),
+        "results_identical": bool(same),
+    }
+
+
+def bench_served(args):
+    """Request loop: Poisson arrivals of encrypt (1k-100k samples),
+    aggregate (one depth-6 tree node, F in [8, 128]) and decrypt (up to
+    64 x 256 x 2 ciphertexts) requests from 4 passive parties; 90% under a
+    2048-bit key (200,000 resident samples), 10% under a 1024-bit key
+    (50,000); mix 10/45/45.  Continuous batching vs FIFO one request per
+    launch, at the given rate and at 0.8x the measured capacity."""
+    import numpy as np
+    import torch
+    from paper_2504_03909_amd import he, serve
+    k2 = he.Key.generate(2048, KEY_SEED)
+    k1 = he.Key.generate(1024, 1)
+    rng = np.random.default_rng(5)
+    setups = {"k2048": serve.make_setup(k2, 200_000, 6, 4, 128, rng, 11),
+              "k1024": serve.make_setup(k1, 50_000, 6, 4, 64, rng, 12)}
+    budget = 64 << 30
+    share = {"k2048": 0.9, "k1024": 0.1}
+
+    def run(rate, n, policy, seed):
+        tr = serve.build_trace(np.random.default_rng(seed), n, rate, setups, share)
+        be = serve.backend_for(setups, n_streams=4 if policy == "continuous" else 1)
+        return serve.Server(be, budget, max_inflight=8, policy=policy).run(tr, time_limit=900)
+
+    run(1000.0, 16, "continuous", 99)  # warm-up: workspaces and kernels
+    out = {"metric": "p50/p99 request latency and throughput, 2048-bit (90%) + 1024-bit (10%) keys",
+           "workload": f"{args.requests} requests, Poisson arrivals, mix encrypt/aggregate/decrypt 10/45/45, "
+                       "4 passive parties, depth-6 trees over resident encrypted gradients, HBM budget 64 GiB"}
+    cont = run(args.rate, args.requests, "continuous", 1)
+    fifo = run(args.rate, args.requests, "fifo", 1)
+    out[f"rate_{args.rate:g}"] = {"continuous": cont, "fifo": fifo}
+    cap = cont["throughput_req_s"]
+    r2 = round(0.8 * cap, 2)
+    n2 = max(50, int(min(args.requests, r2 * 20)))
+    out[f"rate_{r2:g}_(0.8x_capacity)"] = {"continuous": run(r2, n2, "continuous", 2),
+                                            "fifo": run(r2, n2, "fifo", 2)}
+    return out
 
 
 if __name__ == "__main__":

@@ -166,6 +166,31 @@ int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint64_t rows, i
                          const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk,
                          hipStream_t stream);
 
+/* Autotuner for the batched aggregation: times he_hist_aggregate on these
+ * jobs (synchronising `stream`) for work-item lengths of 16..512 samples and
+ * for one or two groups per (item, slot), and remembers the fastest choice
+ * for the shape class (key size, total contributions and job count rounded
+ * to powers of two, largest bin count).  Later he_hist_aggregate calls and
+ * plans with chunk 0 in the same class use it.  The histograms are written
+ * (correctly) several times.  Outputs are host pointers, each optional. */
+int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
+                     const he_hist_job *jobs, uint32_t n_jobs, uint32_t *chunk, uint32_t *split,
+                     float *ms, hipStream_t stream);
+
+/* A batched aggregation captured once into a HIP graph (all of its kernels,
+ * with a workspace the plan owns), to be replayed with one launch, e.g. once
+ * per tree level per boosting round.  Each replay reads the buffers that the
+ * job descriptors and `ct` point to at replay time, so the caller refreshes
+ * their contents in place; the sizes are fixed at creation.  chunk/split 0
+ * take the autotuned or default values.  Replays of one plan must not
+ * overlap (one plan per concurrent stream). */
+typedef struct he_hist_plan he_hist_plan;
+int he_hist_plan_create(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
+                        const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk, uint32_t split,
+                        he_hist_plan **out);
+int he_hist_plan_launch(he_hist_plan *plan, hipStream_t stream);
+void he_hist_plan_free(he_hist_plan *plan);
+
 /* Decryption (Sec. III-B: the active party decrypts the returned
  * histograms), by the CRT: m_p = L_p(c^(p-1) mod p^2) h_p mod p with
  * h_p = (-q mod p)^-1 mod p, likewise m_q, then m = m_q + q ((m_p - m_q)

@@ -6,6 +6,7 @@
 #include <string.h>
 
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -334,31 +335,41 @@ int he_hist_aggregate(const he_key *key, const uint32_t *ct, uint64_t rows, int 
 
 namespace {
 size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
-}  // namespace
 
-extern "C" int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
-                                    const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk,
-                                    hipStream_t stream) {
+// Device layout of one histogram batch: job descriptors, flat per-(feature,
+// bin) arrays, work items, the permutation and the partial products.
+struct HistLayout {
+  std::vector<he::DJob> dj;
+  uint64_t total_fb = 0, total_f = 0, total_blocks = 0, total_perm = 0, items_cap = 0;
+  uint64_t contributions = 0;
+  size_t o_jobs = 0, o_counts = 0, o_offs = 0, o_cursor = 0, o_fch = 0, o_fitem = 0, o_ftot = 0,
+         o_fbase = 0, o_nitems = 0, o_items = 0, o_perm = 0, o_part = 0, o_ctm = 0, bytes = 0;
+  uint32_t chunk = 64, split = 2;
+  bool convert = false;
+};
+
+int plan_layout(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form, const he_hist_job *jobs,
+                uint32_t n_jobs, uint32_t chunk, uint32_t split, HistLayout &lay) {
   if (!key) return fail(HE_ERR_ARG, "null key");
-  if (n_jobs == 0) return HE_OK;
   if (!jobs) return fail(HE_ERR_ARG, "null jobs");
   if (ct_form != HE_FORM_CANONICAL && ct_form != HE_FORM_MONT) return fail(HE_ERR_ARG, "bad ct_form");
   if (chunk == 0) chunk = 64;
   if (chunk > (1u << 20)) return fail(HE_ERR_ARG, "chunk too large");
-  const size_t L = key->n_bits / 32, S = 2 * L;
-  std::vector<he::DJob> dj(n_jobs);
-  uint64_t total_fb = 0, total_f = 0, total_blocks = 0, total_perm = 0, items_cap = 0;
+  if (split != 1 && split != 2) return fail(HE_ERR_ARG, "split must be 1 or 2");
+  const size_t S = 2 * (key->n_bits / 32);
+  lay.dj.assign(n_jobs, he::DJob{});
+  lay.chunk = chunk;
+  lay.split = split;
   for (uint32_t j = 0; j < n_jobs; ++j) {
     const he_hist_job &J = jobs[j];
+    const std::string tag = "job " + std::to_string(j) + ": ";
     if (J.n_features == 0 || J.n_bins == 0 || J.n_bins > 256)
-      return fail(HE_ERR_ARG, "job " + std::to_string(j) + ": need n_features >= 1 and 1 <= n_bins <= 256");
-    if (!J.hist || !J.bins || (J.n_samples && !J.sample_idx))
-      return fail(HE_ERR_ARG, "job " + std::to_string(j) + ": null pointer");
-    if (J.n_samples > rows || J.n_samples >= (1ull << 32))
-      return fail(HE_ERR_ARG, "job " + std::to_string(j) + ": n_samples exceeds rows");
+      return fail(HE_ERR_ARG, tag + "need n_features >= 1 and 1 <= n_bins <= 256");
+    if (!J.hist || !J.bins || (J.n_samples && !J.sample_idx)) return fail(HE_ERR_ARG, tag + "null pointer");
+    if (J.n_samples > rows || J.n_samples >= (1ull << 32)) return fail(HE_ERR_ARG, tag + "n_samples exceeds rows");
     if (J.n_samples && !ct) return fail(HE_ERR_ARG, "null ct");
-    if (J.bins_ld < rows) return fail(HE_ERR_ARG, "job " + std::to_string(j) + ": bins_ld < rows");
-    he::DJob &d = dj[j];
+    if (J.bins_ld < rows) return fail(HE_ERR_ARG, tag + "bins_ld < rows");
+    he::DJob &d = lay.dj[j];
     d.idx = J.sample_idx;
     d.bins = J.bins;
     d.hist = J.hist;
@@ -366,65 +377,258 @@ extern "C" int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint6
     d.ld = J.bins_ld;
     d.F = J.n_features;
     d.B = J.n_bins;
-    d.fb_off = total_fb;
-    d.perm_off = total_perm;
-    d.blk_off = total_blocks;
-    d.f_off = (uint32_t)total_f;
+    d.fb_off = lay.total_fb;
+    d.perm_off = lay.total_perm;
+    d.blk_off = lay.total_blocks;
+    d.f_off = (uint32_t)lay.total_f;
     d.nblk = (uint32_t)((J.n_samples + he::kSampleBlock - 1) / he::kSampleBlock);
-    total_fb += (uint64_t)d.F * d.B;
-    total_f += d.F;
-    total_blocks += (uint64_t)d.F * d.nblk;
-    total_perm += (uint64_t)d.F * d.n;
-    items_cap += (uint64_t)d.F * ((d.n + chunk - 1) / chunk + std::min<uint64_t>(d.B, d.n));
+    lay.total_fb += (uint64_t)d.F * d.B;
+    lay.total_f += d.F;
+    lay.total_blocks += (uint64_t)d.F * d.nblk;
+    lay.total_perm += (uint64_t)d.F * d.n;
+    lay.items_cap += (uint64_t)d.F * ((d.n + chunk - 1) / chunk + std::min<uint64_t>(d.B, d.n));
+    lay.contributions += 2ull * d.F * d.n;
   }
-  if (items_cap >= (1ull << 32)) return fail(HE_ERR_ARG, "too many work items; use a larger chunk");
-  // workspace layout
+  if (lay.items_cap >= (1ull << 32)) return fail(HE_ERR_ARG, "too many work items; use a larger chunk");
   size_t off = 0;
   auto take = [&](size_t bytes) {
-    size_t o = off;
+    const size_t o = off;
     off = align_up(off + bytes);
     return o;
   };
-  const size_t o_jobs = take(n_jobs * sizeof(he::DJob));
-  const size_t o_counts = take(total_fb * 4), o_offs = take(total_fb * 4), o_cursor = take(total_fb * 4);
-  const size_t o_fch = take(total_fb * 4), o_fitem = take(total_fb * 4);
-  const size_t o_ftot = take(total_f * 4), o_fbase = take(total_f * 4), o_nitems = take(4);
-  const size_t o_items = take(std::max<uint64_t>(items_cap, 1) * sizeof(he::HistItem));
-  const size_t o_perm = take(std::max<uint64_t>(total_perm, 1) * 4);
-  const size_t o_part = take(std::max<uint64_t>(items_cap, 1) * 2 * S * 4);
-  const size_t o_ctm = ct_form == HE_FORM_CANONICAL ? take(rows * 2 * S * 4) : 0;
-  Workspace *w = workspace(stream);
-  int rc = ensure(w->hist, off, stream);
-  if (rc) return rc;
-  char *base = (char *)w->hist.p;
+  lay.o_jobs = take(n_jobs * sizeof(he::DJob));
+  lay.o_counts = take(lay.total_fb * 4);
+  lay.o_offs = take(lay.total_fb * 4);
+  lay.o_cursor = take(lay.total_fb * 4);
+  lay.o_fch = take(lay.total_fb * 4);
+  lay.o_fitem = take(lay.total_fb * 4);
+  lay.o_ftot = take(lay.total_f * 4);
+  lay.o_fbase = take(lay.total_f * 4);
+  lay.o_nitems = take(4);
+  lay.o_items = take(std::max<uint64_t>(lay.items_cap, 1) * sizeof(he::HistItem));
+  lay.o_perm = take(std::max<uint64_t>(lay.total_perm, 1) * 4);
+  lay.o_part = take(std::max<uint64_t>(lay.items_cap, 1) * 2 * S * 4);
+  lay.convert = ct_form == HE_FORM_CANONICAL && rows > 0;
+  lay.o_ctm = lay.convert ? take(rows * 2 * S * 4) : 0;
+  lay.bytes = off;
+  return HE_OK;
+}
+
+he::HistWs bind_layout(const HistLayout &lay, char *base) {
   he::HistWs ws{};
-  ws.jobs = (he::DJob *)(base + o_jobs);
-  ws.n_jobs = n_jobs;
-  ws.counts = (uint32_t *)(base + o_counts);
-  ws.offs = (uint32_t *)(base + o_offs);
-  ws.cursor = (uint32_t *)(base + o_cursor);
-  ws.fch = (uint32_t *)(base + o_fch);
-  ws.fitem = (uint32_t *)(base + o_fitem);
-  ws.ftot = (uint32_t *)(base + o_ftot);
-  ws.fbase = (uint32_t *)(base + o_fbase);
-  ws.n_items = (uint32_t *)(base + o_nitems);
-  ws.items = (he::HistItem *)(base + o_items);
-  ws.perm = (uint32_t *)(base + o_perm);
-  ws.partials = (uint32_t *)(base + o_part);
-  ws.total_fb = total_fb;
-  ws.total_f = total_f;
-  ws.total_blocks = total_blocks;
-  ws.items_cap = items_cap;
-  ws.chunk = chunk;
-  const uint32_t *ctm = ct;
+  ws.jobs = (he::DJob *)(base + lay.o_jobs);
+  ws.n_jobs = (uint32_t)lay.dj.size();
+  ws.counts = (uint32_t *)(base + lay.o_counts);
+  ws.offs = (uint32_t *)(base + lay.o_offs);
+  ws.cursor = (uint32_t *)(base + lay.o_cursor);
+  ws.fch = (uint32_t *)(base + lay.o_fch);
+  ws.fitem = (uint32_t *)(base + lay.o_fitem);
+  ws.ftot = (uint32_t *)(base + lay.o_ftot);
+  ws.fbase = (uint32_t *)(base + lay.o_fbase);
+  ws.n_items = (uint32_t *)(base + lay.o_nitems);
+  ws.items = (he::HistItem *)(base + lay.o_items);
+  ws.perm = (uint32_t *)(base + lay.o_perm);
+  ws.partials = (uint32_t *)(base + lay.o_part);
+  ws.total_fb = lay.total_fb;
+  ws.total_f = lay.total_f;
+  ws.total_blocks = lay.total_blocks;
+  ws.items_cap = lay.items_cap;
+  ws.chunk = lay.chunk;
+  ws.split = lay.split;
+  return ws;
+}
+
+// Enqueues every kernel of one batch on `stream` (no allocation, no
+// memset: safe to capture into a graph).
+int enqueue_hist(const he_key *key, const uint32_t *ct, uint64_t rows, const HistLayout &lay, char *base,
+                 hipStream_t stream) {
+  const he::HistWs ws = bind_layout(lay, base);
   const int KP = kp_of(key);
-  if (ct_form == HE_FORM_CANONICAL && rows) {
-    uint32_t *dst = (uint32_t *)(base + o_ctm);
+  const uint32_t *ctm = ct;
+  if (lay.convert) {
+    uint32_t *dst = (uint32_t *)(base + lay.o_ctm);
     HE_TRY_HIP(he::launch_mont_convert(KP, key->dk, ct, rows * 2, dst, true, stream));
     ctm = dst;
   }
-  const uint32_t grid = he::resident_blocks(KP, 3);
-  HE_TRY_HIP(he::launch_hist(KP, key->dk, ctm, dj.data(), ws, grid, stream));
+  HE_TRY_HIP(he::launch_hist(KP, key->dk, ctm, lay.dj.data(), ws, he::resident_blocks(KP, 3), stream));
+  return HE_OK;
+}
+
+int hist_run(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form, const he_hist_job *jobs,
+             uint32_t n_jobs, uint32_t chunk, uint32_t split, hipStream_t stream) {
+  if (n_jobs == 0) return key ? HE_OK : fail(HE_ERR_ARG, "null key");
+  HistLayout lay;
+  int rc = plan_layout(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, lay);
+  if (rc) return rc;
+  Workspace *w = workspace(stream);
+  rc = ensure(w->hist, lay.bytes, stream);
+  if (rc) return rc;
+  return enqueue_hist(key, ct, rows, lay, (char *)w->hist.p, stream);
+}
+
+// Autotuner cache: best (chunk, split) per shape class.
+struct TuneKey {
+  uint32_t bits, log2_contrib, log2_jobs, max_bins;
+  bool operator<(const TuneKey &o) const {
+    return std::tie(bits, log2_contrib, log2_jobs, max_bins) < std::tie(o.bits, o.log2_contrib, o.log2_jobs, o.max_bins);
+  }
+};
+struct TuneVal {
+  uint32_t chunk, split;
+  float ms;
+};
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneVal> g_tune;
+
+uint32_t ilog2(uint64_t x) {
+  uint32_t r = 0;
+  while (x > 1) {
+    x >>= 1;
+    ++r;
+  }
+  return r;
+}
+
+TuneKey tune_key(const he_key *key, const he_hist_job *jobs, uint32_t n_jobs) {
+  uint64_t contrib = 0;
+  uint32_t mb = 0;
+  for (uint32_t j = 0; j < n_jobs; ++j) {
+    contrib += 2ull * jobs[j].n_features * jobs[j].n_samples;
+    mb = std::max(mb, jobs[j].n_bins);
+  }
+  return TuneKey{key->n_bits, ilog2(contrib + 1), ilog2(n_jobs), mb};
+}
+
+}  // namespace
+
+extern "C" int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
+                                    const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk,
+                                    hipStream_t stream) {
+  uint32_t split = 2;
+  if (chunk == 0 && key && jobs && n_jobs) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(key, jobs, n_jobs));
+    if (it != g_tune.end()) {
+      chunk = it->second.chunk;
+      split = it->second.split;
+    }
+  }
+  return hist_run(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, stream);
+}
+
+extern "C" int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
+                                const he_hist_job *jobs, uint32_t n_jobs, uint32_t *chunk_out,
+                                uint32_t *split_out, float *ms_out, hipStream_t stream) {
+  if (!key || !jobs || n_jobs == 0) return fail(HE_ERR_ARG, "need a key and at least one job");
+  static const uint32_t chunks[] = {16, 32, 64, 128, 256, 512};
+  hipEvent_t e0, e1;
+  HE_TRY_HIP(hipEventCreate(&e0));
+  HE_TRY_HIP(hipEventCreate(&e1));
+  TuneVal best{64, 2, 1e30f};
+  int rc = HE_OK;
+  for (uint32_t split : {2u, 1u}) {
+    for (uint32_t c : chunks) {
+      rc = hist_run(key, ct, rows, ct_form, jobs, n_jobs, c, split, stream);  // warm-up, sizes workspace
+      if (rc) break;
+      HE_TRY_HIP(hipEventRecord(e0, stream));
+      for (int r = 0; r < 2 && !rc; ++r) rc = hist_run(key, ct, rows, ct_form, jobs, n_jobs, c, split, stream);
+      if (rc) break;
+      HE_TRY_HIP(hipEventRecord(e1, stream));
+      HE_TRY_HIP(hipEventSynchronize(e1));
+      float ms = 0;
+      HE_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+      ms /= 2;
+      if (ms < best.ms) best = TuneVal{c, split, ms};
+    }
+    if (rc) break;
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(key, jobs, n_jobs)] = best;
+  }
+  if (chunk_out) *chunk_out = best.chunk;
+  if (split_out) *split_out = best.split;
+  if (ms_out) *ms_out = best.ms;
+  return HE_OK;
+}
+
+// ------------------------------------------------------------ captured plans
+struct he_hist_plan {
+  const he_key *key = nullptr;
+  HistLayout lay;
+  void *ws = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+extern "C" void he_hist_plan_free(he_hist_plan *plan) {
+  if (!plan) return;
+  if (plan->exec) hipGraphExecDestroy(plan->exec);
+  if (plan->graph) hipGraphDestroy(plan->graph);
+  if (plan->ws) hipFree(plan->ws);
+  delete plan;
+}
+
+extern "C" int he_hist_plan_create(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
+                                   const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk, uint32_t split,
+                                   he_hist_plan **out) {
+  if (!out) return fail(HE_ERR_ARG, "null out");
+  if (!key || !jobs || n_jobs == 0) return fail(HE_ERR_ARG, "need a key and at least one job");
+  if (chunk == 0) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(key, jobs, n_jobs));
+    chunk = it != g_tune.end() ? it->second.chunk : 64;
+    if (split == 0) split = it != g_tune.end() ? it->second.split : 2;
+  }
+  if (split == 0) split = 2;
+  he_hist_plan *p = new (std::nothrow) he_hist_plan();
+  if (!p) return fail(HE_ERR_OOM, "out of host memory");
+  p->key = key;
+  int rc = plan_layout(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, p->lay);
+  if (rc) {
+    delete p;
+    return rc;
+  }
+  if (hipMalloc(&p->ws, std::max<size_t>(p->lay.bytes, 256)) != hipSuccess) {
+    hipGetLastError();
+    delete p;
+    return fail(HE_ERR_OOM, "plan workspace allocation of " + std::to_string(p->lay.bytes) + " bytes failed");
+  }
+  // resident block counts are queried before capture (occupancy calls are
+  // not stream work, but keep capture free of anything but launches)
+  (void)he::resident_blocks(kp_of(key), 3);
+  hipStream_t cs;
+  if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
+    he_hist_plan_free(p);
+    return fail(HE_ERR_DEVICE, "stream creation failed");
+  }
+  hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+  if (e == hipSuccess) {
+    rc = enqueue_hist(key, ct, rows, p->lay, (char *)p->ws, cs);
+    hipError_t e2 = hipStreamEndCapture(cs, &p->graph);
+    if (rc == HE_OK && e2 != hipSuccess) rc = fail(HE_ERR_DEVICE, std::string("capture: ") + hipGetErrorString(e2));
+  } else {
+    rc = fail(HE_ERR_DEVICE, std::string("begin capture: ") + hipGetErrorString(e));
+  }
+  hipStreamDestroy(cs);
+  if (rc == HE_OK) {
+    e = hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) rc = fail(HE_ERR_DEVICE, std::string("instantiate: ") + hipGetErrorString(e));
+  }
+  if (rc != HE_OK) {
+    he_hist_plan_free(p);
+    return rc;
+  }
+  *out = p;
+  return HE_OK;
+}
+
+extern "C" int he_hist_plan_launch(he_hist_plan *plan, hipStream_t stream) {
+  if (!plan || !plan->exec) return fail(HE_ERR_ARG, "null plan");
+  HE_TRY_HIP(hipGraphLaunch(plan->exec, stream));
   return HE_OK;
 }
 

@@ -79,6 +79,7 @@ struct HistWs {
   uint32_t *partials;                              // [items_cap][2][S]
   uint64_t total_fb, total_f, total_blocks, items_cap;
   uint32_t chunk;                                  // samples per item
+  uint32_t split;                                  // groups per (item, slot): 1 or 2
 };
 
 constexpr int kWindowBits = 5;     // exponent window width (see mont.hpp)
@@ -102,6 +103,9 @@ hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count,
                       uint32_t *tab, uint32_t grid, hipStream_t s);
 hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *host_jobs,
                        const HistWs &ws, uint32_t chunk_grid, hipStream_t s);
+// Work items are chunks of `chunk` samples of one (feature, bin); with
+// split 2 one wave takes one item (two groups per slot, halves combined),
+// with split 1 one wave takes two items (one group per slot).
 hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_probe_mul(uint64_t iters, uint32_t grid, uint32_t *sink, hipStream_t s);
 

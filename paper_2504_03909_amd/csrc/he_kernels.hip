@@ -536,9 +536,11 @@ __global__ __launch_bounds__(256) void k_hist_scatter(HistWs ws) {
   }
 }
 
-// Product of the ciphertexts of one item (chunk), one item per wave: groups
-// 0/1 take slot g/h of the first half of the chunk, groups 2/3 of the second
-// half; the halves are combined at the end.  Output in Montgomery form.
+// Product of the ciphertexts of one item (chunk) per (item, slot).  With
+// split 2 a wave takes one item: groups 0/1 take slot g/h of the first half
+// of the chunk, groups 2/3 of the second half, and the halves are combined at
+// the end.  With split 1 a wave takes two items, one group per (item, slot).
+// Output in Montgomery form.
 template <int KP>
 __global__ __launch_bounds__(kBlockThreads) void k_hist_chunk(DKey key, const uint32_t *__restrict__ ctm,
                                                              HistWs ws) {
@@ -549,41 +551,64 @@ __global__ __launch_bounds__(kBlockThreads) void k_hist_chunk(DKey key, const ui
   uint32_t *lds = lds_all + (wrow + g) * S;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  const uint32_t slot = g & 1u, half = g >> 1;
+  const uint32_t slot = g & 1u, sub = g >> 1;
+  const bool split = ws.split == 2;
   const Mod<K> M = load_mod<K>(key.n2.N, key.n2.ninv);
   uint32_t one[K];
   ld<K>(one, key.n2.R1);
   const uint64_t n_items = *ws.n_items;
-  for (uint64_t it = gw; it < n_items; it += nw) {
-    const HistItem item = ws.items[it];
-    const uint32_t len_lo = (item.len + 1) >> 1, len_hi = item.len >> 1;
-    const uint32_t my_len = half ? len_hi : len_lo;
-    const uint32_t *pp = ws.perm + item.start + (half ? len_lo : 0u);
-    uint32_t acc[K], b[K];
-    if (my_len) {
-      ld<K>(acc, ctm + ((uint64_t)pp[0] * 2 + slot) * S);
+  const uint64_t per_wave = split ? 1 : 2;
+  for (uint64_t w0 = gw * per_wave; w0 < n_items; w0 += nw * per_wave) {
+    // this group's sample run and the wave-wide trip count
+    uint64_t start;
+    uint32_t my_len, trip;
+    uint64_t it;
+    if (split) {
+      it = w0;
+      const HistItem item = ws.items[it];
+      const uint32_t len_lo = (item.len + 1) >> 1;
+      my_len = sub ? item.len >> 1 : len_lo;
+      start = item.start + (sub ? len_lo : 0u);
+      trip = len_lo;
     } else {
-      copy(acc, one);
+      const HistItem a = ws.items[w0];
+      const bool has_b = w0 + 1 < n_items;
+      const HistItem b = ws.items[has_b ? w0 + 1 : w0];
+      const uint32_t len_b = has_b ? b.len : 0u;
+      it = w0 + sub;
+      my_len = sub ? len_b : a.len;
+      start = sub ? b.start : a.start;
+      trip = max(a.len, len_b);
     }
-    if (len_lo > 1) ld<K>(b, ctm + ((uint64_t)pp[min(1u, my_len ? my_len - 1 : 0u)] * 2 + slot) * S);
+    const uint32_t *pp = ws.perm + start;
+    uint32_t acc[K], b[K];
+    if (my_len)
+      ld<K>(acc, ctm + ((uint64_t)pp[0] * 2 + slot) * S);
+    else
+      copy(acc, one);
+    const uint32_t last = my_len ? my_len - 1 : 0u;
+    if (trip > 1) ld<K>(b, ctm + ((uint64_t)pp[min(1u, last)] * 2 + slot) * S);
 #pragma unroll 1
-    for (uint32_t k = 1; k < len_lo; ++k) {
+    for (uint32_t k = 1; k < trip; ++k) {
       uint32_t nb[K];
-      const uint32_t kn = min(k + 1, my_len ? my_len - 1 : 0u);
-      if (k + 1 < len_lo) ld<K>(nb, ctm + ((uint64_t)pp[kn] * 2 + slot) * S);
+      if (k + 1 < trip) ld<K>(nb, ctm + ((uint64_t)pp[min(k + 1, last)] * 2 + slot) * S);
       uint32_t t[K];
       mont_mul<K>(t, acc, b, M, lds);
       select(acc, k < my_len, t, acc);
-      if (k + 1 < len_lo) copy(b, nb);
+      if (k + 1 < trip) copy(b, nb);
     }
-    // combine the two halves
-    st<K>(lds, acc);
-    __builtin_amdgcn_wave_barrier();
-    uint32_t other[K];
-    ld<K>(other, lds_all + (wrow + (g ^ 2u)) * S);
-    __builtin_amdgcn_wave_barrier();
-    mont_mul<K>(acc, acc, other, M, lds);
-    if (half == 0) st<K>(ws.partials + (it * 2 + slot) * S, acc);
+    if (split) {
+      // combine the two halves
+      st<K>(lds, acc);
+      __builtin_amdgcn_wave_barrier();
+      uint32_t other[K];
+      ld<K>(other, lds_all + (wrow + (g ^ 2u)) * S);
+      __builtin_amdgcn_wave_barrier();
+      mont_mul<K>(acc, acc, other, M, lds);
+      if (sub == 0) st<K>(ws.partials + (it * 2 + slot) * S, acc);
+    } else if (it < n_items) {
+      st<K>(ws.partials + (it * 2 + slot) * S, acc);
+    }
   }
 }
 

@@ -26,6 +26,7 @@ EXPORTED = (
     "he_keygen", "he_key_import", "he_key_export", "he_key_bits", "he_key_has_private",
     "he_key_free", "he_encode", "he_encrypt", "he_encrypt_public", "he_to_mont", "he_from_mont",
     "he_hist_aggregate", "he_hist_aggregate_ex", "he_decrypt", "he_probe_int_mul", "he_last_error",
+    "he_hist_autotune", "he_hist_plan_create", "he_hist_plan_launch", "he_hist_plan_free",
 )
 
 
@@ -74,6 +75,13 @@ _hist = _sig("he_hist_aggregate_ex", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER
 _decrypt = _sig("he_decrypt", _i32, [_vp, _vp, _u64, _vp, _vp, _vp, _vp])
 _probe = _sig("he_probe_int_mul", _i32, [_u64, _u32, ctypes.POINTER(_u64), _vp])
 _last_error = _sig("he_last_error", ctypes.c_char_p, [])
+_autotune = _sig("he_hist_autotune", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32,
+                                            ctypes.POINTER(_u32), ctypes.POINTER(_u32),
+                                            ctypes.POINTER(ctypes.c_float), _vp])
+_plan_create = _sig("he_hist_plan_create", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32, _u32,
+                                                  _u32, ctypes.POINTER(_vp)])
+_plan_launch = _sig("he_hist_plan_launch", _i32, [_vp, _vp])
+_plan_free = _sig("he_hist_plan_free", None, [_vp])
 
 
 def _check(rc: int) -> None:
@@ -247,6 +255,49 @@ def hist_aggregate(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = 
     arr = (HistJob * len(jobs))(*[j.as_c(key) for j in jobs])
     _check(_hist(key.handle, _ptr(ct), rows, form, arr, len(jobs), chunk, _stream(stream)))
     return [j.hist for j in jobs]
+
+
+def hist_autotune(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = HE_FORM_CANONICAL,
+                  stream=None):
+    """Times the batched aggregation of these jobs over the candidate
+    work-item shapes; returns (chunk, split, ms) of the fastest, which the
+    library then uses for this shape class when chunk is 0."""
+    arr = (HistJob * len(jobs))(*[j.as_c(key) for j in jobs])
+    c, sp, ms = _u32(), _u32(), ctypes.c_float()
+    _check(_autotune(key.handle, _ptr(ct), ct.shape[0], form, arr, len(jobs), ctypes.byref(c),
+                     ctypes.byref(sp), ctypes.byref(ms), _stream(stream)))
+    return int(c.value), int(sp.value), float(ms.value)
+
+
+class HistPlan:
+    """A batched aggregation captured into a HIP graph; launch() replays all
+    of its kernels with one graph launch.  The tensors it was built from must
+    stay alive (the plan keeps references)."""
+
+    def __init__(self, key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = HE_FORM_CANONICAL,
+                 chunk: int = 0, split: int = 0):
+        self._keep = (key, ct, list(jobs))
+        arr = (HistJob * len(jobs))(*[j.as_c(key) for j in jobs])
+        h = _vp()
+        _check(_plan_create(key.handle, _ptr(ct), ct.shape[0], form, arr, len(jobs), chunk, split,
+                            ctypes.byref(h)))
+        self._h = h
+        self.hists = [j.hist for j in jobs]
+
+    def launch(self, stream=None):
+        _check(_plan_launch(self._h, _stream(stream)))
+        return self.hists
+
+    def close(self):
+        if self._h and self._h.value:
+            _plan_free(self._h)
+            self._h = _vp()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def decrypt(key: Key, ct: torch.Tensor, raw: bool = False, stream=None):

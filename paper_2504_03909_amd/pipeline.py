@@ -1,0 +1,80 @@
+"""Tree-level orchestration of the encrypted-histogram path on one GPU.
+
+The active party encrypts every sample's g and h once per boosting round and
+the ciphertexts stay resident in device memory (canonical form for transfer,
+Montgomery form for the histogram kernels) across all nodes of the tree; a
+passive party builds one encrypted histogram per tree node (Sec. III-B) and
+the active party decrypts them.  Every arithmetic step runs in the HIP library
+(``he``); this module only arranges buffers and calls.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass, field
+from typing import List, Optional, Sequence
+
+import torch
+
+from . import he
+
+
+@dataclass
+class Resident:
+    """Encrypted gradients of one round, resident on the device."""
+    key: he.Key
+    ct: torch.Tensor    # int32 [M, 2, 2L], canonical (what would be sent)
+    ctm: torch.Tensor   # int32 [M, 2, 2L], Montgomery form (what the kernels read)
+
+    @property
+    def rows(self) -> int:
+        return self.ct.shape[0]
+
+
+def encrypt_gradients(key: he.Key, grads: torch.Tensor, r_seed: int, frac_bits: int = 32,
+                      stream=None) -> Resident:
+    """grads: float64 [M, 2] on the device -> resident ciphertexts."""
+    M = grads.shape[0]
+    m = he.encode(grads.reshape(-1).contiguous(), frac_bits, stream=stream)
+    ct = he.encrypt(key, m, seed=r_seed, stream=stream).view(M, 2, 2 * key.limbs)
+    ctm = he.to_mont(key, ct, stream=stream)
+    return Resident(key, ct, ctm)
+
+
+def node_job(sample_idx: torch.Tensor, bins: torch.Tensor, n_bins: int) -> he.Job:
+    return he.Job(sample_idx, bins, n_bins)
+
+
+@dataclass
+class TreeRun:
+    hists: List[List[torch.Tensor]] = field(default_factory=list)   # [level][node]
+    plans: List[he.HistPlan] = field(default_factory=list)
+
+
+def aggregate_levels(res: Resident, levels: Sequence[Sequence[torch.Tensor]], bins: torch.Tensor,
+                     n_bins: int, mode: str = "per_node", chunk: int = 0, stream=None) -> TreeRun:
+    """Encrypted histograms of every node, level by level.
+
+    mode "per_node": one he_hist_aggregate call (one job) per node -- the
+    plain one-job-per-launch path.  mode "per_level": all nodes of a level in
+    one batched call.  mode "per_level_graph": all nodes of a level in one
+    captured plan, replayed with a single graph launch."""
+    run = TreeRun()
+    for lvl in levels:
+        jobs = [node_job(idx, bins, n_bins) for idx in lvl]
+        if mode == "per_node":
+            for j in jobs:
+                he.hist_aggregate(res.key, res.ctm, [j], form=he.HE_FORM_MONT, chunk=chunk, stream=stream)
+        elif mode == "per_level":
+            he.hist_aggregate(res.key, res.ctm, jobs, form=he.HE_FORM_MONT, chunk=chunk, stream=stream)
+        elif mode == "per_level_graph":
+            plan = he.HistPlan(res.key, res.ctm, jobs, form=he.HE_FORM_MONT, chunk=chunk)
+            plan.launch(stream)
+            run.plans.append(plan)
+        else:
+            raise ValueError(mode)
+        run.hists.append([j.hist for j in jobs])
+    return run
+
+
+def decrypt_levels(key: he.Key, run: TreeRun, stream=None) -> List[List[torch.Tensor]]:
+    """Signed int64 histograms [F, B, 2] of every node."""
+    return [[he.decrypt(key, h, stream=stream)[0] for h in lvl] for lvl in run.hists]

@@ -104,22 +104,22 @@ def random_units(n: int, count: int, rng: np.random.Generator) -> List[int]:
     return out
 
 
-@dataclass
-class HistJobShape:
-    n_samples: int
-    n_features: int
-    n_bins: int
+def bins_tables(n_rows: int, n_features: int, bin_choices: Sequence[int], rng: np.random.Generator,
+                s: float = 1.1):
+    """One Zipf(s) bin table per bin count: {B: uint8 [n_features, n_rows]}."""
+    return {int(b): bins_zipf(n_features, n_rows, int(b), rng, s) for b in bin_choices}
 
 
 def batched_jobs(n_jobs: int, rng: np.random.Generator, pool_rows: int,
                  min_samples: int = 1_000, max_samples: int = 200_000,
                  min_features: int = 8, max_features: int = 128,
-                 bin_choices: Sequence[int] = (16, 64, 256)):
-    """Uneven tree-node histogram jobs over a pool of ``pool_rows`` encrypted
-    samples: |S| log-uniform in [min_samples, max_samples], F uniform on
-    {min_features..max_features}, B uniform over ``bin_choices``; each job
-    has a seeded sorted subset of the pool and its own Zipf(1.1) bins
-    (uint8 [F, pool_rows], indexed by pool row)."""
+                 bin_choices: Sequence[int] = (16, 64, 256)) -> List[dict]:
+    """Shapes of uneven tree-node histogram jobs over a pool of ``pool_rows``
+    encrypted samples: |S| log-uniform in [min_samples, max_samples] (capped
+    at the pool), F uniform on {min_features..max_features}, B uniform over
+    ``bin_choices``, a seeded sorted subset of the pool as the node's samples,
+    and a seeded window [f0, f0 + F) of the rows of the Zipf table for B (see
+    ``bins_tables``, built with max_features rows) as the job's features."""
     jobs = []
     for _ in range(n_jobs):
         m = int(round(math.exp(rng.uniform(math.log(min_samples), math.log(max_samples)))))
@@ -127,8 +127,8 @@ def batched_jobs(n_jobs: int, rng: np.random.Generator, pool_rows: int,
         f = int(rng.integers(min_features, max_features + 1))
         b = int(rng.choice(np.asarray(bin_choices)))
         idx = np.sort(rng.choice(pool_rows, size=m, replace=False)).astype(np.uint32)
-        bins = bins_zipf(f, pool_rows, b, rng)
-        jobs.append(dict(sample_idx=idx, bins=bins, n_features=f, n_bins=b))
+        f0 = int(rng.integers(0, max_features - f + 1))
+        jobs.append(dict(sample_idx=idx, n_features=f, n_bins=b, f0=f0))
     return jobs
 
 

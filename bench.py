@@ -149,6 +149,8 @@ def main():
     ap.add_argument("--workload", default="pass", choices=("pass", "tree", "batched", "served"))
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}); the multi-GPU "
@@ -161,6 +163,15 @@ def main():
     from synth import workloads as W
 
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = args.calibrate_copy << 18  # int32 elements
+        src = torch.ones(n, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": 4 * n}), flush=True)
+        return
     if args.workload != "pass":
         line = {"tree": bench_tree, "batched": bench_batched, "served": bench_served}[args.workload](args)
         print(json.dumps(line), flush=True)
@@ -280,13 +291,16 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-def _timed(fn):
+def _timed(fn, label=""):
     import torch
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     out = fn()
     torch.cuda.synchronize()
-    return out, time.perf_counter() - t0
+    dt = time.perf_counter() - t0
+    if label:
+        print(f"[bench] {label}: {dt:.3f} s", file=sys.stderr, flush=True)
+    return out, dt
 
 
 def bench_tree(args):
@@ -303,15 +317,15 @@ def bench_tree(args):
     bins = torch.from_numpy(W.bins_zipf(Jt, Mt, Kt, st[2])).cuda()
     levels = [[torch.from_numpy(n.view(np.int32)).cuda() for n in lvl] for lvl in W.tree_levels(Mt, depth, st[4])]
     pipeline.encrypt_gradients(key, g[:1000].contiguous(), R_SEED)  # warm-up
-    res, t_enc = _timed(lambda: pipeline.encrypt_gradients(key, g, R_SEED))
+    res, t_enc = _timed(lambda: pipeline.encrypt_gradients(key, g, R_SEED), "tree encrypt")
     pipeline.aggregate_levels(res, levels[:1], bins, Kt, mode="per_node")  # warm-up / workspace
-    run_plain, t_plain = _timed(lambda: pipeline.aggregate_levels(res, levels, bins, Kt, mode="per_node"))
-    run_batched, t_batched = _timed(lambda: pipeline.aggregate_levels(res, levels, bins, Kt, mode="per_level"))
+    run_plain, t_plain = _timed(lambda: pipeline.aggregate_levels(res, levels, bins, Kt, mode="per_node"), "tree per node")
+    run_batched, t_batched = _timed(lambda: pipeline.aggregate_levels(res, levels, bins, Kt, mode="per_level"), "tree per level")
     plans = pipeline.aggregate_levels(res, levels, bins, Kt, mode="per_level_graph")
     torch.cuda.synchronize()
-    _, t_graph = _timed(lambda: [p.launch() for p in plans.plans])
+    _, t_graph = _timed(lambda: [p.launch() for p in plans.plans], "tree graphs")
     same = all(torch.equal(a, b) for la, lb in zip(run_plain.hists, plans.hists) for a, b in zip(la, lb))
-    _, t_dec = _timed(lambda: pipeline.decrypt_levels(key, run_plain))
+    _, t_dec = _timed(lambda: pipeline.decrypt_levels(key, run_plain), "tree decrypt")
     contrib = 2 * Jt * sum(int(n.numel()) for lvl in levels for n in lvl)
     n_dec = 63 * Jt * Kt * 2
     return {
@@ -404,7 +418,10 @@ def bench_served(args):
     def run(rate, n, policy, seed):
         tr = serve.build_trace(np.random.default_rng(seed), n, rate, setups, share)
         be = serve.backend_for(setups, n_streams=4 if policy == "continuous" else 1)
-        return serve.Server(be, budget, max_inflight=8, policy=policy).run(tr, time_limit=900)
+        st = serve.Server(be, budget, max_inflight=8, policy=policy).run(tr, time_limit=900)
+        print(f"[bench] served rate={rate:g} n={n} {policy}: {st['makespan_s']} s, p99 {st['p99_ms']} ms",
+              file=sys.stderr, flush=True)
+        return st
 
     run(1000.0, 16, "continuous", 99)  # warm-up: workspaces and kernels
     out = {"metric": "p50/p99 request latency and throughput, 2048-bit (90%) + 1024-bit (10%) keys",

@@ -44,8 +44,8 @@ def test_served_results_equal_alone():
             assert torch.equal(solo, r.result), (r.rid, r.kind)
     # one decrypt result against the oracle: it decrypts resident ciphertexts
     # of known plaintexts (the encoded gradients)
-    d = next(r for r in trace if r.kind == "decrypt" and r.key_id == "k1024")
-    st = setups["k1024"]
+    d = next(r for r in trace if r.kind == "decrypt")
+    st = setups[d.key_id]
     flat_ct = st["ct"].view(-1, st["ct"].shape[-1])
     start = (d.payload["ct"].data_ptr() - flat_ct.data_ptr()) // (4 * flat_ct.shape[-1])
     mh = st["m"].cpu().numpy()

@@ -417,7 +417,8 @@ def bench_served(args):
 
     def run(rate, n, policy, seed):
         tr = serve.build_trace(np.random.default_rng(seed), n, rate, setups, share)
-        be = serve.backend_for(setups, n_streams=4 if policy == "continuous" else 1)
+        be = (serve.backend_for(setups, n_streams=4, enc_slice=16384) if policy == "continuous"
+              else serve.backend_for(setups, n_streams=1))
         st = serve.Server(be, budget, max_inflight=8, policy=policy).run(tr, time_limit=900)
         print(f"[bench] served rate={rate:g} n={n} {policy}: {st['makespan_s']} s, p99 {st['p99_ms']} ms",
               file=sys.stderr, flush=True)

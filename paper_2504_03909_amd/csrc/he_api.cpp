@@ -166,8 +166,8 @@ int ensure(Buf &b, size_t bytes, hipStream_t s) {
   return HE_OK;
 }
 
-uint32_t persistent_grid(int KP, int kind, uint64_t work_blocks) {
-  const uint32_t res = he::resident_blocks(KP, kind);
+uint32_t persistent_grid(int KP, int kind, uint64_t work_blocks, int G = 16) {
+  const uint32_t res = he::resident_blocks(KP, kind, G);
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(res, work_blocks));
 }
 
@@ -180,13 +180,15 @@ int encrypt_impl(const he_key *key, const int64_t *m, uint64_t count, const uint
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
   if (key->priv && !force_pub) {
-    const uint32_t grid = persistent_grid(KP, 0, (2 * ((count + 3) / 4) + 3) / 4);
-    int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 0), stream);
+    const int G = he::pick_group(KP, 0, count);
+    const uint64_t per_wave = 64 / G;
+    const uint32_t grid = persistent_grid(KP, 0, (2 * ((count + per_wave - 1) / per_wave) + 3) / 4, G);
+    int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 0, G), stream);
     if (rc) return rc;
     rc = ensure(w->tmp, count * 2 * L * sizeof(uint32_t), stream);
     if (rc) return rc;
     HE_TRY_HIP(he::launch_enc_crt(KP, key->dk, m, count, r, r_seed, r_offset, (uint32_t *)w->tmp.p, ct,
-                                  (uint32_t *)w->tab.p, grid, stream));
+                                  (uint32_t *)w->tab.p, grid, G, stream));
   } else {
     const uint32_t grid = persistent_grid(KP, 1, ((count + 3) / 4 + 3) / 4);
     int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 1), stream);
@@ -316,13 +318,15 @@ int he_decrypt(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m
   Workspace *w = workspace(stream);
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
-  const uint32_t grid = persistent_grid(KP, 2, (2 * ((count + 3) / 4) + 3) / 4);
-  int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 2), stream);
+  const int G = he::pick_group(KP, 2, count);
+  const uint64_t per_wave = 64 / G;
+  const uint32_t grid = persistent_grid(KP, 2, (2 * ((count + per_wave - 1) / per_wave) + 3) / 4, G);
+  int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 2, G), stream);
   if (rc) return rc;
   rc = ensure(w->tmp, count * L * sizeof(uint32_t), stream);
   if (rc) return rc;
   HE_TRY_HIP(he::launch_dec(KP, key->dk, ct, count, (uint32_t *)w->tmp.p, m, raw, n_overflow,
-                            (uint32_t *)w->tab.p, grid, stream));
+                            (uint32_t *)w->tab.p, grid, G, stream));
   return HE_OK;
 }
 

@@ -84,7 +84,7 @@ struct HistWs {
 
 constexpr int kWindowBits = 5;     // exponent window width (see mont.hpp)
 constexpr int kSampleBlock = 4096;   // samples per bucketing block
-constexpr int kBlockThreads = 256;   // 4 waves, 16 groups of 16 lanes
+constexpr int kBlockThreads = 256;   // 4 waves
 
 // ---- launchers (he_kernels.hip) ------------------------------------------------
 // KP = limbs per lane of a prime: 1 for 1024-bit keys, 2 for 2048-bit keys.
@@ -92,7 +92,7 @@ hipError_t launch_encode(const double *x, uint64_t count, uint32_t frac_bits, in
                          uint32_t *n_bad, hipStream_t s);
 hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count,
                           const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *cpq,
-                          uint32_t *ct, uint32_t *tab, uint32_t grid, hipStream_t s);
+                          uint32_t *ct, uint32_t *tab, uint32_t grid, int G, hipStream_t s);
 hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
                           const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *ct,
                           uint32_t *tab, uint32_t grid, hipStream_t s);
@@ -100,7 +100,7 @@ hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64
                                uint32_t *out, bool to_mont, hipStream_t s);
 hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count,
                       uint32_t *mpq, int64_t *m, uint32_t *raw, uint32_t *n_overflow,
-                      uint32_t *tab, uint32_t grid, hipStream_t s);
+                      uint32_t *tab, uint32_t grid, int G, hipStream_t s);
 hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *host_jobs,
                        const HistWs &ws, uint32_t chunk_grid, hipStream_t s);
 // Work items are chunks of `chunk` samples of one (feature, bin); with
@@ -110,9 +110,12 @@ hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_probe_mul(uint64_t iters, uint32_t grid, uint32_t *sink, hipStream_t s);
 
 // Resident blocks of 256 threads the device holds for each persistent kernel
-// (occupancy x compute units), by kind: 0 enc_crt, 1 enc_pub, 2 dec, 3 hist chunk.
-uint32_t resident_blocks(int KP, int kind);
-// Window-table scratch bytes per resident block for the given kernel kind.
-uint64_t table_bytes_per_block(int KP, int kind);
+// (occupancy x compute units), by kind: 0 enc_crt, 1 enc_pub, 2 dec, 3 hist
+// chunk; G = lanes per integer of the kernel variant (kinds 0 and 2).
+uint32_t resident_blocks(int KP, int kind, int G = 16);
+// Window-table scratch bytes per resident block of the given kernel kind.
+uint64_t table_bytes_per_block(int KP, int kind, int G = 16);
+// Lanes per integer for a CRT exponentiation kernel over `count` ciphertexts.
+int pick_group(int KP, int kind, uint64_t count);
 
 }  // namespace he

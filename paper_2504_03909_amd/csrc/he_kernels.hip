@@ -18,28 +18,28 @@ static_assert(kWindow == kWindowBits, "window width mismatch");
 
 // ------------------------------------------------------------- small helpers
 // Limb t of a little-endian buffer of `nl` limbs, zero past the end.
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void ld_part(uint32_t (&x)[K], const uint32_t *p, int nl) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const int t = (int)glane() * K + j;
+    const int t = (int)glane<G>() * K + j;
     x[j] = t < nl ? p[t] : 0u;
   }
 }
 
 // x = v mod N for a signed 64-bit v (|v| < N).
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void signed_mod(uint32_t (&x)[K], int64_t v, const uint32_t (&N)[K]) {
   const uint64_t mag = v < 0 ? (uint64_t)0 - (uint64_t)v : (uint64_t)v;
   uint32_t a[K];
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const int t = (int)glane() * K + j;
+    const int t = (int)glane<G>() * K + j;
     a[j] = t == 0 ? (uint32_t)mag : (t == 1 ? (uint32_t)(mag >> 32) : 0u);
   }
   if (v < 0) {
     uint32_t d[K];
-    sub_plain<K>(d, N, a);
+    sub_plain<K, G>(d, N, a);
     copy(x, d);
   } else {
     copy(x, a);
@@ -47,22 +47,22 @@ __device__ __forceinline__ void signed_mod(uint32_t (&x)[K], int64_t v, const ui
 }
 
 // x += 1 (no reduction).
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void add_one(uint32_t (&x)[K]) {
   uint32_t one[K];
-  set_small(one, 1u);
-  add_plain<K>(x, x, one);
+  set_small<K, G>(one, 1u);
+  add_plain<K, G>(x, x, one);
 }
 
-// Limbs [first, first + 16K) of the seeded stream integer
+// Limbs [first, first + G K) of the seeded stream integer
 // X = sum_j w(seed, base + j) 2^(64 j), each lane taking its K limbs;
 // limbs at or past `nl` are zero.
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void seeded_limbs(uint32_t (&x)[K], uint64_t seed, uint64_t base,
                                              int first, int nl) {
 #pragma unroll
   for (int j = 0; j < K; ++j) {
-    const int t = first + (int)glane() * K + j;
+    const int t = first + (int)glane<G>() * K + j;
     const uint64_t w = splitmix64(seed, base + (uint64_t)(t >> 1));
     x[j] = t < nl ? (uint32_t)((t & 1) ? (w >> 32) : w) : 0u;
   }
@@ -89,83 +89,94 @@ __global__ void k_encode(const double *__restrict__ x, uint64_t count, uint32_t 
 // ----------------------------------------------------------- CRT encryption
 // Phase A: for each (ciphertext i, prime P) compute
 //   c_P = (1 + m n) r^n mod P^2,  r^n mod P^2 = (r^(Q mod (P-1)) mod P)^P mod P^2.
-// Work unit = (prime, 4 consecutive ciphertexts) so that the exponent is the
-// same for the whole wave.  Output cpq[i][P] (S_P2 limbs, canonical).
-template <int KP>
+// Work unit = (prime, 64/G consecutive ciphertexts) so that the exponent is
+// the same for the whole wave.  Output cpq[i][P] (S_P2 limbs, canonical).
+// G = lanes per integer (kEncGroup).
+template <int KP, int G>
 __global__ __launch_bounds__(kBlockThreads) void k_enc_crt_a(
     DKey key, const int64_t *__restrict__ m, uint64_t count, const uint32_t *__restrict__ r,
     uint64_t seed, uint64_t roff, uint32_t *__restrict__ cpq, uint32_t *__restrict__ tabs) {
-  constexpr int KP2 = 2 * KP, SP = 16 * KP, SP2 = 32 * KP, L = SP2;
-  __shared__ __align__(16) uint32_t lds_all[16 * SP2];
-  const uint32_t g = group_in_wave();
-  uint32_t *lds = lds_all + (wave_in_block() * 4 + g) * SP2;
+  constexpr int SP = 16 * KP, SP2 = 32 * KP, L = SP2;
+  constexpr int K1 = SP / G, K2 = SP2 / G;  // limbs per lane mod P and mod P^2
+  constexpr int NG = 64 / G, GB = kBlockThreads / G;
+  __shared__ __align__(16) uint32_t lds_all[GB * SP2];
+  const uint32_t g = (threadIdx.x & 63u) / G;
+  uint32_t *lds = lds_all + (threadIdx.x / G) * SP2;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * 4 + g) * (uint64_t)(kTable * SP2);
-  const uint64_t nquads = 2 * ((count + 3) / 4);
+  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * SP2);
+  const uint64_t nunits = 2 * ((count + NG - 1) / NG);
   const uint64_t W = (uint64_t)SP + 1;  // stream words per r
 
-  for (uint64_t qd = gw; qd < nquads; qd += nw) {
+  for (uint64_t qd = gw; qd < nunits; qd += nw) {
     const int which = (int)(qd & 1);
     const DPrime &P = key.pr[which];
-    uint64_t i = (qd >> 1) * 4 + g;
+    uint64_t i = (qd >> 1) * NG + g;
     const bool valid = i < count;
     if (!valid) i = count - 1;
-    const Mod<KP> Mp = load_mod<KP>(P.P.N, P.P.ninv);
-
-    // x = Montgomery form of r mod P
-    uint32_t x[KP], t0[KP], t1[KP], c[KP];
-    if (r) {
-      ld<KP>(t0, r + i * L);
-      ld<KP>(t1, r + i * L + SP);
-      ld<KP>(c, P.P.R2);
-      mont_mul<KP>(t0, t0, c, Mp, lds);
-      ld<KP>(c, P.P.R3);
-      mont_mul<KP>(t1, t1, c, Mp, lds);
-      add_mod<KP>(x, t0, t1, Mp);
-    } else {
-      const uint64_t base = (roff + i) * W;
-      uint32_t t2[KP];
-      seeded_limbs<KP>(t0, seed, base, 0, 2 * SP + 2);
-      seeded_limbs<KP>(t1, seed, base, SP, 2 * SP + 2);
-      seeded_limbs<KP>(t2, seed, base, 2 * SP, 2 * SP + 2);
-      ld<KP>(c, P.P.R2);
-      mont_mul<KP>(t0, t0, c, Mp, lds);
-      ld<KP>(c, P.P.R3);
-      mont_mul<KP>(t1, t1, c, Mp, lds);
-      ld<KP>(c, P.P.R4);
-      mont_mul<KP>(t2, t2, c, Mp, lds);
-      add_mod<KP>(x, t0, t1, Mp);
-      add_mod<KP>(x, x, t2, Mp);
+    uint32_t w[K2];
+    {
+      const Mod<K1> Mp = load_mod<K1, G>(P.P.N, P.P.ninv);
+      // x = Montgomery form of r mod P
+      uint32_t x[K1], t0[K1], t1[K1], c[K1];
+      if (r) {
+        ld<K1, G>(t0, r + i * L);
+        ld<K1, G>(t1, r + i * L + SP);
+        ld<K1, G>(c, P.P.R2);
+        mont_mul<K1, G>(t0, t0, c, Mp, lds);
+        ld<K1, G>(c, P.P.R3);
+        mont_mul<K1, G>(t1, t1, c, Mp, lds);
+        add_mod<K1, G>(x, t0, t1, Mp);
+      } else {
+        const uint64_t base = (roff + i) * W;
+        uint32_t t2[K1];
+        seeded_limbs<K1, G>(t0, seed, base, 0, 2 * SP + 2);
+        seeded_limbs<K1, G>(t1, seed, base, SP, 2 * SP + 2);
+        seeded_limbs<K1, G>(t2, seed, base, 2 * SP, 2 * SP + 2);
+        ld<K1, G>(c, P.P.R2);
+        mont_mul<K1, G>(t0, t0, c, Mp, lds);
+        ld<K1, G>(c, P.P.R3);
+        mont_mul<K1, G>(t1, t1, c, Mp, lds);
+        ld<K1, G>(c, P.P.R4);
+        mont_mul<K1, G>(t2, t2, c, Mp, lds);
+        add_mod<K1, G>(x, t0, t1, Mp);
+        add_mod<K1, G>(x, x, t2, Mp);
+      }
+      // t = r^(Q mod (P-1)) mod P, canonical
+      ld<K1, G>(c, P.P.R1);
+      mont_pow<K1, G>(x, P.e_enc.e, P.e_enc.nwin, tab, c, Mp, lds);
+      set_small<K1, G>(c, 1u);
+      mont_mul<K1, G>(x, x, c, Mp, lds);
+      relayout<K1, K2, G>(w, x, lds);
     }
-    // t = r^(Q mod (P-1)) mod P, canonical
-    ld<KP>(c, P.P.R1);
-    mont_pow<KP>(x, P.e_enc.e, P.e_enc.nwin, tab, c, Mp, lds);
-    set_small(c, 1u);
-    mont_mul<KP>(x, x, c, Mp, lds);
-    // u = (m mod P) Q mod P
-    const int64_t mv = m[i];
-    uint32_t u[KP];
-    signed_mod<KP>(u, mv, Mp.n);
-    ld<KP>(c, P.QR_P);
-    mont_mul<KP>(u, u, c, Mp, lds);
-
-    // lift to P^2: omega = t^P mod P^2 (Montgomery form)
-    const Mod<KP2> M2 = load_mod<KP2>(P.P2.N, P.P2.ninv);
-    uint32_t w[KP2], c2[KP2], f[KP2];
-    relayout<KP, KP2>(w, x, lds);
-    ld<KP2>(c2, P.P2.R2);
-    mont_mul<KP2>(w, w, c2, M2, lds);
-    ld<KP2>(c2, P.P2.R1);
-    mont_pow<KP2>(w, P.e_lift.e, P.e_lift.nwin, tab, c2, M2, lds);
-    // f = 1 + m n mod P^2 = 1 + P (m Q mod P)
-    relayout<KP, KP2>(f, u, lds);
-    ld<KP2>(c2, P.PR_P2);
-    mont_mul<KP2>(f, f, c2, M2, lds);
-    add_one<KP2>(f);
+    const Mod<K2> M2 = load_mod<K2, G>(P.P2.N, P.P2.ninv);
+    {
+      // omega = t^P mod P^2 (Montgomery form)
+      uint32_t c2[K2];
+      ld<K2, G>(c2, P.P2.R2);
+      mont_mul<K2, G>(w, w, c2, M2, lds);
+      ld<K2, G>(c2, P.P2.R1);
+      mont_pow<K2, G>(w, P.e_lift.e, P.e_lift.nwin, tab, c2, M2, lds);
+    }
+    uint32_t f[K2];
+    {
+      // u = (m mod P) Q mod P, then f = 1 + m n mod P^2 = 1 + P u
+      const Mod<K1> Mp = load_mod<K1, G>(P.P.N, P.P.ninv);
+      uint32_t u[K1], c[K1];
+      signed_mod<K1, G>(u, m[i], Mp.n);
+      ld<K1, G>(c, P.QR_P);
+      mont_mul<K1, G>(u, u, c, Mp, lds);
+      relayout<K1, K2, G>(f, u, lds);
+    }
+    {
+      uint32_t c2[K2];
+      ld<K2, G>(c2, P.PR_P2);
+      mont_mul<K2, G>(f, f, c2, M2, lds);
+      add_one<K2, G>(f);
+    }
     // c_P = omega f mod P^2 (the Montgomery factor of omega cancels)
-    mont_mul<KP2>(w, w, f, M2, lds);
-    if (valid) st<KP2>(cpq + (i * 2 + which) * SP2, w);
+    mont_mul<K2, G>(w, w, f, M2, lds);
+    if (valid) st<K2, G>(cpq + (i * 2 + which) * SP2, w);
   }
 }
 
@@ -265,52 +276,57 @@ __global__ __launch_bounds__(kBlockThreads) void k_mont_convert(DKey key, const 
 // -------------------------------------------------------------- decryption
 // Phase A: for (ciphertext i, prime P):
 //   x = c^(P-1) mod P^2,  m_P = ((x - 1) / P) h_P mod P.
-template <int KP>
+// Work unit = (prime, 64/G consecutive ciphertexts); G = lanes per integer.
+template <int KP, int G>
 __global__ __launch_bounds__(kBlockThreads) void k_dec_a(DKey key, const uint32_t *__restrict__ ct,
                                                         uint64_t count, uint32_t *__restrict__ mpq,
                                                         uint32_t *__restrict__ tabs) {
-  constexpr int KP2 = 2 * KP, SP = 16 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
-  __shared__ __align__(16) uint32_t lds_all[16 * SP2];
-  const uint32_t g = group_in_wave();
-  uint32_t *lds = lds_all + (wave_in_block() * 4 + g) * SP2;
+  constexpr int SP = 16 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
+  constexpr int K1 = SP / G, K2 = SP2 / G, NG = 64 / G, GB = kBlockThreads / G;
+  __shared__ __align__(16) uint32_t lds_all[GB * SP2];
+  const uint32_t g = (threadIdx.x & 63u) / G;
+  uint32_t *lds = lds_all + (threadIdx.x / G) * SP2;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * 4 + g) * (uint64_t)(kTable * SP2);
-  const uint64_t nquads = 2 * ((count + 3) / 4);
-  for (uint64_t qd = gw; qd < nquads; qd += nw) {
+  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * SP2);
+  const uint64_t nunits = 2 * ((count + NG - 1) / NG);
+  for (uint64_t qd = gw; qd < nunits; qd += nw) {
     const int which = (int)(qd & 1);
     const DPrime &P = key.pr[which];
-    uint64_t i = (qd >> 1) * 4 + g;
+    uint64_t i = (qd >> 1) * NG + g;
     const bool valid = i < count;
     if (!valid) i = count - 1;
-    const Mod<KP2> M2 = load_mod<KP2>(P.P2.N, P.P2.ninv);
-    uint32_t x[KP2], y[KP2], c[KP2];
-    // c mod P^2 in Montgomery form: c = c0 + c1 R'
-    ld<KP2>(x, ct + i * SN2);
-    ld<KP2>(y, ct + i * SN2 + SP2);
-    ld<KP2>(c, P.P2.R2);
-    mont_mul<KP2>(x, x, c, M2, lds);
-    ld<KP2>(c, P.P2.R3);
-    mont_mul<KP2>(y, y, c, M2, lds);
-    add_mod<KP2>(x, x, y, M2);
-    ld<KP2>(c, P.P2.R1);
-    mont_pow<KP2>(x, P.e_dec.e, P.e_dec.nwin, tab, c, M2, lds);
-    set_small(c, 1u);
-    mont_mul<KP2>(x, x, c, M2, lds);  // canonical, = 1 mod P
-    set_small(c, 1u);
-    sub_plain<KP2>(x, x, c);          // x - 1 = k P
-    // k = (x - 1) P^-1 mod 2^(32 S_P) (exact division)
-    uint32_t lo[KP], k[KP], pinv[KP];
-    relayout<KP2, KP>(lo, x, lds);
-    ld<KP>(pinv, P.Pinv);
-    st<KP>(lds, lo);
+    uint32_t lo[K1];
+    {
+      const Mod<K2> M2 = load_mod<K2, G>(P.P2.N, P.P2.ninv);
+      uint32_t x[K2], y[K2], c[K2];
+      // c mod P^2 in Montgomery form: c = c0 + c1 R'
+      ld<K2, G>(x, ct + i * SN2);
+      ld<K2, G>(y, ct + i * SN2 + SP2);
+      ld<K2, G>(c, P.P2.R2);
+      mont_mul<K2, G>(x, x, c, M2, lds);
+      ld<K2, G>(c, P.P2.R3);
+      mont_mul<K2, G>(y, y, c, M2, lds);
+      add_mod<K2, G>(x, x, y, M2);
+      ld<K2, G>(c, P.P2.R1);
+      mont_pow<K2, G>(x, P.e_dec.e, P.e_dec.nwin, tab, c, M2, lds);
+      set_small<K2, G>(c, 1u);
+      mont_mul<K2, G>(x, x, c, M2, lds);  // canonical, = 1 mod P
+      set_small<K2, G>(c, 1u);
+      sub_plain<K2, G>(x, x, c);          // x - 1 = k P
+      relayout<K2, K1, G>(lo, x, lds);
+    }
+    // k = (x - 1) P^-1 mod 2^(32 S_P) (exact division), m_P = k h_P mod P
+    uint32_t k[K1], pinv[K1];
+    ld<K1, G>(pinv, P.Pinv);
+    st<K1, G>(lds, lo);
     __builtin_amdgcn_wave_barrier();
-    mul_lo_lds<KP>(k, lds, pinv);
+    mul_lo_lds<K1, G>(k, lds, pinv);
     __builtin_amdgcn_wave_barrier();
-    const Mod<KP> Mp = load_mod<KP>(P.P.N, P.P.ninv);
-    ld<KP>(pinv, P.hR_P);
-    mont_mul<KP>(k, k, pinv, Mp, lds);  // m_P = k h_P mod P
-    if (valid) st<KP>(mpq + (i * 2 + which) * SP, k);
+    const Mod<K1> Mp = load_mod<K1, G>(P.P.N, P.P.ninv);
+    ld<K1, G>(pinv, P.hR_P);
+    mont_mul<K1, G>(k, k, pinv, Mp, lds);
+    if (valid) st<K1, G>(mpq + (i * 2 + which) * SP, k);
   }
 }
 
@@ -697,19 +713,26 @@ hipError_t launch_encode(const double *x, uint64_t count, uint32_t frac_bits, in
 template <int KP>
 static hipError_t enc_crt(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r,
                           uint64_t seed, uint64_t roff, uint32_t *cpq, uint32_t *ct, uint32_t *tab,
-                          uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_enc_crt_a<KP>, dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed,
-                     roff, cpq, tab);
+                          uint32_t grid, int G, hipStream_t s) {
+  if (G == 4)
+    hipLaunchKernelGGL((k_enc_crt_a<KP, 4>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff,
+                       cpq, tab);
+  else if (G == 8)
+    hipLaunchKernelGGL((k_enc_crt_a<KP, 8>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff,
+                       cpq, tab);
+  else
+    hipLaunchKernelGGL((k_enc_crt_a<KP, 16>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff,
+                       cpq, tab);
   hipLaunchKernelGGL(k_enc_crt_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k,
                      (const uint32_t *)cpq, count, ct);
   return hipGetLastError();
 }
 hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count,
                           const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *cpq,
-                          uint32_t *ct, uint32_t *tab, uint32_t grid, hipStream_t s) {
+                          uint32_t *ct, uint32_t *tab, uint32_t grid, int G, hipStream_t s) {
   if (!count) return hipSuccess;
-  return KP == 1 ? enc_crt<1>(k, m, count, r, seed, roff, cpq, ct, tab, grid, s)
-                 : enc_crt<2>(k, m, count, r, seed, roff, cpq, ct, tab, grid, s);
+  return KP == 1 ? enc_crt<1>(k, m, count, r, seed, roff, cpq, ct, tab, grid, G, s)
+                 : enc_crt<2>(k, m, count, r, seed, roff, cpq, ct, tab, grid, G, s);
 }
 
 hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
@@ -736,18 +759,23 @@ hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64
 
 template <int KP>
 static hipError_t dec(const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *mpq, int64_t *m,
-                      uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL(k_dec_a<KP>, dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
+                      uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, uint32_t grid, int G, hipStream_t s) {
+  if (G == 4)
+    hipLaunchKernelGGL((k_dec_a<KP, 4>), dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
+  else if (G == 8)
+    hipLaunchKernelGGL((k_dec_a<KP, 8>), dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
+  else
+    hipLaunchKernelGGL((k_dec_a<KP, 16>), dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
   hipLaunchKernelGGL(k_dec_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k,
                      (const uint32_t *)mpq, count, m, raw, n_overflow);
   return hipGetLastError();
 }
 hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *mpq,
                       int64_t *m, uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, uint32_t grid,
-                      hipStream_t s) {
+                      int G, hipStream_t s) {
   if (!count) return hipSuccess;
-  return KP == 1 ? dec<1>(k, ct, count, mpq, m, raw, n_overflow, tab, grid, s)
-                 : dec<2>(k, ct, count, mpq, m, raw, n_overflow, tab, grid, s);
+  return KP == 1 ? dec<1>(k, ct, count, mpq, m, raw, n_overflow, tab, grid, G, s)
+                 : dec<2>(k, ct, count, mpq, m, raw, n_overflow, tab, grid, G, s);
 }
 
 hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
@@ -798,24 +826,47 @@ static uint32_t occupancy_blocks(const void *fn) {
   return (uint32_t)(nb * std::max(cus, 1));
 }
 
-uint32_t resident_blocks(int KP, int kind) {
-  static uint32_t cache[2][4] = {};
-  uint32_t &c = cache[KP - 1][kind];
+static int gidx(int G) { return G == 4 ? 0 : (G == 8 ? 1 : 2); }
+
+uint32_t resident_blocks(int KP, int kind, int G) {
+  static uint32_t cache[2][4][3] = {};
+  uint32_t &c = cache[KP - 1][kind][gidx(G)];
   if (c) return c;
   const void *fn = nullptr;
+  const bool one = KP == 1;
   switch (kind) {
-    case 0: fn = KP == 1 ? (const void *)k_enc_crt_a<1> : (const void *)k_enc_crt_a<2>; break;
-    case 1: fn = KP == 1 ? (const void *)k_enc_pub<1> : (const void *)k_enc_pub<2>; break;
-    case 2: fn = KP == 1 ? (const void *)k_dec_a<1> : (const void *)k_dec_a<2>; break;
-    default: fn = KP == 1 ? (const void *)k_hist_chunk<1> : (const void *)k_hist_chunk<2>; break;
+    case 0:
+      if (G == 4) fn = one ? (const void *)k_enc_crt_a<1, 4> : (const void *)k_enc_crt_a<2, 4>;
+      else if (G == 8) fn = one ? (const void *)k_enc_crt_a<1, 8> : (const void *)k_enc_crt_a<2, 8>;
+      else fn = one ? (const void *)k_enc_crt_a<1, 16> : (const void *)k_enc_crt_a<2, 16>;
+      break;
+    case 1: fn = one ? (const void *)k_enc_pub<1> : (const void *)k_enc_pub<2>; break;
+    case 2:
+      if (G == 4) fn = one ? (const void *)k_dec_a<1, 4> : (const void *)k_dec_a<2, 4>;
+      else if (G == 8) fn = one ? (const void *)k_dec_a<1, 8> : (const void *)k_dec_a<2, 8>;
+      else fn = one ? (const void *)k_dec_a<1, 16> : (const void *)k_dec_a<2, 16>;
+      break;
+    default: fn = one ? (const void *)k_hist_chunk<1> : (const void *)k_hist_chunk<2>; break;
   }
   c = occupancy_blocks(fn);
   return c;
 }
 
-uint64_t table_bytes_per_block(int KP, int kind) {
+uint64_t table_bytes_per_block(int KP, int kind, int G) {
   const uint64_t S = kind == 1 ? 64 * KP : 32 * KP;  // public path tables are mod n^2
-  return 16ull * kTable * S * sizeof(uint32_t);
+  return (uint64_t)(kBlockThreads / G) * kTable * S * sizeof(uint32_t);
+}
+
+// Group width for a CRT exponentiation kernel (kind 0 encryption, 2
+// decryption) over `count` ciphertexts: the narrowest group (more limbs per
+// lane, less cross-lane work per product) whose launch still has enough
+// waves to fill every resident slot of the device.
+int pick_group(int KP, int kind, uint64_t count) {
+  for (int G : {4, 8}) {
+    const uint64_t waves = 2 * ((count + 64 / G - 1) / (64 / G));
+    if (waves >= (uint64_t)resident_blocks(KP, kind, G) * 4) return G;
+  }
+  return 16;
 }
 
 }  // namespace he

@@ -1,21 +1,24 @@
 // Wave-cooperative multiprecision Montgomery arithmetic for gfx950.
 //
-// One big integer of S = 16 K little-endian 32-bit limbs lives in a "group"
-// of 16 consecutive lanes (one DPP row): lane l holds limbs l*K .. l*K+K-1 in
-// VGPRs.  A wave64 therefore works on four independent integers at once, and
-// every cross-lane step of the arithmetic is a DPP row operation (shift by one
-// lane, broadcast of lane 0 or 15 of the row) or one wave-wide ballot.
+// One big integer of S = G K little-endian 32-bit limbs lives in a "group" of
+// G consecutive lanes (G = 16: one DPP row; G = 8: half a row; G = 4: one
+// quad): lane l of the group holds limbs l*K .. l*K+K-1 in VGPRs.  A wave64
+// works on 64/G independent integers at once, and every cross-lane step of the
+// arithmetic is a DPP operation (shift by one lane, broadcast of the group's
+// first or last lane) or one wave-wide ballot.  Smaller groups give each lane
+// more limbs, which amortises the per-step cross-lane work over more
+// multiply-adds; larger groups keep more integers' worth of registers free.
 //
 // Montgomery product (CIOS: for each limb a_i of the multiplier, add a_i * b,
 // pick the quotient digit that clears the lowest limb, add q * N, shift down
 // one limb).  The multiplier's limbs are read from LDS with one address per
-// group, so the 16 lanes get a broadcast; the multiplicand b and the modulus
+// group, so the lanes of a group get a broadcast; the multiplicand b and the modulus
 // N stay in registers.  The accumulator is kept as per-column 64-bit words
 // with overflow counters (see "column accumulators" below), so a product costs
 // one multiply-add and one carry add, and only the lowest column is folded per
 // step; no step waits on a cross-lane carry chain.  The final carry
 // resolution and the conditional subtraction use a ballot carry-lookahead over
-// the 16 lanes.
+// the lanes of the group.
 //
 // Every function here must be called by all 64 lanes of the wave (ballots and
 // DPP read all of them); callers predicate results, never control flow.
@@ -31,47 +34,83 @@ constexpr int kWindow = 5;                 // fixed-window exponentiation width
 constexpr int kTable = 1 << kWindow;       // entries per window table
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
-__device__ __forceinline__ uint32_t glane() { return __lane_id() & 15u; }
+template <int G = 16>
+__device__ __forceinline__ uint32_t glane() { return __lane_id() & (G - 1u); }
 
-// ---- DPP row operations (rows of 16 lanes) --------------------------------
-// row_newbcast:0 / :15 -- every lane of the row reads lane 0 / lane 15.
+// ---- DPP group operations -------------------------------------------------
+// Every lane of the group reads the group's first / last lane.
+//   G = 16: row_newbcast:0 / :15;  G = 8: row_newbcast:0 on banks 0-1 and :8
+//   on banks 2-3 (resp. :7 / :15);  G = 4: quad_perm [0,0,0,0] / [3,3,3,3].
+template <int G = 16>
 __device__ __forceinline__ uint32_t bcast_first(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150, 0xF, 0xF, false);
+  static_assert(G == 4 || G == 8 || G == 16, "group width");
+  if constexpr (G == 16) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150, 0xF, 0xF, false);
+  } else if constexpr (G == 8) {
+    const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x150, 0xF, 0x3, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x158, 0xF, 0xC, false);
+  } else {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x00, 0xF, 0xF, false);
+  }
 }
+template <int G = 16>
 __device__ __forceinline__ uint32_t bcast_last(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x15F, 0xF, 0xF, false);
+  static_assert(G == 4 || G == 8 || G == 16, "group width");
+  if constexpr (G == 16) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x15F, 0xF, 0xF, false);
+  } else if constexpr (G == 8) {
+    const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x157, 0xF, 0x3, false);
+    return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x15F, 0xF, 0xC, false);
+  } else {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xFF, 0xF, 0xF, false);
+  }
 }
-// row_shl:1 -- lane l reads lane l+1 of its row; lane 15 reads 0.
+// Lane l reads lane l+1 of its group; the group's last lane reads 0
+// (row_shl:1; for G < 16 the lane that would read across a group edge inside
+// the row is cleared).
+template <int G = 16>
 __device__ __forceinline__ uint32_t from_next(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x101, 0xF, 0xF, true);
+  const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x101, 0xF, 0xF, true);
+  if constexpr (G == 16) return t;
+  else return glane<G>() == G - 1 ? 0u : t;
 }
-// row_shr:1 -- lane l reads lane l-1 of its row; lane 0 reads 0.
+// Lane l reads lane l-1 of its group; the group's first lane reads 0 (row_shr:1).
+template <int G = 16>
 __device__ __forceinline__ uint32_t from_prev(uint32_t v) {
-  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+  const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+  if constexpr (G == 16) return t;
+  else return glane<G>() == 0 ? 0u : t;
 }
 
-// Carry lookahead across the 16 lanes of every row at once.  gen: the lane
+template <int G>
+constexpr uint64_t group_top_mask() {
+  return G == 16 ? 0x8000800080008000ull : (G == 8 ? 0x8080808080808080ull : 0x8888888888888888ull);
+}
+
+// Carry lookahead across the lanes of every group at once.  gen: the lane
 // produces a carry by itself; prop: the lane passes an incoming carry on
 // (all its limbs are at their maximum).  Returns the carry into this lane.
-// Lane 15 neither sends to the next row nor is allowed to chain into it.
+// A group's last lane neither sends to the next group nor chains into it.
+template <int G = 16>
 __device__ __forceinline__ bool carry_in(bool gen, bool prop) {
-  constexpr uint64_t kRowTop = 0x8000800080008000ull;
-  const uint64_t g = __builtin_amdgcn_ballot_w64(gen) & ~kRowTop;
-  const uint64_t p = __builtin_amdgcn_ballot_w64(prop) & ~kRowTop;
+  constexpr uint64_t kTop = group_top_mask<G>();
+  const uint64_t g = __builtin_amdgcn_ballot_w64(gen) & ~kTop;
+  const uint64_t p = __builtin_amdgcn_ballot_w64(prop) & ~kTop;
   const uint64_t c = ((g << 1) + p) ^ p;
   return (c >> lane_id()) & 1ull;
 }
 
-// True in every lane of a row iff `v` is true in any lane of the row.
+// True in every lane of a group iff `v` is true in any lane of the group.
+template <int G = 16>
 __device__ __forceinline__ bool row_any(bool v) {
   const uint64_t b = __builtin_amdgcn_ballot_w64(v);
-  return ((b >> (lane_id() & 48u)) & 0xFFFFull) != 0;
+  return ((b >> (lane_id() & ~(uint32_t)(G - 1))) & ((1ull << G) - 1)) != 0;
 }
 
 // ---- register <-> memory ----------------------------------------------------
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void ld(uint32_t (&x)[K], const uint32_t *p) {
-  p += glane() * K;
+  p += glane<G>() * K;
   if constexpr (K % 4 == 0) {
 #pragma unroll
     for (int j = 0; j < K; j += 4) {
@@ -85,9 +124,9 @@ __device__ __forceinline__ void ld(uint32_t (&x)[K], const uint32_t *p) {
     x[0] = p[0];
   }
 }
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void st(uint32_t *p, const uint32_t (&x)[K]) {
-  p += glane() * K;
+  p += glane<G>() * K;
   if constexpr (K % 4 == 0) {
 #pragma unroll
     for (int j = 0; j < K; j += 4)
@@ -98,22 +137,22 @@ __device__ __forceinline__ void st(uint32_t *p, const uint32_t (&x)[K]) {
     p[0] = x[0];
   }
 }
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void set_zero(uint32_t (&x)[K]) {
 #pragma unroll
   for (int j = 0; j < K; ++j) x[j] = 0;
 }
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void set_small(uint32_t (&x)[K], uint32_t v) {
   set_zero(x);
-  if (glane() == 0) x[0] = v;
+  if (glane<G>() == 0) x[0] = v;
 }
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void copy(uint32_t (&d)[K], const uint32_t (&s)[K]) {
 #pragma unroll
   for (int j = 0; j < K; ++j) d[j] = s[j];
 }
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void select(uint32_t (&d)[K], bool c, const uint32_t (&a)[K],
                                        const uint32_t (&b)[K]) {
 #pragma unroll
@@ -126,18 +165,18 @@ struct Mod {
   uint32_t n[K];   // this lane's limbs of N
   uint32_t ninv;   // -N^-1 mod 2^32
 };
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ Mod<K> load_mod(const uint32_t *N, uint32_t ninv) {
   Mod<K> m;
-  ld<K>(m.n, N);
+  ld<K, G>(m.n, N);
   m.ninv = ninv;
   return m;
 }
 
 // ---- carry resolution and reduction ----------------------------------------
 // If top:t >= N then t -= N (t < 2N on entry, top = bits at and above limb S,
-// meaningful in lane 15).  Result in [0, N).
-template <int K>
+// meaningful in the group's last lane).  Result in [0, N).
+template <int K, int G = 16>
 __device__ __forceinline__ void cond_sub(uint32_t (&t)[K], uint32_t top, const Mod<K> &M) {
   uint32_t d[K];
   unsigned b;
@@ -148,11 +187,11 @@ __device__ __forceinline__ void cond_sub(uint32_t (&t)[K], uint32_t top, const M
   bool prop = true;
 #pragma unroll
   for (int j = 0; j < K; ++j) prop = prop && (d[j] == 0u);
-  unsigned b2 = carry_in(gen, prop);
+  unsigned b2 = carry_in<G>(gen, prop);
 #pragma unroll
   for (int j = 0; j < K; ++j) d[j] = __builtin_subc(d[j], 0u, b2, &b2);
   const bool borrow_out = gen || b2;
-  const bool ge = bcast_last((top != 0u || !borrow_out) ? 1u : 0u) != 0u;
+  const bool ge = bcast_last<G>((top != 0u || !borrow_out) ? 1u : 0u) != 0u;
   select(t, ge, d, t);
 }
 
@@ -204,7 +243,7 @@ __device__ __forceinline__ void mac1(uint64_t &c0, uint32_t &o0, uint32_t a, uin
       : "v"(a), "v"(b0));
 }
 
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void row_mac(uint64_t (&C)[K], uint32_t (&O)[K], uint32_t a,
                                         const uint32_t (&b)[K]) {
   if constexpr (K == 1) {
@@ -232,14 +271,14 @@ __device__ __forceinline__ uint32_t mul_lo32(uint32_t x, uint32_t y) {
 // (high word and overflow) of column 0 into column 1 -- the same weight after
 // the shift -- and hands the low word of column 0 to the previous lane, whose
 // new top column it becomes (lane 0's low word is zero and is dropped).
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void mont_step(uint64_t (&C)[K], uint32_t (&O)[K], uint32_t ai,
                                           const uint32_t (&b)[K], const Mod<K> &M) {
   row_mac<K>(C, O, ai, b);
-  const uint32_t q = bcast_first(mul_lo32((uint32_t)C[0], M.ninv));
+  const uint32_t q = bcast_first<G>(mul_lo32((uint32_t)C[0], M.ninv));
   row_mac<K>(C, O, q, M.n);
   const uint32_t lo0 = (uint32_t)C[0], hi0 = (uint32_t)(C[0] >> 32);
-  const uint32_t nb = from_next(lo0);
+  const uint32_t nb = from_next<G>(lo0);
   if constexpr (K == 1) {
     // the lane's new column = low word from the next lane + own upper part
     unsigned c;
@@ -265,15 +304,15 @@ __device__ __forceinline__ void mont_step(uint64_t (&C)[K], uint32_t (&O)[K], ui
 }
 
 // Turns the column accumulators into plain limbs t (columns 0..S-1 of the
-// group) and returns, in lane 15, the part at and above limb S.
-template <int K>
+// group) and returns, in the group's last lane, the part at and above limb S.
+template <int K, int G = 16>
 __device__ __forceinline__ uint32_t resolve(uint32_t (&t)[K], const uint64_t (&C)[K],
                                             const uint32_t (&O)[K]) {
   // Column c receives lo(C_c), hi(C_{c-1}) and O_{c-2}; the terms of the
   // lane's lowest columns come from the previous lane(s).
-  const uint32_t in_hi = from_prev((uint32_t)(C[K - 1] >> 32));
-  const uint32_t in_o1 = from_prev(O[K - 1]);
-  const uint32_t in_o2 = K >= 2 ? from_prev(O[K >= 2 ? K - 2 : 0]) : from_prev(in_o1);
+  const uint32_t in_hi = from_prev<G>((uint32_t)(C[K - 1] >> 32));
+  const uint32_t in_o1 = from_prev<G>(O[K - 1]);
+  const uint32_t in_o2 = K >= 2 ? from_prev<G>(O[K >= 2 ? K - 2 : 0]) : from_prev<G>(in_o1);
   uint32_t carry = 0;
 #pragma unroll
   for (int j = 0; j < K; ++j) {
@@ -284,7 +323,7 @@ __device__ __forceinline__ uint32_t resolve(uint32_t (&t)[K], const uint64_t (&C
     carry = (uint32_t)(s >> 32);
   }
   // the lane's carry (at most 3) goes to the next lane's lowest limb
-  const uint32_t cin = from_prev(carry);
+  const uint32_t cin = from_prev<G>(carry);
   unsigned c;
   t[0] = __builtin_addc(t[0], cin, 0u, &c);
 #pragma unroll
@@ -293,17 +332,17 @@ __device__ __forceinline__ uint32_t resolve(uint32_t (&t)[K], const uint64_t (&C
   bool prop = true;
 #pragma unroll
   for (int j = 0; j < K; ++j) prop = prop && (t[j] == 0xFFFFFFFFu);
-  unsigned c2 = carry_in(gen, prop);
+  unsigned c2 = carry_in<G>(gen, prop);
 #pragma unroll
   for (int j = 0; j < K; ++j) t[j] = __builtin_addc(t[j], 0u, c2, &c2);
-  // lane 15: everything at and above limb S.  The result is below 2N < 2^(32S+1),
+  // last lane: everything at and above limb S.  The result is below 2N < 2^(32S+1),
   // so this is 0 or 1; any nonzero part counts.
   const uint32_t top_hi = (uint32_t)(C[K - 1] >> 32);
   const uint32_t top_o2 = K >= 2 ? O[K >= 2 ? K - 2 : 0] : in_o1;
   return (top_hi | top_o2 | O[K - 1]) != 0u ? 1u : (carry + (uint32_t)gen + c2);
 }
 
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void lds_limbs(uint32_t (&a)[K], const uint32_t *p) {
   if constexpr (K % 4 == 0) {
 #pragma unroll
@@ -321,7 +360,7 @@ __device__ __forceinline__ void lds_limbs(uint32_t (&a)[K], const uint32_t *p) {
 
 // t = a * b * 2^(-32 S) mod N with a taken from this group's LDS copy
 // (S limbs, a < 2^(32 S)) and b < N in registers.  t may alias b.
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void mont_mul_lds(uint32_t (&t)[K], const uint32_t *a_lds,
                                              const uint32_t (&b)[K], const Mod<K> &M) {
   uint64_t C[K];
@@ -331,12 +370,13 @@ __device__ __forceinline__ void mont_mul_lds(uint32_t (&t)[K], const uint32_t *a
     C[j] = 0;
     O[j] = 0;
   }
-  // U steps per loop iteration (at least 8 and two full rotations of the
-  // lane's columns) so the loop-carried registers rotate back less often.
-  constexpr int U = K >= 4 ? 2 * K : 8;
-  static_assert((kGroupLanes * K) % U == 0, "unroll must divide S");
+  // U steps per loop iteration (at least 8, and two full rotations of the
+  // lane's columns while that fits in registers) so the loop-carried
+  // registers rotate back less often.
+  constexpr int U = K >= 8 ? K : (K >= 4 ? 2 * K : 8);
+  static_assert((G * K) % U == 0, "unroll must divide S");
 #pragma unroll 1
-  for (int i0 = 0; i0 < kGroupLanes * K; i0 += U) {
+  for (int i0 = 0; i0 < G * K; i0 += U) {
     uint32_t av[U];
 #pragma unroll
     for (int h = 0; h < U; h += 4) {
@@ -344,28 +384,28 @@ __device__ __forceinline__ void mont_mul_lds(uint32_t (&t)[K], const uint32_t *a
       av[h] = v.x; av[h + 1] = v.y; av[h + 2] = v.z; av[h + 3] = v.w;
     }
 #pragma unroll
-    for (int s = 0; s < U; ++s) mont_step<K>(C, O, av[s], b, M);
+    for (int s = 0; s < U; ++s) mont_step<K, G>(C, O, av[s], b, M);
   }
   uint32_t r[K];
-  const uint32_t top = resolve<K>(r, C, O);
-  cond_sub<K>(r, top, M);
+  const uint32_t top = resolve<K, G>(r, C, O);
+  cond_sub<K, G>(r, top, M);
   copy(t, r);
 }
 
 // t = a * b * 2^(-32 S) mod N, both operands in registers; `lds` is this
 // group's S-limb scratch row.  t may alias a or b.
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void mont_mul(uint32_t (&t)[K], const uint32_t (&a)[K],
                                          const uint32_t (&b)[K], const Mod<K> &M, uint32_t *lds) {
-  st<K>(lds, a);
+  st<K, G>(lds, a);
   __builtin_amdgcn_wave_barrier();
-  mont_mul_lds<K>(t, lds, b, M);
+  mont_mul_lds<K, G>(t, lds, b, M);
   __builtin_amdgcn_wave_barrier();
 }
 
 // ---- modular add / sub --------------------------------------------------------
 // t = x + y mod N for x, y < N.
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void add_mod(uint32_t (&t)[K], const uint32_t (&x)[K],
                                         const uint32_t (&y)[K], const Mod<K> &M) {
   unsigned c;
@@ -376,15 +416,15 @@ __device__ __forceinline__ void add_mod(uint32_t (&t)[K], const uint32_t (&x)[K]
   bool prop = true;
 #pragma unroll
   for (int j = 0; j < K; ++j) prop = prop && (t[j] == 0xFFFFFFFFu);
-  unsigned c2 = carry_in(gen, prop);
+  unsigned c2 = carry_in<G>(gen, prop);
 #pragma unroll
   for (int j = 0; j < K; ++j) t[j] = __builtin_addc(t[j], 0u, c2, &c2);
-  const uint32_t top = (uint32_t)gen + c2;  // meaningful in lane 15
-  cond_sub<K>(t, top, M);
+  const uint32_t top = (uint32_t)gen + c2;  // meaningful in the last lane
+  cond_sub<K, G>(t, top, M);
 }
 
-// t = x + y (no reduction); returns the carry out of the top (lane 15).
-template <int K>
+// t = x + y (no reduction); returns the carry out of the top (last lane).
+template <int K, int G = 16>
 __device__ __forceinline__ uint32_t add_plain(uint32_t (&t)[K], const uint32_t (&x)[K],
                                               const uint32_t (&y)[K]) {
   unsigned c;
@@ -395,14 +435,14 @@ __device__ __forceinline__ uint32_t add_plain(uint32_t (&t)[K], const uint32_t (
   bool prop = true;
 #pragma unroll
   for (int j = 0; j < K; ++j) prop = prop && (t[j] == 0xFFFFFFFFu);
-  unsigned c2 = carry_in(gen, prop);
+  unsigned c2 = carry_in<G>(gen, prop);
 #pragma unroll
   for (int j = 0; j < K; ++j) t[j] = __builtin_addc(t[j], 0u, c2, &c2);
   return (uint32_t)gen + c2;
 }
 
-// t = x - y (mod 2^(32S)); returns true in lane 15 iff x < y.
-template <int K>
+// t = x - y (mod 2^(32S)); returns true in the last lane iff x < y.
+template <int K, int G = 16>
 __device__ __forceinline__ bool sub_plain(uint32_t (&t)[K], const uint32_t (&x)[K],
                                           const uint32_t (&y)[K]) {
   unsigned b;
@@ -413,26 +453,26 @@ __device__ __forceinline__ bool sub_plain(uint32_t (&t)[K], const uint32_t (&x)[
   bool prop = true;
 #pragma unroll
   for (int j = 0; j < K; ++j) prop = prop && (t[j] == 0u);
-  unsigned b2 = carry_in(gen, prop);
+  unsigned b2 = carry_in<G>(gen, prop);
 #pragma unroll
   for (int j = 0; j < K; ++j) t[j] = __builtin_subc(t[j], 0u, b2, &b2);
   return gen || b2;
 }
 
 // t = x - y mod N for x, y < N.
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void sub_mod(uint32_t (&t)[K], const uint32_t (&x)[K],
                                         const uint32_t (&y)[K], const Mod<K> &M) {
-  const bool neg = bcast_last(sub_plain<K>(t, x, y) ? 1u : 0u) != 0u;
+  const bool neg = bcast_last<G>(sub_plain<K, G>(t, x, y) ? 1u : 0u) != 0u;
   uint32_t w[K];
-  add_plain<K>(w, t, M.n);
+  add_plain<K, G>(w, t, M.n);
   select(t, neg, w, t);
 }
 
 // ---- low-half product ----------------------------------------------------------
 // t = a * b mod 2^(32 S), with a from this group's LDS copy and b in registers.
 // (Used for the exact division x / P = x * P^-1 mod 2^(32 S) when P | x.)
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void mul_lo_lds(uint32_t (&t)[K], const uint32_t *a_lds,
                                            const uint32_t (&b)[K]) {
   uint32_t acc[K], bs[K];
@@ -440,7 +480,7 @@ __device__ __forceinline__ void mul_lo_lds(uint32_t (&t)[K], const uint32_t *a_l
   copy(bs, b);
   uint32_t cin = 0;  // pending carry into this lane's lowest column
 #pragma unroll 1
-  for (int i0 = 0; i0 < kGroupLanes * K; i0 += K) {
+  for (int i0 = 0; i0 < G * K; i0 += K) {
     uint32_t av[K];
     lds_limbs<K>(av, a_lds + i0);
 #pragma unroll
@@ -455,9 +495,9 @@ __device__ __forceinline__ void mul_lo_lds(uint32_t (&t)[K], const uint32_t *a_l
 #pragma unroll
       for (int j = 1; j < K; ++j) acc[j] = __builtin_addc((uint32_t)x[j], (uint32_t)(x[j - 1] >> 32), c, &c);
       const uint32_t top = (uint32_t)(x[K - 1] >> 32) + c;
-      cin = from_prev(top);
+      cin = from_prev<G>(top);
       // shift bs up by one limb for the next multiplier limb
-      const uint32_t down = from_prev(bs[K - 1]);
+      const uint32_t down = from_prev<G>(bs[K - 1]);
 #pragma unroll
       for (int j = K - 1; j > 0; --j) bs[j] = bs[j - 1];
       bs[0] = down;
@@ -472,7 +512,7 @@ __device__ __forceinline__ void mul_lo_lds(uint32_t (&t)[K], const uint32_t *a_l
   bool prop = true;
 #pragma unroll
   for (int j = 0; j < K; ++j) prop = prop && (acc[j] == 0xFFFFFFFFu);
-  unsigned c2 = carry_in(gen, prop);
+  unsigned c2 = carry_in<G>(gen, prop);
 #pragma unroll
   for (int j = 0; j < K; ++j) acc[j] = __builtin_addc(acc[j], 0u, c2, &c2);
   copy(t, acc);
@@ -493,45 +533,45 @@ __device__ __forceinline__ uint32_t exp_digit(const uint32_t *e, int w) {
 // multiplication by the table entry is done for every window, zero digits
 // included, so the sequence of operations does not depend on the exponent.
 // `tab` is this group's table: kTable entries of S limbs in global memory.
-template <int K>
+template <int K, int G = 16>
 __device__ __forceinline__ void mont_pow(uint32_t (&x)[K], const uint32_t *e, int nwin,
                                          uint32_t *tab, const uint32_t (&one)[K],
                                          const Mod<K> &M, uint32_t *lds) {
-  constexpr int S = kGroupLanes * K;
-  st<K>(tab, one);
-  st<K>(tab + S, x);
+  constexpr int S = G * K;
+  st<K, G>(tab, one);
+  st<K, G>(tab + S, x);
   uint32_t cur[K];
   copy(cur, x);
 #pragma unroll 1
   for (int d = 2; d < kTable; ++d) {
-    mont_mul<K>(cur, cur, x, M, lds);
-    st<K>(tab + d * S, cur);
+    mont_mul<K, G>(cur, cur, x, M, lds);
+    st<K, G>(tab + d * S, cur);
   }
   __threadfence_block();
-  ld<K>(cur, tab + exp_digit(e, nwin - 1) * S);
+  ld<K, G>(cur, tab + exp_digit(e, nwin - 1) * S);
 #pragma unroll 1
   for (int w = nwin - 2; w >= 0; --w) {
     uint32_t tb[K];
-    ld<K>(tb, tab + exp_digit(e, w) * S);
+    ld<K, G>(tb, tab + exp_digit(e, w) * S);
 #pragma unroll 1
-    for (int s = 0; s < kWindow; ++s) mont_mul<K>(cur, cur, cur, M, lds);
-    mont_mul<K>(cur, cur, tb, M, lds);
+    for (int s = 0; s < kWindow; ++s) mont_mul<K, G>(cur, cur, cur, M, lds);
+    mont_mul<K, G>(cur, cur, tb, M, lds);
   }
   copy(x, cur);
 }
 
 // Moves an integer between limb layouts through this group's LDS row:
-// src has 16*KS limbs (KS per lane), dst gets 16*KD limbs (KD per lane); the
+// src has G*KS limbs (KS per lane), dst gets G*KD limbs (KD per lane); the
 // limbs are taken starting at `first` and limbs beyond the source are zero.
-template <int KS, int KD>
+template <int KS, int KD, int G = 16>
 __device__ __forceinline__ void relayout(uint32_t (&dst)[KD], const uint32_t (&src)[KS],
                                          uint32_t *lds, int first = 0) {
-  constexpr int SS = kGroupLanes * KS;
-  st<KS>(lds, src);
+  constexpr int SS = G * KS;
+  st<KS, G>(lds, src);
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int j = 0; j < KD; ++j) {
-    const int idx = first + (int)glane() * KD + j;
+    const int idx = first + (int)glane<G>() * KD + j;
     dst[j] = idx < SS ? lds[idx] : 0u;
   }
   __builtin_amdgcn_wave_barrier();

@@ -249,7 +249,7 @@ class GpuBackend(Backend):
     party): (uint8 [F_max, rows] device tensor, n_bins)} (each passive
     party's feature bins)."""
 
-    def __init__(self, keys, pools, bins, n_streams: int = 4, chunk: int = 0):
+    def __init__(self, keys, pools, bins, n_streams: int = 4, chunk: int = 0, enc_slice: int = 0):
         import torch
         from . import he
         self.he = he
@@ -260,6 +260,10 @@ class GpuBackend(Backend):
         self.n_streams = n_streams
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.chunk = chunk
+        # encryptions longer than enc_slice values go out as several launches
+        # (consecutive stretches of the same seeded r stream), so launches of
+        # other streams can run between them; 0 = one launch
+        self.enc_slice = enc_slice
 
     # Footprint estimates mirror the buffers each launch allocates (outputs
     # plus library workspace).
@@ -288,8 +292,15 @@ class GpuBackend(Backend):
         with torch.cuda.stream(st):
             if kind == "encrypt":
                 (r,) = reqs
-                r.result = he.encrypt(key, r.payload["m"], seed=r.payload["seed"],
-                                      offset=r.payload.get("offset", 0), stream=st)
+                m = r.payload["m"]
+                n = m.numel()
+                out = torch.empty((n, 2 * key.limbs), dtype=torch.int32, device=m.device)
+                step = self.enc_slice or n
+                off0 = r.payload.get("offset", 0)
+                for a in range(0, n, step):
+                    b = min(n, a + step)
+                    he.encrypt(key, m[a:b], seed=r.payload["seed"], offset=off0 + a, out=out[a:b], stream=st)
+                r.result = out
                 outs = None
             elif kind == "aggregate":
                 pool = self.pools[key_id]
@@ -405,8 +416,9 @@ def make_setup(key, rows: int, depth: int, n_parties: int, f_max: int, rng, r_se
             "parties": n_parties, "f_max": f_max}
 
 
-def backend_for(setups: Dict[str, Dict[str, Any]], n_streams: int = 4, chunk: int = 0) -> "GpuBackend":
+def backend_for(setups: Dict[str, Dict[str, Any]], n_streams: int = 4, chunk: int = 0,
+                enc_slice: int = 0) -> "GpuBackend":
     keys = {k: s["key"] for k, s in setups.items()}
     pools = {k: s["pool"] for k, s in setups.items()}
     bins = {(k, p): v for k, s in setups.items() for p, v in s["bins"].items()}
-    return GpuBackend(keys, pools, bins, n_streams=n_streams, chunk=chunk)
+    return GpuBackend(keys, pools, bins, n_streams=n_streams, chunk=chunk, enc_slice=enc_slice)

@@ -25,7 +25,7 @@ def test_served_results_equal_alone():
               "k1024": serve.make_setup(k1, 3000, 3, 4, 16, rng, 6)}
     trace = serve.build_trace(rng, 48, 2000.0, setups, {"k2048": 0.9, "k1024": 0.1},
                               enc_range=(100, 4000), max_decrypt=3000, feature_range=(4, 24))
-    backend = serve.backend_for(setups, n_streams=4)
+    backend = serve.backend_for(setups, n_streams=4, enc_slice=1000)
     srv = serve.Server(backend, hbm_budget=2 << 30, max_inflight=6)
     stats = srv.run(trace, time_limit=300)
     torch.cuda.synchronize()

@@ -120,6 +120,23 @@ int he_encrypt_public(const he_key *key, const int64_t *m, uint64_t count,
                       const uint32_t *r, uint64_t r_seed, uint64_t r_offset,
                       uint32_t *ct, hipStream_t stream);
 
+/* Obfuscators for encryption ahead of time: rho[i] = r_i^n mod n^2, i.e. the
+ * encryption of 0 with the same r as he_encrypt (explicit r, or the seeded
+ * stream with r_seed / r_offset).  rho: device uint32[count][2L], canonical.
+ * This is the exponentiation part of encryption, which does not depend on
+ * the plaintext, so the encrypting party can run it before the gradients
+ * exist. */
+int he_obfuscators(const he_key *key, uint64_t count, const uint32_t *r, uint64_t r_seed,
+                   uint64_t r_offset, uint32_t *rho, hipStream_t stream);
+
+/* Encryption with precomputed obfuscators: ct[i] = (1 + (m[i] mod n) n)
+ * rho[i] mod n^2 -- the same ciphertext as he_encrypt with the r that
+ * produced rho[i], for three Montgomery products per value.  Each obfuscator
+ * must be used for one plaintext only.  m: device int64[count]; rho, ct:
+ * device uint32[count][2L] (ct may alias rho). */
+int he_encrypt_obfuscated(const he_key *key, const int64_t *m, uint64_t count, const uint32_t *rho,
+                          uint32_t *ct, hipStream_t stream);
+
 /* Montgomery conversion of ciphertexts: out = in * 2^(64L) mod n^2 (to_mont)
  * or in * 2^(-64L) mod n^2 (from_mont).  Device uint32[count][2L]; in-place
  * (in == out) is allowed.  Keeps gradients resident in the form the

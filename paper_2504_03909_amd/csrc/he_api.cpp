@@ -171,11 +171,12 @@ uint32_t persistent_grid(int KP, int kind, uint64_t work_blocks, int G = 16) {
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(res, work_blocks));
 }
 
+// m == nullptr encrypts zeros (the obfuscators r^n mod n^2).
 int encrypt_impl(const he_key *key, const int64_t *m, uint64_t count, const uint32_t *r,
                  uint64_t r_seed, uint64_t r_offset, uint32_t *ct, hipStream_t stream, bool force_pub) {
   if (!key) return fail(HE_ERR_ARG, "null key");
   if (count == 0) return HE_OK;
-  if (!m || !ct) return fail(HE_ERR_ARG, "null m or ct");
+  if (!ct) return fail(HE_ERR_ARG, "null ct");
   Workspace *w = workspace(stream);
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
@@ -285,11 +286,27 @@ int he_encode(const double *x, uint64_t count, uint32_t frac_bits, int64_t *m, u
 
 int he_encrypt(const he_key *key, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t r_seed,
                uint64_t r_offset, uint32_t *ct, hipStream_t stream) {
+  if (count && !m) return fail(HE_ERR_ARG, "null m");
   return encrypt_impl(key, m, count, r, r_seed, r_offset, ct, stream, false);
+}
+
+int he_obfuscators(const he_key *key, uint64_t count, const uint32_t *r, uint64_t r_seed, uint64_t r_offset,
+                   uint32_t *rho, hipStream_t stream) {
+  return encrypt_impl(key, nullptr, count, r, r_seed, r_offset, rho, stream, false);
+}
+
+int he_encrypt_obfuscated(const he_key *key, const int64_t *m, uint64_t count, const uint32_t *rho,
+                          uint32_t *ct, hipStream_t stream) {
+  if (!key) return fail(HE_ERR_ARG, "null key");
+  if (count == 0) return HE_OK;
+  if (!m || !rho || !ct) return fail(HE_ERR_ARG, "null m, rho or ct");
+  HE_TRY_HIP(he::launch_enc_obf(kp_of(key), key->dk, m, count, rho, ct, stream));
+  return HE_OK;
 }
 
 int he_encrypt_public(const he_key *key, const int64_t *m, uint64_t count, const uint32_t *r,
                       uint64_t r_seed, uint64_t r_offset, uint32_t *ct, hipStream_t stream) {
+  if (count && !m) return fail(HE_ERR_ARG, "null m");
   return encrypt_impl(key, m, count, r, r_seed, r_offset, ct, stream, true);
 }
 

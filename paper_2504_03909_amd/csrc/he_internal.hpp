@@ -96,6 +96,8 @@ hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t coun
 hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
                           const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *ct,
                           uint32_t *tab, uint32_t grid, hipStream_t s);
+hipError_t launch_enc_obf(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *rho,
+                          uint32_t *ct, hipStream_t s);
 hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64_t count,
                                uint32_t *out, bool to_mont, hipStream_t s);
 hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count,

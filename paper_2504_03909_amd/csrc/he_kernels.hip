@@ -163,7 +163,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_crt_a(
       // u = (m mod P) Q mod P, then f = 1 + m n mod P^2 = 1 + P u
       const Mod<K1> Mp = load_mod<K1, G>(P.P.N, P.P.ninv);
       uint32_t u[K1], c[K1];
-      signed_mod<K1, G>(u, m[i], Mp.n);
+      signed_mod<K1, G>(u, m ? m[i] : 0, Mp.n);
       ld<K1, G>(c, P.QR_P);
       mont_mul<K1, G>(u, u, c, Mp, lds);
       relayout<K1, K2, G>(f, u, lds);
@@ -242,13 +242,41 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
     mont_pow<KN2>(x, key.e_n.e, key.e_n.nwin, tab, c, M, lds);
     // f = 1 + (m mod n) n, exact (< n^2)
     ld_part<KN2>(c, key.n.N, L);
-    signed_mod<KN2>(f, m[i], c);
+    signed_mod<KN2>(f, m ? m[i] : 0, c);
     ld<KN2>(c, key.nR_n2);
     mont_mul<KN2>(f, f, c, M, lds);
     add_one<KN2>(f);
     mont_mul<KN2>(x, x, f, M, lds);
     if (valid) st<KN2>(ct + i * SN2, x);
   }
+}
+
+// ------------------------------------------------ obfuscated encryption
+// ct = (1 + (m mod n) n) rho mod n^2 with a precomputed obfuscator
+// rho = r^n mod n^2 (canonical): three Montgomery products per ciphertext.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_enc_obf(DKey key, const int64_t *__restrict__ m,
+                                                          uint64_t count, const uint32_t *rho,
+                                                          uint32_t *ct) {
+  constexpr int KN2 = 4 * KP, SN2 = 64 * KP, L = 32 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SN2;
+  uint64_t i = (uint64_t)blockIdx.x * 16 + gi;
+  const bool valid = i < count;
+  if (!valid) i = count - 1;
+  const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
+  uint32_t x[KN2], c[KN2], f[KN2];
+  ld<KN2>(x, rho + i * SN2);
+  ld<KN2>(c, key.n2.R2);
+  mont_mul<KN2>(x, x, c, M, lds);  // Montgomery form of rho
+  ld_part<KN2>(c, key.n.N, L);
+  signed_mod<KN2>(f, m[i], c);
+  ld<KN2>(c, key.nR_n2);
+  mont_mul<KN2>(f, f, c, M, lds);  // (m mod n) n, exact
+  add_one<KN2>(f);
+  mont_mul<KN2>(x, x, f, M, lds);
+  if (valid) st<KN2>(ct + i * SN2, x);
 }
 
 // ------------------------------------------------------ Montgomery conversion
@@ -665,12 +693,14 @@ __global__ __launch_bounds__(kBlockThreads) void k_hist_final(DKey key, HistWs w
       mont_mul<K>(t, acc, b, M, lds);
       select(acc, k < my_n, t, acc);
     }
-    st<K>(lds, acc);
-    __builtin_amdgcn_wave_barrier();
-    uint32_t other[K];
-    ld<K>(other, lds_all + (wrow + (g ^ 2u)) * S);
-    __builtin_amdgcn_wave_barrier();
-    mont_mul<K>(acc, acc, other, M, lds);
+    if (n_hi) {  // wave-uniform: one entry per wave
+      st<K>(lds, acc);
+      __builtin_amdgcn_wave_barrier();
+      uint32_t other[K];
+      ld<K>(other, lds_all + (wrow + (g ^ 2u)) * S);
+      __builtin_amdgcn_wave_barrier();
+      mont_mul<K>(acc, acc, other, M, lds);
+    }
     set_small(b, 1u);
     mont_mul<K>(acc, acc, b, M, lds);  // out of Montgomery form
     if (half == 0) st<K>(J.hist + (fb * 2 + slot) * S, acc);
@@ -743,6 +773,17 @@ hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t coun
     hipLaunchKernelGGL(k_enc_pub<1>, dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff, ct, tab);
   else
     hipLaunchKernelGGL(k_enc_pub<2>, dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff, ct, tab);
+  return hipGetLastError();
+}
+
+hipError_t launch_enc_obf(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *rho,
+                          uint32_t *ct, hipStream_t s) {
+  if (!count) return hipSuccess;
+  const dim3 grid(blocks_for(count, 16));
+  if (KP == 1)
+    hipLaunchKernelGGL(k_enc_obf<1>, grid, dim3(kBlockThreads), 0, s, k, m, count, rho, ct);
+  else
+    hipLaunchKernelGGL(k_enc_obf<2>, grid, dim3(kBlockThreads), 0, s, k, m, count, rho, ct);
   return hipGetLastError();
 }
 

@@ -74,6 +74,17 @@ __device__ __forceinline__ uint32_t from_next(uint32_t v) {
   if constexpr (G == 16) return t;
   else return glane<G>() == G - 1 ? 0u : t;
 }
+// Lane l reads lane l+1 of its group, the group's last lane reads the group's
+// first lane (G = 4: quad_perm [1,2,3,0]; G = 16: row_ror:15).  Used for the
+// one-limb shift of a Montgomery step, where the first lane's value is the
+// cleared lowest column and therefore 0, so this equals from_next without the
+// edge fix-up; G = 8 has no 8-lane rotation and uses from_next.
+template <int G = 16>
+__device__ __forceinline__ uint32_t rotate_next(uint32_t v) {
+  if constexpr (G == 4) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x39, 0xF, 0xF, false);
+  else if constexpr (G == 16) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x12F, 0xF, 0xF, false);
+  else return from_next<G>(v);
+}
 // Lane l reads lane l-1 of its group; the group's first lane reads 0 (row_shr:1).
 template <int G = 16>
 __device__ __forceinline__ uint32_t from_prev(uint32_t v) {
@@ -278,7 +289,7 @@ __device__ __forceinline__ void mont_step(uint64_t (&C)[K], uint32_t (&O)[K], ui
   const uint32_t q = bcast_first<G>(mul_lo32((uint32_t)C[0], M.ninv));
   row_mac<K>(C, O, q, M.n);
   const uint32_t lo0 = (uint32_t)C[0], hi0 = (uint32_t)(C[0] >> 32);
-  const uint32_t nb = from_next<G>(lo0);
+  const uint32_t nb = rotate_next<G>(lo0);
   if constexpr (K == 1) {
     // the lane's new column = low word from the next lane + own upper part
     unsigned c;

@@ -27,6 +27,7 @@ EXPORTED = (
     "he_key_free", "he_encode", "he_encrypt", "he_encrypt_public", "he_to_mont", "he_from_mont",
     "he_hist_aggregate", "he_hist_aggregate_ex", "he_decrypt", "he_probe_int_mul", "he_last_error",
     "he_hist_autotune", "he_hist_plan_create", "he_hist_plan_launch", "he_hist_plan_free",
+    "he_obfuscators", "he_encrypt_obfuscated",
 )
 
 
@@ -69,6 +70,8 @@ _key_free = _sig("he_key_free", None, [_vp])
 _encode = _sig("he_encode", _i32, [_vp, _u64, _u32, _vp, _vp, _vp])
 _encrypt = _sig("he_encrypt", _i32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp])
 _encrypt_pub = _sig("he_encrypt_public", _i32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp])
+_obf = _sig("he_obfuscators", _i32, [_vp, _u64, _vp, _u64, _u64, _vp, _vp])
+_enc_obf = _sig("he_encrypt_obfuscated", _i32, [_vp, _vp, _u64, _vp, _vp, _vp])
 _to_mont = _sig("he_to_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
 _from_mont = _sig("he_from_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
 _hist = _sig("he_hist_aggregate_ex", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32, _u32, _vp])
@@ -216,6 +219,25 @@ def encrypt(key: Key, m: torch.Tensor, r: Optional[torch.Tensor] = None, seed: i
         out = torch.empty((*m.shape, 2 * L), dtype=torch.int32, device=m.device)
     fn = _encrypt_pub if public else _encrypt
     _check(fn(key.handle, _ptr(m), count, _ptr(r), seed, offset, _ptr(out), _stream(stream)))
+    return out
+
+
+def obfuscators(key: Key, count: int, r: Optional[torch.Tensor] = None, seed: int = 0, offset: int = 0,
+                stream=None, device="cuda") -> torch.Tensor:
+    """r_i^n mod n^2 for the same r as encrypt(seed=..., offset=...) -> int32 [count, 2L]."""
+    out = torch.empty((count, 2 * key.limbs), dtype=torch.int32, device=device)
+    _check(_obf(key.handle, count, _ptr(r), seed, offset, _ptr(out), _stream(stream)))
+    return out
+
+
+def encrypt_obfuscated(key: Key, m: torch.Tensor, rho: torch.Tensor, out: Optional[torch.Tensor] = None,
+                       stream=None) -> torch.Tensor:
+    """(1 + m n) rho mod n^2 -> int32 [..., 2L]; equals encrypt() with rho's r."""
+    assert m.dtype == torch.int64 and rho.numel() == m.numel() * 2 * key.limbs
+    m = m.contiguous()
+    if out is None:
+        out = torch.empty((*m.shape, 2 * key.limbs), dtype=torch.int32, device=m.device)
+    _check(_enc_obf(key.handle, _ptr(m), m.numel(), _ptr(rho.contiguous()), _ptr(out), _stream(stream)))
     return out
 
 

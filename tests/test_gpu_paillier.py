@@ -141,6 +141,33 @@ def test_encrypt_seeded_r_bit_exact(he, bits, seed, count, offset, path):
     assert he.limbs_to_ints(host(ct)) == pool.encrypt_many(pk, ms, rs)
 
 
+@pytest.mark.parametrize("bits,seed,count,offset", [(1024, 1, 1500, 3), (2048, 2, 77, 0)])
+def test_obfuscated_encryption_bit_exact(he, bits, seed, count, offset):
+    """Obfuscators r^n mod n^2 (the oracle's encryption of 0 with r), and
+    encryption with them, equal the oracle's E(m; r) for the seeded r."""
+    say(f"obfuscated encryption {bits} count={count}")
+    sk = oracle_key(bits, seed)
+    pk = sk.public
+    rng = np.random.default_rng(count + 5)
+    ms = plaintexts(count // 2 + 4, rng)[:count]
+    r_seed = 0xBEEF + count
+    rs = [P.seeded_r(pk.n, bits, r_seed, offset + i) for i in range(count)]
+    k = gpu_key(bits, seed)
+    rho = he.obfuscators(k, count, seed=r_seed, offset=offset)
+    pick = rng.choice(count, size=min(count, 64), replace=False)
+    got_rho = he.limbs_to_ints(host(rho))
+    want_rho = pool.encrypt_many(pk, [0] * len(pick), [rs[i] for i in pick])
+    assert [got_rho[i] for i in pick] == want_rho
+    ct = he.encrypt_obfuscated(k, dev(np.array(ms, dtype=np.int64)), rho)
+    assert he.limbs_to_ints(host(ct)) == pool.encrypt_many(pk, ms, rs)
+    # explicit r, and the result written over the obfuscators
+    rx = W.random_units(pk.n, 40, rng)
+    rho2 = he.obfuscators(k, 40, r=dev(he.ints_to_limbs(rx, k.limbs)))
+    m2 = dev(np.array(ms[:40], dtype=np.int64))
+    he.encrypt_obfuscated(k, m2, rho2, out=rho2)
+    assert he.limbs_to_ints(host(rho2)) == pool.encrypt_many(pk, ms[:40], rx)
+
+
 # ---------------------------------------------------------- decryption
 @pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
 def test_decrypt_exact(he, bits, seed):

@@ -325,8 +325,27 @@ def bench_tree(args):
     torch.cuda.synchronize()
     _, t_graph = _timed(lambda: [p.launch() for p in plans.plans], "tree graphs")
     same = all(torch.equal(a, b) for la, lb in zip(run_plain.hists, plans.hists) for a, b in zip(la, lb))
+    pipeline.aggregate_levels(res, levels[:2], bins, Kt, mode="sibling")  # warm-up
+    run_sib, t_sib = _timed(lambda: pipeline.aggregate_levels(res, levels, bins, Kt, mode="sibling"),
+                            "tree sibling")
+    sib_same = all(torch.equal(a, b) for la, lb in zip(run_plain.hists, run_sib.hists) for a, b in zip(la, lb))
+    # the subtraction alone, over the deepest level's 16 parents (524,288 ciphertexts)
+    last = run_sib.hists[-2]
+    par = torch.stack(last[:16])
+    chl = torch.stack(run_sib.hists[-1][0:32:2])
+    out = torch.empty_like(par)
+    he.hist_subtract(key, par, chl, out=out)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+    ev[0].record()
+    he.hist_subtract(key, par, chl, out=out)
+    ev[1].record()
+    torch.cuda.synchronize()
+    sub_ms = ev[0].elapsed_time(ev[1])
+    n_sub = par.numel() // (2 * key.limbs)
     _, t_dec = _timed(lambda: pipeline.decrypt_levels(key, run_plain), "tree decrypt")
     contrib = 2 * Jt * sum(int(n.numel()) for lvl in levels for n in lvl)
+    contrib_sib = 2 * Jt * (Mt + sum(min(int(lvl[i].numel()), int(lvl[i + 1].numel()))
+                                     for lvl in levels[1:] for i in range(0, len(lvl), 2)))
     n_dec = 63 * Jt * Kt * 2
     return {
         "metric": "Paillier encryptions/s + encrypted hist sample-adds/s at 2048-bit key",
@@ -341,6 +360,11 @@ def bench_tree(args):
         "contributions": contrib,
         "decrypt_s": round(t_dec, 3), "decryptions_per_s": round(n_dec / t_dec, 1),
         "graph_equals_plain": bool(same),
+        "aggregate_sibling_s": round(t_sib, 3),
+        "sibling_contributions": contrib_sib,
+        "sibling_equals_plain": bool(sib_same),
+        "subtract_524288_ms": round(sub_ms, 3),
+        "subtract_per_s": round(n_sub / (sub_ms / 1e3), 1),
         "total_s_one_job_per_launch": round(t_enc + t_plain + t_dec, 3),
     }
 

@@ -208,6 +208,23 @@ int he_hist_plan_create(const he_key *key, const uint32_t *ct, uint64_t rows, in
 int he_hist_plan_launch(he_hist_plan *plan, hipStream_t stream);
 void he_hist_plan_free(he_hist_plan *plan);
 
+/* Encrypted histogram subtraction (the sibling trick of tree building: the
+ * samples of a node split into its two children, so the larger child's
+ * histogram is the parent's "minus" the smaller child's).  By the additive
+ * homomorphism (Sec. III-C), out[i] = parent[i] child[i]^-1 mod n^2 is an
+ * encryption of m_parent - m_child; when the child's samples are a subset of
+ * the parent's, it equals bit for bit the product over the remaining samples.
+ * Needs only the public key.  Inverses come from Kaliski's binary
+ * almost-inverse with Montgomery's batch trick (one inversion per `batch`
+ * consecutive elements, 0 = chosen from the count and the device).
+ * parent, child, out: device uint32[count][2L] canonical, any layout of
+ * histograms flattened to ciphertexts (e.g. [F][B][2]); out must not
+ * overlap parent or child (it holds intermediate products).  Elements whose
+ * child is not a unit mod n^2 (never the case for ciphertexts) get 0 and are
+ * counted into *n_bad (device uint32, optional, not cleared). */
+int he_hist_subtract(const he_key *key, const uint32_t *parent, const uint32_t *child, uint64_t count,
+                     uint32_t batch, uint32_t *out, uint32_t *n_bad, hipStream_t stream);
+
 /* Decryption (Sec. III-B: the active party decrypts the returned
  * histograms), by the CRT: m_p = L_p(c^(p-1) mod p^2) h_p mod p with
  * h_p = (-q mod p)^-1 mod p, likewise m_q, then m = m_q + q ((m_p - m_q)

@@ -23,7 +23,9 @@ The paper cites Paillier (EUROCRYPT 1999) without restating it, so the scheme
 below is the textbook one: with n = p q and g = n + 1,
 E(m; r) = g^m r^n mod n^2, D(c) = L(c^lambda mod n^2) mu mod n with
 L(u) = (u - 1) / n, lambda = lcm(p - 1, q - 1), mu = L(g^lambda mod n^2)^-1
-mod n; encrypted addition is the product of ciphertexts mod n^2.
+mod n; encrypted addition is the product of ciphertexts mod n^2, and
+encrypted subtraction (a node's histogram "minus" one child's, for the
+sibling) multiplies by the inverse mod n^2.
 
 Readings where the paper is silent (each is also listed in the design doc):
 key sizes 1024/2048 bits with p, q of exactly half the bits (top two bits set);
@@ -231,6 +233,13 @@ def encrypt(pk: PublicKey, m: int, r: int) -> int:
 def add(pk: PublicKey, c1: int, c2: int) -> int:
     """Encrypted addition: the product of two ciphertexts mod n^2."""
     return c1 * c2 % pk.n2
+
+
+def subtract(pk: PublicKey, c1: int, c2: int) -> int:
+    """Encrypted subtraction: c1 times the inverse of c2 mod n^2, an
+    encryption of m1 - m2 (the inverse of E(m; r) is E(-m; r^-1)).  Raises
+    ValueError when c2 is not a unit mod n^2."""
+    return c1 * pow(c2, -1, pk.n2) % pk.n2
 
 
 def decrypt(sk: PrivateKey, c: int) -> int:

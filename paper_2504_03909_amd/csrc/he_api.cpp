@@ -310,6 +310,23 @@ int he_encrypt_public(const he_key *key, const int64_t *m, uint64_t count, const
   return encrypt_impl(key, m, count, r, r_seed, r_offset, ct, stream, true);
 }
 
+int he_hist_subtract(const he_key *key, const uint32_t *parent, const uint32_t *child, uint64_t count,
+                     uint32_t batch, uint32_t *out, uint32_t *n_bad, hipStream_t stream) {
+  if (!key) return fail(HE_ERR_ARG, "null key");
+  if (count == 0) return HE_OK;
+  if (!parent || !child || !out) return fail(HE_ERR_ARG, "null parent, child or out");
+  const uint64_t bytes = count * (key->n_bits / 16) * sizeof(uint32_t);
+  auto overlap = [bytes](const void *x, const void *y) {
+    const uintptr_t a = (uintptr_t)x, b = (uintptr_t)y;
+    return a < b + bytes && b < a + bytes;
+  };
+  if (overlap(out, parent) || overlap(out, child)) return fail(HE_ERR_ARG, "out overlaps parent or child");
+  if (batch == 0) batch = he::ct_div_batch(count);
+  if ((count + batch - 1) / batch > (uint64_t)16 * 0x7FFFFFFF) return fail(HE_ERR_ARG, "batch too small");
+  HE_TRY_HIP(he::launch_ct_div(kp_of(key), key->dk, parent, child, count, batch, out, n_bad, stream));
+  return HE_OK;
+}
+
 int he_to_mont(const he_key *key, const uint32_t *in, uint64_t count, uint32_t *out, hipStream_t stream) {
   if (!key) return fail(HE_ERR_ARG, "null key");
   if (count == 0) return HE_OK;

@@ -279,6 +279,87 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_obf(DKey key, const int64
   if (valid) st<KN2>(ct + i * SN2, x);
 }
 
+// ------------------------------------------------------ ciphertext division
+// out[i] = num[i] den[i]^-1 mod n^2, i.e. an encryption of m_num - m_den.
+// Montgomery's batch-inversion trick per group of `batch` consecutive
+// elements: prefix products Q_j = Q_(j-1) a_j R^-1 (Q_0 = a_0, stored in
+// `out`), one inversion J = Q_last^-1 R, then backwards a_j^-1 R =
+// J Q_(j-1) R^-1 and J <- J a_j R^-1 = Q_(j-1)^-1 R -- four Montgomery
+// products per element plus one inversion per batch.  A batch whose product
+// is not invertible is redone element by element; elements whose den is
+// not a unit mod n^2 get 0 and are counted into *n_bad.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_ct_div(DKey key, const uint32_t *__restrict__ num,
+                                                         const uint32_t *__restrict__ den, uint64_t count,
+                                                         uint32_t batch, uint32_t *__restrict__ out,
+                                                         uint32_t *__restrict__ n_bad) {
+  constexpr int KN2 = 4 * KP, SN2 = 64 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SN2;
+  const uint64_t first = ((uint64_t)blockIdx.x * 16 + gi) * batch;
+  const uint32_t len = first < count ? (uint32_t)min((uint64_t)batch, count - first) : 0u;
+  const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
+
+  // forward: prefix products
+  uint32_t Q[KN2], a[KN2], t[KN2];
+  set_zero(Q);
+  set_zero(a);
+  if (len) {
+    ld<KN2>(Q, den + first * SN2);
+    st<KN2>(out + first * SN2, Q);
+  }
+#pragma unroll 1
+  for (uint32_t j = 1; j < batch; ++j) {
+    const bool v = j < len;
+    if (v) ld<KN2>(a, den + (first + j) * SN2);
+    mont_mul<KN2>(t, Q, a, M, lds);
+    select(Q, v, t, Q);
+    if (v) st<KN2>(out + (first + j) * SN2, Q);
+  }
+
+  uint32_t J[KN2];
+  const bool ok = mont_inverse<KN2>(J, Q, M, key.n2.R2, lds, len > 0u);
+
+  // backward
+  uint32_t p[KN2], ainv[KN2];
+  set_zero(p);
+#pragma unroll 1
+  for (uint32_t j = batch; j-- > 0u;) {
+    const bool v = ok && j < len;
+    if (j > 0u) {
+      if (v) ld<KN2>(t, out + (first + j - 1) * SN2);
+      mont_mul<KN2>(ainv, J, t, M, lds);
+      if (v) ld<KN2>(a, den + (first + j) * SN2);
+      mont_mul<KN2>(t, J, a, M, lds);
+      select(J, v, t, J);
+    } else {
+      copy(ainv, J);
+    }
+    if (v) ld<KN2>(p, num + (first + j) * SN2);
+    mont_mul<KN2>(p, p, ainv, M, lds);
+    if (v) st<KN2>(out + (first + j) * SN2, p);
+  }
+
+  // element-by-element retry for batches that held a non-unit
+  const bool retry = len > 0u && !ok;
+  if (wave_any(retry)) {
+#pragma unroll 1
+    for (uint32_t j = 0; j < batch; ++j) {
+      const bool v = retry && j < len;
+      if (v) {
+        ld<KN2>(a, den + (first + j) * SN2);
+        ld<KN2>(p, num + (first + j) * SN2);
+      }
+      const bool ok1 = mont_inverse<KN2>(J, a, M, key.n2.R2, lds, v);
+      mont_mul<KN2>(p, p, J, M, lds);
+      if (!ok1) set_zero(p);
+      if (v) st<KN2>(out + (first + j) * SN2, p);
+      if (v && !ok1 && glane() == 0 && n_bad) atomicAdd(n_bad, 1u);
+    }
+  }
+}
+
 // ------------------------------------------------------ Montgomery conversion
 template <int KP>
 __global__ __launch_bounds__(kBlockThreads) void k_mont_convert(DKey key, const uint32_t *in, uint64_t count,
@@ -787,6 +868,18 @@ hipError_t launch_enc_obf(int KP, const DKey &k, const int64_t *m, uint64_t coun
   return hipGetLastError();
 }
 
+hipError_t launch_ct_div(int KP, const DKey &k, const uint32_t *num, const uint32_t *den, uint64_t count,
+                         uint32_t batch, uint32_t *out, uint32_t *n_bad, hipStream_t s) {
+  if (!count) return hipSuccess;
+  const uint64_t groups = (count + batch - 1) / batch;
+  const dim3 grid(blocks_for(groups, 16));
+  if (KP == 1)
+    hipLaunchKernelGGL(k_ct_div<1>, grid, dim3(kBlockThreads), 0, s, k, num, den, count, batch, out, n_bad);
+  else
+    hipLaunchKernelGGL(k_ct_div<2>, grid, dim3(kBlockThreads), 0, s, k, num, den, count, batch, out, n_bad);
+  return hipGetLastError();
+}
+
 hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64_t count,
                                uint32_t *out, bool to_mont, hipStream_t s) {
   if (!count) return hipSuccess;
@@ -865,6 +958,20 @@ static uint32_t occupancy_blocks(const void *fn) {
   hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlockThreads, 0) != hipSuccess || nb < 1) nb = 1;
   return (uint32_t)(nb * std::max(cus, 1));
+}
+
+// Elements per inversion batch of k_ct_div: enough groups for about two
+// waves per SIMD, each group then chains as many elements as needed.
+uint32_t ct_div_batch(uint64_t count) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 1;
+  }
+  const uint64_t groups = (uint64_t)cus * 4 * 2 * 4;
+  return (uint32_t)std::max<uint64_t>(1, (count + groups - 1) / groups);
 }
 
 static int gidx(int G) { return G == 4 ? 0 : (G == 8 ? 1 : 2); }

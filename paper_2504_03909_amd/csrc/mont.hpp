@@ -480,6 +480,203 @@ __device__ __forceinline__ void sub_mod(uint32_t (&t)[K], const uint32_t (&x)[K]
   select(t, neg, w, t);
 }
 
+// ---- shifts and tests ----------------------------------------------------------
+__device__ __forceinline__ bool wave_any(bool v) { return __builtin_amdgcn_ballot_w64(v) != 0ull; }
+
+// Group-uniform: x == 0.
+template <int K, int G = 16>
+__device__ __forceinline__ bool is_zero(const uint32_t (&x)[K]) {
+  bool nz = false;
+#pragma unroll
+  for (int j = 0; j < K; ++j) nz = nz || x[j] != 0u;
+  return !row_any<G>(nz);
+}
+// Group-uniform: x == 1.
+template <int K, int G = 16>
+__device__ __forceinline__ bool is_one(const uint32_t (&x)[K]) {
+  bool bad = false;
+#pragma unroll
+  for (int j = 0; j < K; ++j) bad = bad || x[j] != ((j == 0 && glane<G>() == 0) ? 1u : 0u);
+  return !row_any<G>(bad);
+}
+// (hi:lo) >> t for 0 <= t <= 32 (v_alignbit_b32; written out, the 64-bit
+// form gets turned into unaligned loads from a stack copy of the array).
+__device__ __forceinline__ uint32_t funnel_r(uint32_t hi, uint32_t lo, uint32_t t) {
+  return t >= 32u ? hi : __builtin_amdgcn_alignbit(hi, lo, t);
+}
+// x >>= t for 0 <= t <= 32 (group-uniform t); the bits entering at the top
+// come from `top` (read in the group's last lane).
+template <int K, int G = 16>
+__device__ __forceinline__ void shr_bits(uint32_t (&x)[K], uint32_t t, uint32_t top = 0u) {
+  uint32_t hi = from_next<G>(x[0]);
+  if (glane<G>() == G - 1) hi = top;
+#pragma unroll
+  for (int j = 0; j + 1 < K; ++j) x[j] = funnel_r(x[j + 1], x[j], t);
+  x[K - 1] = funnel_r(hi, x[K - 1], t);
+}
+// x <<= t for 0 <= t <= 32 (group-uniform t); bits above limb S are dropped.
+template <int K, int G = 16>
+__device__ __forceinline__ void shl_bits(uint32_t (&x)[K], uint32_t t) {
+  const uint32_t lo = from_prev<G>(x[K - 1]);
+  if (t == 0u) return;
+#pragma unroll
+  for (int j = K - 1; j > 0; --j) x[j] = __builtin_amdgcn_alignbit(x[j], x[j - 1], 32u - t);
+  x[0] = __builtin_amdgcn_alignbit(x[0], lo, 32u - t);
+}
+// If z: x >>= 32 (resp. x <<= 32, dropping the top limb).
+template <int K, int G = 16>
+__device__ __forceinline__ void shr_limb_if(uint32_t (&x)[K], bool z) {
+  const uint32_t hi = from_next<G>(x[0]);
+#pragma unroll
+  for (int j = 0; j + 1 < K; ++j) x[j] = z ? x[j + 1] : x[j];
+  x[K - 1] = z ? hi : x[K - 1];
+}
+template <int K, int G = 16>
+__device__ __forceinline__ void shl_limb_if(uint32_t (&x)[K], bool z) {
+  const uint32_t lo = from_prev<G>(x[K - 1]);
+#pragma unroll
+  for (int j = K - 1; j > 0; --j) x[j] = z ? x[j - 1] : x[j];
+  x[0] = z ? lo : x[0];
+}
+// Trailing zero bits of the group's lowest limb (0 if that limb is 0).
+template <int G = 16>
+__device__ __forceinline__ uint32_t low_ctz(uint32_t x0) {
+  const uint32_t lo = bcast_first<G>(x0);
+  return lo ? (uint32_t)__builtin_ctz(lo) : 0u;
+}
+
+// ---- inversion --------------------------------------------------------------------
+// Kaliski's almost-inverse ("The Montgomery inverse and its applications",
+// IEEE Trans. Computers 1995), phase one, for odd N and 0 < y < N:
+// x = y^-1 2^k mod N.  The state u, v, r, s keeps u s + v r = N,
+// y s = v 2^k and y r = -u 2^k (mod N); each step subtracts the smaller of
+// the odd pair u, v from the larger and shifts every trailing zero of the
+// difference out at once (doubling r or s as often), so log2(u v) drops by at
+// least one per step and the loop ends within 2 log2 N + 1 steps with u = v =
+// gcd(y, N).  When that gcd is 1, x = N - r.  Nothing here is secret (the
+// operands are public ciphertexts), so the running time may depend on them.
+// Returns (group-uniform) whether y was invertible; `active` false skips the
+// group (it still takes part in the wave's cross-lane steps).
+template <int K, int G = 16>
+__device__ __forceinline__ bool almost_inverse(uint32_t (&x)[K], uint32_t &k, const uint32_t (&y)[K],
+                                               const Mod<K> &M, bool active) {
+  uint32_t u[K], v[K], r[K], s[K];
+  copy(u, M.n);
+  copy(v, y);
+  set_zero(r);
+  set_small<K, G>(s, 1u);
+  k = 0;
+  bool live = active && !is_zero<K, G>(y);
+  bool met = false;  // the loop ended with u == v
+  // make v odd: while r = 0, halving v only adds to k
+  while (wave_any(live && bcast_first<G>(v[0]) == 0u)) {
+    const bool z = live && bcast_first<G>(v[0]) == 0u;
+    shr_limb_if<K, G>(v, z);
+    k += z ? 32u : 0u;
+  }
+  {
+    const uint32_t t = live ? low_ctz<G>(v[0]) : 0u;
+    shr_bits<K, G>(v, t);
+    k += t;
+  }
+  constexpr int kCap = 2 * 32 * G * K + 2;
+#pragma unroll 1
+  for (int it = 0; it < kCap; ++it) {
+    if (!wave_any(live)) break;
+    // d = |u - v|: the larger of the odd pair minus the smaller
+    uint32_t d[K];
+    const bool lt = bcast_last<G>(sub_plain<K, G>(d, u, v) ? 1u : 0u) != 0u;  // u < v
+    {
+      uint32_t e[K];
+      sub_plain<K, G>(e, v, u);
+      select(d, lt, e, d);
+    }
+    const bool eq = is_zero<K, G>(d);
+    met = met || (live && eq);
+    live = live && !eq;
+    // the larger one's coefficient gains the other's (p); the other's is
+    // doubled once per bit shifted out of d (q)
+    uint32_t p[K], q[K];
+    select(p, lt, s, r);
+    select(q, lt, r, s);
+    add_plain<K, G>(p, p, q);
+    while (wave_any(live && bcast_first<G>(d[0]) == 0u)) {
+      const bool z = live && bcast_first<G>(d[0]) == 0u;
+      shr_limb_if<K, G>(d, z);
+      shl_limb_if<K, G>(q, z);
+      k += z ? 32u : 0u;
+    }
+    const uint32_t t = live ? low_ctz<G>(d[0]) : 0u;
+    shr_bits<K, G>(d, t);
+    shl_bits<K, G>(q, t);
+    k += t;
+    const bool lu = live && !lt, lv = live && lt;
+#pragma unroll
+    for (int j = 0; j < K; ++j) {
+      u[j] = lu ? d[j] : u[j];
+      v[j] = lv ? d[j] : v[j];
+      r[j] = lu ? p[j] : (lv ? q[j] : r[j]);
+      s[j] = lu ? q[j] : (lv ? p[j] : s[j]);
+    }
+  }
+  sub_plain<K, G>(x, M.n, r);
+  return met && is_one<K, G>(u);
+}
+
+// x <- x 2^-k mod N for x < N (group-uniform k): up to 32 bits per step,
+// x = (x + q N) / 2^j with q = -x N^-1 mod 2^j, which stays below N.
+template <int K, int G = 16>
+__device__ __forceinline__ void div_pow2(uint32_t (&x)[K], uint32_t k, const Mod<K> &M) {
+#pragma unroll 1
+  for (;;) {
+    const bool act = k > 0u;
+    if (!wave_any(act)) break;
+    const uint32_t j = k >= 32u ? 32u : k;
+    const uint32_t mask = j >= 32u ? 0xFFFFFFFFu : ((1u << j) - 1u);
+    const uint32_t q = act ? (bcast_first<G>(mul_lo32(x[0], M.ninv)) & mask) : 0u;
+    uint32_t t[K];
+    uint32_t c = 0;
+#pragma unroll
+    for (int i = 0; i < K; ++i) {
+      const uint64_t w = (uint64_t)q * M.n[i] + x[i] + c;
+      t[i] = (uint32_t)w;
+      c = (uint32_t)(w >> 32);
+    }
+    // the lane's carry word goes into the next lane's lowest limb
+    const uint32_t cin = from_prev<G>(c);
+    unsigned b;
+    t[0] = __builtin_addc(t[0], cin, 0u, &b);
+#pragma unroll
+    for (int i = 1; i < K; ++i) t[i] = __builtin_addc(t[i], 0u, b, &b);
+    const bool gen = b;
+    bool prop = true;
+#pragma unroll
+    for (int i = 0; i < K; ++i) prop = prop && (t[i] == 0xFFFFFFFFu);
+    unsigned b2 = carry_in<G>(gen, prop);
+#pragma unroll
+    for (int i = 0; i < K; ++i) t[i] = __builtin_addc(t[i], 0u, b2, &b2);
+    const uint32_t top = c + (uint32_t)gen + b2;  // x + q N < 2^j N: one word above limb S
+    shr_bits<K, G>(t, j, top);
+    select(x, act, t, x);
+    k -= act ? j : 0u;
+  }
+}
+
+// J = y^-1 R mod N (R = 2^(32 S), i.e. the Montgomery form of y^-1) for
+// 0 < y < N coprime to N; returns false (group-uniform) otherwise.  R2 points
+// to R^2 mod N (S limbs).
+template <int K, int G = 16>
+__device__ __forceinline__ bool mont_inverse(uint32_t (&J)[K], const uint32_t (&y)[K], const Mod<K> &M,
+                                             const uint32_t *R2, uint32_t *lds, bool active) {
+  uint32_t k;
+  const bool ok = almost_inverse<K, G>(J, k, y, M, active);
+  div_pow2<K, G>(J, ok ? k : 0u, M);
+  uint32_t r2[K];
+  ld<K, G>(r2, R2);
+  mont_mul<K, G>(J, J, r2, M, lds);
+  return ok;
+}
+
 // ---- low-half product ----------------------------------------------------------
 // t = a * b mod 2^(32 S), with a from this group's LDS copy and b in registers.
 // (Used for the exact division x / P = x * P^-1 mod 2^(32 S) when P | x.)

@@ -27,7 +27,7 @@ EXPORTED = (
     "he_key_free", "he_encode", "he_encrypt", "he_encrypt_public", "he_to_mont", "he_from_mont",
     "he_hist_aggregate", "he_hist_aggregate_ex", "he_decrypt", "he_probe_int_mul", "he_last_error",
     "he_hist_autotune", "he_hist_plan_create", "he_hist_plan_launch", "he_hist_plan_free",
-    "he_obfuscators", "he_encrypt_obfuscated",
+    "he_obfuscators", "he_encrypt_obfuscated", "he_hist_subtract",
 )
 
 
@@ -72,6 +72,7 @@ _encrypt = _sig("he_encrypt", _i32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp])
 _encrypt_pub = _sig("he_encrypt_public", _i32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp])
 _obf = _sig("he_obfuscators", _i32, [_vp, _u64, _vp, _u64, _u64, _vp, _vp])
 _enc_obf = _sig("he_encrypt_obfuscated", _i32, [_vp, _vp, _u64, _vp, _vp, _vp])
+_sub = _sig("he_hist_subtract", _i32, [_vp, _vp, _vp, _u64, _u32, _vp, _vp, _vp])
 _to_mont = _sig("he_to_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
 _from_mont = _sig("he_from_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
 _hist = _sig("he_hist_aggregate_ex", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32, _u32, _vp])
@@ -238,6 +239,18 @@ def encrypt_obfuscated(key: Key, m: torch.Tensor, rho: torch.Tensor, out: Option
     if out is None:
         out = torch.empty((*m.shape, 2 * key.limbs), dtype=torch.int32, device=m.device)
     _check(_enc_obf(key.handle, _ptr(m), m.numel(), _ptr(rho.contiguous()), _ptr(out), _stream(stream)))
+    return out
+
+
+def hist_subtract(key: Key, parent: torch.Tensor, child: torch.Tensor, out: Optional[torch.Tensor] = None,
+                  batch: int = 0, n_bad: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """parent * child^-1 mod n^2 elementwise (an encryption of m_parent - m_child)."""
+    assert parent.shape == child.shape and parent.shape[-1] == 2 * key.limbs
+    parent, child = parent.contiguous(), child.contiguous()
+    if out is None:
+        out = torch.empty_like(parent)
+    count = parent.numel() // (2 * key.limbs)
+    _check(_sub(key.handle, _ptr(parent), _ptr(child), count, batch, _ptr(out), _ptr(n_bad), _stream(stream)))
     return out
 
 

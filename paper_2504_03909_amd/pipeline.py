@@ -56,7 +56,13 @@ def aggregate_levels(res: Resident, levels: Sequence[Sequence[torch.Tensor]], bi
     mode "per_node": one he_hist_aggregate call (one job) per node -- the
     plain one-job-per-launch path.  mode "per_level": all nodes of a level in
     one batched call.  mode "per_level_graph": all nodes of a level in one
-    captured plan, replayed with a single graph launch."""
+    captured plan, replayed with a single graph launch.  modes "sibling" and
+    "sibling_graph": per level, only the smaller child of every parent is
+    aggregated (batched, resp. as a captured plan) and the larger one is the
+    parent's histogram divided by it (``he.hist_subtract``); the children of
+    node i of one level are nodes 2i and 2i + 1 of the next."""
+    if mode in ("sibling", "sibling_graph"):
+        return _sibling_levels(res, levels, bins, n_bins, chunk, mode == "sibling_graph", stream)
     run = TreeRun()
     for lvl in levels:
         jobs = [node_job(idx, bins, n_bins) for idx in lvl]
@@ -78,3 +84,46 @@ def aggregate_levels(res: Resident, levels: Sequence[Sequence[torch.Tensor]], bi
 def decrypt_levels(key: he.Key, run: TreeRun, stream=None) -> List[List[torch.Tensor]]:
     """Signed int64 histograms [F, B, 2] of every node."""
     return [[he.decrypt(key, h, stream=stream)[0] for h in lvl] for lvl in run.hists]
+
+
+def _sibling_levels(res: Resident, levels: Sequence[Sequence[torch.Tensor]], bins: torch.Tensor,
+                    n_bins: int, chunk: int, graph: bool, stream) -> TreeRun:
+    # Histograms of a level live in one buffer [slots, F, B, 2, 2L] whose
+    # slots are ordered [smaller children of every parent slot..., larger
+    # children...], so the next level's parents are one contiguous array
+    # and the whole level's subtraction is one call.
+    key = res.key
+    F = bins.shape[0]
+    shape = (F, n_bins, 2, 2 * key.limbs)
+    run = TreeRun()
+
+    def aggregate(jobs):
+        if graph:
+            plan = he.HistPlan(key, res.ctm, jobs, form=he.HE_FORM_MONT, chunk=chunk)
+            plan.launch(stream)
+            run.plans.append(plan)
+        else:
+            he.hist_aggregate(key, res.ctm, jobs, form=he.HE_FORM_MONT, chunk=chunk, stream=stream)
+
+    buf = torch.empty((1, *shape), dtype=torch.int32, device=res.ctm.device)
+    aggregate([he.Job(levels[0][0], bins, n_bins, hist=buf[0])])
+    run.hists.append([buf[0]])
+    slot_node = [0]
+    for lvl in levels[1:]:
+        P = len(slot_node)
+        nxt = torch.empty((2, P, *shape), dtype=torch.int32, device=buf.device)
+        node_hist: List[Optional[torch.Tensor]] = [None] * len(lvl)
+        jobs, small, large = [], [], []
+        for s, u in enumerate(slot_node):
+            a, b = 2 * u, 2 * u + 1
+            sm, lg = (a, b) if lvl[a].numel() <= lvl[b].numel() else (b, a)
+            jobs.append(he.Job(lvl[sm], bins, n_bins, hist=nxt[0, s]))
+            node_hist[sm], node_hist[lg] = nxt[0, s], nxt[1, s]
+            small.append(sm)
+            large.append(lg)
+        aggregate(jobs)
+        he.hist_subtract(key, buf, nxt[0], out=nxt[1], stream=stream)
+        buf = nxt.view(2 * P, *shape)
+        slot_node = small + large
+        run.hists.append(node_hist)
+    return run

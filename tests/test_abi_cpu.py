@@ -57,6 +57,10 @@ def test_host_side_argument_errors(lib):
     assert lib.he_encrypt(None, None, 0, None, 0, 0, None, None) == -1
     lib.he_decrypt.argtypes = [ctypes.c_void_p] * 7
     assert lib.he_decrypt(None, None, None, None, None, None, None) == -1
+    lib.he_hist_subtract.argtypes = [ctypes.c_void_p] * 3 + [ctypes.c_uint64, ctypes.c_uint32] + [ctypes.c_void_p] * 3
+    assert lib.he_hist_subtract(None, None, None, 1, 0, None, None, None) == -1
+    lib.he_encrypt_obfuscated.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_uint64] + [ctypes.c_void_p] * 3
+    assert lib.he_encrypt_obfuscated(None, None, 1, None, None, None) == -1
     lib.he_probe_int_mul.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
     assert lib.he_probe_int_mul(0, 0, None, None) == -1
 

@@ -209,8 +209,9 @@ def test_batched_64_jobs_2048(he):
 
 def test_tree_depth6_full_size(he):
     """2048-bit key, 1,000,000 samples, 64 features x 256 Zipf bins, depth-6
-    tree (63 nodes, seeded splits): one job per launch and one captured plan
-    per level give identical histograms; every node's decrypted histogram
+    tree (63 nodes, seeded splits): one job per launch, one captured plan per
+    level and the sibling mode (smaller child aggregated, larger one the
+    parent divided by it) give identical histograms; every node's decrypted histogram
     equals the oracle's sums; sampled slots are bit-exact in closed form."""
     import torch
     from paper_2504_03909_amd import pipeline
@@ -227,9 +228,12 @@ def test_tree_depth6_full_size(he):
     lv_d = [[dev(n.view(np.int32)) for n in lvl] for lvl in levels]
     plain = pipeline.aggregate_levels(res, lv_d, bins_d, K, mode="per_node")
     graph = pipeline.aggregate_levels(res, lv_d, bins_d, K, mode="per_level_graph")
-    for la, lb in zip(plain.hists, graph.hists):
-        for a, b in zip(la, lb):
-            assert torch.equal(a, b)
+    sib = pipeline.aggregate_levels(res, lv_d, bins_d, K, mode="sibling")
+    for other in (graph, sib):
+        for la, lb in zip(plain.hists, other.hists):
+            for a, b in zip(la, lb):
+                assert torch.equal(a, b)
+    del graph, sib
     dec = pipeline.decrypt_levels(k, plain)
     m = np.rint(g * 2.0 ** 32).astype(np.int64)
     rng = np.random.default_rng(0)

@@ -114,6 +114,66 @@ def test_homomorphic_product_is_encryption_of_sum(bits, seed):
         assert P.decode(P.decrypt(sk, lhs), pk.n) == a + b
 
 
+def test_toy_subtract_inverts_every_unit():
+    # For every unit c mod 143^2, subtract(1, c) is the c' with c c' = 1,
+    # found here by search over the unit group for a sample of c.
+    pk = TOY.public
+    n2 = pk.n2
+    units = [c for c in range(1, n2) if math.gcd(c, n2) == 1]
+    for c in units:
+        assert P.subtract(pk, 1, c) * c % n2 == 1
+    for c in units[::997]:
+        assert [x for x in units if x * c % n2 == 1] == [P.subtract(pk, 1, c)]
+    for bad in (0, 11, 13 * 5, 143):
+        with pytest.raises(ValueError):
+            P.subtract(pk, 1, bad)
+
+
+@pytest.mark.parametrize("bits,seed", [(256, 3), (1024, 1)])
+def test_subtract_closed_form(bits, seed):
+    # E(a; r1) / E(b; r2) = E(a - b; r1 r2^-1 mod n), bit for bit, and it
+    # decrypts to a - b; dividing a product by one factor gives the other.
+    sk = real_key(bits, seed)
+    pk = sk.public
+    rng = random.Random(13)
+    for _ in range(20):
+        a, b = rng.randrange(-(1 << 40), 1 << 40), rng.randrange(-(1 << 40), 1 << 40)
+        r1, r2 = rng.randrange(1, pk.n), rng.randrange(1, pk.n)
+        c1, c2 = P.encrypt(pk, a, r1), P.encrypt(pk, b, r2)
+        d = P.subtract(pk, c1, c2)
+        # r2^-1 mod n from the extended Euclidean identity u r2 + v n = 1
+        u, v, x0, x1 = r2, pk.n, 1, 0
+        while v:
+            qq = u // v
+            u, v, x0, x1 = v, u - qq * v, x1, x0 - qq * x1
+        assert u == 1
+        assert d == P.encrypt(pk, a - b, r1 * (x0 % pk.n) % pk.n)
+        assert P.decode(P.decrypt(sk, d), pk.n) == a - b
+        assert P.subtract(pk, P.add(pk, c1, c2), c2) == c1
+
+
+def test_subtract_histograms_gives_sibling():
+    # A parent node's samples split into two children: the parent's encrypted
+    # histogram divided by one child's equals the other child's, slot by slot.
+    sk = real_key(256, 3)
+    pk = sk.public
+    rng = np.random.default_rng(5)
+    M, F, B = 60, 3, 5
+    rs = W.random_units(pk.n, 2 * M, rng)
+    ct = [[P.encrypt(pk, int(rng.integers(-1000, 1000)), rs[2 * i + t]) for t in range(2)] for i in range(M)]
+    bins = rng.integers(0, B, size=(F, M)).tolist()
+    parent = rng.choice(M, size=40, replace=False)
+    left = parent[rng.random(40) < 0.4]
+    right = np.setdiff1d(parent, left)
+    hp = P.aggregate(pk, ct, parent, bins, F, B)
+    hl = P.aggregate(pk, ct, left, bins, F, B)
+    hr = P.aggregate(pk, ct, right, bins, F, B)
+    for f in range(F):
+        for b in range(B):
+            for t in range(2):
+                assert P.subtract(pk, hp[f][b][t], hl[f][b][t]) == hr[f][b][t]
+
+
 @pytest.mark.parametrize("bits,seed", [(256, 3), (1024, 1)])
 def test_decrypt_equals_crt_decryption(bits, seed):
     # Independent route: per prime, m_p = L_p(c^(p-1) mod p^2) h_p mod p with

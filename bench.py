@@ -36,6 +36,12 @@ KEY_SEED, R_SEED, DATA_SEED = 2, 2024, 1
 # (v_mad_u64_u32) per lane per clock.
 PEAK_MUL32_PER_S = 256 * 64 * 2.4e9
 MI355X_HBM_BPS = 8.0e12
+# HBM-side bytes of one encryption launch (k_enc_crt_a + k_enc_crt_b over
+# 200,000 ciphertexts), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled
+# by a 256 MiB copy (profiles/enc_crt_2048_100k_counters.md).  Valid for the
+# kernel build those passes ran on; set to None when the encryption kernels
+# change until the passes are repeated.
+ENC_LAUNCH_TRAFFIC_BYTES = 3.0656e10
 
 
 def mm_products(s: int) -> int:
@@ -234,6 +240,23 @@ def main():
             np.add.at(ref, bins_h[f].astype(np.int64), mo[:, t])
             ok = ok and np.array_equal(ref, dmh[f, :, t])
 
+    # Encryption split into an offline part (obfuscators r^n mod n^2, which do
+    # not depend on the gradients) and an online part (three Montgomery
+    # products per value).  Reported beside the step, not inside it.
+    m_last = he.encode(grads)
+    rho = he.obfuscators(key, 2 * M, seed=R_SEED)
+    ct_obf = he.encrypt_obfuscated(key, m_last, rho)
+    obf_marks = [ev() for _ in range(3)]
+    obf_marks[0].record(stream)
+    he.obfuscators(key, 2 * M, seed=R_SEED, out=rho)
+    obf_marks[1].record(stream)
+    he.encrypt_obfuscated(key, m_last, rho, out=ct_obf)
+    obf_marks[2].record(stream)
+    torch.cuda.synchronize()
+    obf_same = bool(torch.equal(ct_obf, ct.view(-1, 2 * L)))
+    t_off, t_on = obf_marks[0].elapsed_time(obf_marks[1]), obf_marks[1].elapsed_time(obf_marks[2])
+    del rho, ct_obf
+
     enc_products = crt_encrypt_products(p, q, L)
     achieved = 2 * M * enc_products / (avg["encrypt"] / 1e3)
     line = {
@@ -280,11 +303,19 @@ def main():
             "peak": round(PEAK_MUL32_PER_S / 1e12, 3),
             "unit": "T mul32/s",
             "frac": round(achieved / PEAK_MUL32_PER_S, 4),
-            "traffic": None,
+            "traffic": ENC_LAUNCH_TRAFFIC_BYTES,
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "algorithmic_bytes_per_launch": 2 * M * (8 + 4 * 2 * L),
             "algorithmic_products_per_launch": 2 * M * enc_products,
             "products_per_ciphertext": enc_products,
         },
         "parity_self_check": bool(ok),
+        "obfuscated_encryption": {
+            "offline_obfuscators_ms": round(t_off, 3),
+            "online_encrypt_ms": round(t_on, 3),
+            "online_encryptions_per_s": round(2 * M / (t_on / 1e3), 1),
+            "equals_encrypt": obf_same,
+        },
     }
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(p, q, grads_h, bins_h)

@@ -224,9 +224,11 @@ def encrypt(key: Key, m: torch.Tensor, r: Optional[torch.Tensor] = None, seed: i
 
 
 def obfuscators(key: Key, count: int, r: Optional[torch.Tensor] = None, seed: int = 0, offset: int = 0,
-                stream=None, device="cuda") -> torch.Tensor:
+                out: Optional[torch.Tensor] = None, stream=None, device="cuda") -> torch.Tensor:
     """r_i^n mod n^2 for the same r as encrypt(seed=..., offset=...) -> int32 [count, 2L]."""
-    out = torch.empty((count, 2 * key.limbs), dtype=torch.int32, device=device)
+    if out is None:
+        out = torch.empty((count, 2 * key.limbs), dtype=torch.int32, device=device)
+    assert out.is_contiguous() and out.numel() == count * 2 * key.limbs
     _check(_obf(key.handle, count, _ptr(r), seed, offset, _ptr(out), _stream(stream)))
     return out
 

@@ -374,6 +374,16 @@ def bench_tree(args):
     sub_ms = ev[0].elapsed_time(ev[1])
     n_sub = par.numel() // (2 * key.limbs)
     _, t_dec = _timed(lambda: pipeline.decrypt_levels(key, run_plain), "tree decrypt")
+    # whole rounds: aggregation + decryption + split finding, three ways
+    rounds, round_splits = {}, {}
+    for mode in (None, "encrypted", "plain"):
+        rr, tr = _timed(lambda: pipeline.tree_round(res, key, levels, bins, Kt, sibling=mode),
+                        f"tree round sibling={mode}")
+        rounds[str(mode)] = round(tr, 3)
+        round_splits[str(mode)] = rr.splits
+        del rr
+    rounds_same = all(torch.equal(a[k], b[k]) for m in ("encrypted", "plain")
+                      for a, b in zip(round_splits["None"], round_splits[m]) for k in a)
     contrib = 2 * Jt * sum(int(n.numel()) for lvl in levels for n in lvl)
     contrib_sib = 2 * Jt * (Mt + sum(min(int(lvl[i].numel()), int(lvl[i + 1].numel()))
                                      for lvl in levels[1:] for i in range(0, len(lvl), 2)))
@@ -396,6 +406,9 @@ def bench_tree(args):
         "sibling_equals_plain": bool(sib_same),
         "subtract_524288_ms": round(sub_ms, 3),
         "subtract_per_s": round(n_sub / (sub_ms / 1e3), 1),
+        "round_s": {"direct": rounds["None"], "sibling_encrypted": rounds["encrypted"],
+                    "sibling_plain": rounds["plain"]},
+        "round_splits_identical": bool(rounds_same),
         "total_s_one_job_per_launch": round(t_enc + t_plain + t_dec, 3),
     }
 

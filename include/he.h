@@ -225,6 +225,33 @@ void he_hist_plan_free(he_hist_plan *plan);
 int he_hist_subtract(const he_key *key, const uint32_t *parent, const uint32_t *child, uint64_t count,
                      uint32_t batch, uint32_t *out, uint32_t *n_bad, hipStream_t stream);
 
+/* Split finding, the active party's step after decryption (Sec. III-B: the
+ * decrypted histograms go to tree building).  The criterion is XGBoost's
+ * split gain (Chen & Guestrin 2016): splitting a feature's bins after bin b
+ * sends bins 0..b left, and
+ *   gain = 1/2 [G_L^2/(H_L+lambda) + G_R^2/(H_R+lambda) - G^2/(H+lambda)] - gamma,
+ * admissible when H_L, H_R >= min_child_weight and H_L+lambda, H_R+lambda > 0.
+ * Sums are exact int64 (prefix sums), converted to double and scaled by
+ * 2^-frac_bits; the gain is evaluated in IEEE double exactly as written (no
+ * fused multiply-add).  Ties: the lowest bin, then the lowest feature; no
+ * admissible split gives gain -inf, feature and bin -1.
+ * hist: device int64 [nodes][F][B][2] (G, H sums, e.g. he_decrypt's output).
+ * minus: optional, same shape: the node's histogram is hist - minus (a
+ *   larger sibling from its parent and the smaller child, in plaintext).
+ * derived: optional, same shape, receives the histogram used (may alias hist).
+ * out_feature: optional device he_split [nodes][F]; out_node: device he_split [nodes].
+ * B must be in [1, 256]. */
+typedef struct he_split {
+  double gain;
+  int32_t feature; /* -1: no admissible split */
+  int32_t bin;     /* left = bins 0..bin */
+  int64_t g_left;  /* fixed-point sums of the left side */
+  int64_t h_left;
+} he_split;
+int he_split_find(const int64_t *hist, const int64_t *minus, uint32_t nodes, uint32_t n_features, uint32_t n_bins,
+                  uint32_t frac_bits, double lambda, double gamma, double min_child_weight, int64_t *derived,
+                  he_split *out_feature, he_split *out_node, hipStream_t stream);
+
 /* Decryption (Sec. III-B: the active party decrypts the returned
  * histograms), by the CRT: m_p = L_p(c^(p-1) mod p^2) h_p mod p with
  * h_p = (-q mod p)^-1 mod p, likewise m_q, then m = m_q + q ((m_p - m_q)

@@ -5,6 +5,7 @@
 #include <stdint.h>
 #include <string.h>
 
+#include <cmath>
 #include <map>
 #include <tuple>
 #include <mutex>
@@ -324,6 +325,22 @@ int he_hist_subtract(const he_key *key, const uint32_t *parent, const uint32_t *
   if (batch == 0) batch = he::ct_div_batch(count);
   if ((count + batch - 1) / batch > (uint64_t)16 * 0x7FFFFFFF) return fail(HE_ERR_ARG, "batch too small");
   HE_TRY_HIP(he::launch_ct_div(kp_of(key), key->dk, parent, child, count, batch, out, n_bad, stream));
+  return HE_OK;
+}
+
+static_assert(sizeof(he_split) == 32, "he_split layout");
+
+int he_split_find(const int64_t *hist, const int64_t *minus, uint32_t nodes, uint32_t n_features, uint32_t n_bins,
+                  uint32_t frac_bits, double lambda, double gamma, double min_child_weight, int64_t *derived,
+                  he_split *out_feature, he_split *out_node, hipStream_t stream) {
+  if (nodes == 0 || n_features == 0) return HE_OK;
+  if (!hist || !out_node) return fail(HE_ERR_ARG, "null hist or out_node");
+  if (n_bins < 1 || n_bins > 256) return fail(HE_ERR_ARG, "n_bins must be in [1, 256]");
+  if (frac_bits > 62) return fail(HE_ERR_ARG, "frac_bits must be at most 62");
+  if (!(lambda >= 0.0) || !(min_child_weight >= 0.0) || !(gamma == gamma))
+    return fail(HE_ERR_ARG, "lambda and min_child_weight must be >= 0, gamma a number");
+  HE_TRY_HIP(he::launch_split(hist, minus, nodes, n_features, n_bins, std::ldexp(1.0, -(int)frac_bits), lambda,
+                              gamma, min_child_weight, derived, out_feature, out_node, stream));
   return HE_OK;
 }
 

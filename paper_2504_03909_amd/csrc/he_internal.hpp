@@ -101,6 +101,9 @@ hipError_t launch_enc_obf(int KP, const DKey &k, const int64_t *m, uint64_t coun
 uint32_t ct_div_batch(uint64_t count);
 hipError_t launch_ct_div(int KP, const DKey &k, const uint32_t *num, const uint32_t *den, uint64_t count,
                          uint32_t batch, uint32_t *out, uint32_t *n_bad, hipStream_t s);
+hipError_t launch_split(const int64_t *hist, const int64_t *minus, uint32_t nodes, uint32_t F, uint32_t B,
+                        double scale, double lam, double gamma, double mcw, int64_t *derived, void *out_feat,
+                        void *out_node, hipStream_t s);
 hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64_t count,
                                uint32_t *out, bool to_mont, hipStream_t s);
 hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count,

@@ -360,6 +360,119 @@ __global__ __launch_bounds__(kBlockThreads) void k_ct_div(DKey key, const uint32
   }
 }
 
+// ------------------------------------------------------ split finding
+// Best split per (node, feature) and per node from decrypted histograms:
+// exact int64 prefix sums over the bins, XGBoost's gain in IEEE double with
+// no contraction (every operation rounded as written), the largest gain with
+// the lowest bin, then the lowest feature, on ties.  One block per node; each
+// wave takes every fourth feature, lane l holds bins 4l .. 4l + 3.
+struct SplitCand {
+  double gain;
+  int32_t feature, bin;
+  int64_t gl, hl;
+};
+
+__device__ __forceinline__ bool split_better(const SplitCand &a, const SplitCand &b, bool by_feature) {
+  if (a.gain > b.gain) return true;
+  if (a.gain < b.gain || a.bin < 0) return false;
+  if (b.bin < 0) return true;
+  return by_feature ? a.feature < b.feature : a.bin < b.bin;
+}
+
+__device__ __forceinline__ SplitCand shfl_xor_cand(const SplitCand &c, int m) {
+  SplitCand o;
+  o.gain = __shfl_xor(c.gain, m, 64);
+  o.feature = __shfl_xor(c.feature, m, 64);
+  o.bin = __shfl_xor(c.bin, m, 64);
+  o.gl = __shfl_xor(c.gl, m, 64);
+  o.hl = __shfl_xor(c.hl, m, 64);
+  return o;
+}
+
+__device__ __forceinline__ double split_term(double g, double h, double lam) {
+#pragma clang fp contract(off)
+  return (g * g) / (h + lam);
+}
+
+__global__ __launch_bounds__(kBlockThreads) void k_split(const int64_t *hist, const int64_t *minus, uint32_t F,
+                                                        uint32_t B, double scale, double lam, double gamma,
+                                                        double mcw, int64_t *derived, SplitCand *out_feat,
+                                                        SplitCand *out_node) {
+#pragma clang fp contract(off)
+  __shared__ SplitCand waves[kBlockThreads / 64];
+  const uint64_t node = blockIdx.x;
+  const uint32_t w = threadIdx.x >> 6, lane = threadIdx.x & 63u;
+  const SplitCand none = {-__builtin_inf(), -1, -1, 0, 0};
+  SplitCand best = none;
+  for (uint32_t f = w; f < F; f += kBlockThreads / 64) {
+    const uint64_t base = (node * F + f) * (uint64_t)B * 2;
+    int64_t g[4], h[4], sg = 0, sh = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t b = lane * 4 + k;
+      g[k] = h[k] = 0;
+      if (b < B) {
+        g[k] = hist[base + 2 * b];
+        h[k] = hist[base + 2 * b + 1];
+        if (minus) {
+          g[k] -= minus[base + 2 * b];
+          h[k] -= minus[base + 2 * b + 1];
+        }
+        if (derived) {
+          derived[base + 2 * b] = g[k];
+          derived[base + 2 * b + 1] = h[k];
+        }
+      }
+      sg += g[k];
+      sh += h[k];
+    }
+    // inclusive scan of the lane sums over the wave
+    int64_t pg = sg, ph = sh;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const int64_t tg = __shfl_up(pg, d, 64), th = __shfl_up(ph, d, 64);
+      if ((int)lane >= d) {
+        pg += tg;
+        ph += th;
+      }
+    }
+    const int64_t G = __shfl(pg, 63, 64), H = __shfl(ph, 63, 64);
+    const double fg = (double)G * scale, fh = (double)H * scale;
+    const double tp = split_term(fg, fh, lam);
+    int64_t gl = pg - sg, hl = ph - sh;
+    SplitCand c = none;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t b = lane * 4 + k;
+      gl += g[k];
+      hl += h[k];
+      if (b + 1 < B) {
+        const double fgl = (double)gl * scale, fhl = (double)hl * scale;
+        const double fgr = (double)(G - gl) * scale, fhr = (double)(H - hl) * scale;
+        if (fhl >= mcw && fhr >= mcw && fhl + lam > 0.0 && fhr + lam > 0.0) {
+          const double gain = 0.5 * ((split_term(fgl, fhl, lam) + split_term(fgr, fhr, lam)) - tp) - gamma;
+          if (gain > c.gain) c = {gain, (int32_t)f, (int32_t)b, gl, hl};
+        }
+      }
+    }
+#pragma unroll
+    for (int m = 32; m >= 1; m >>= 1) {
+      const SplitCand o = shfl_xor_cand(c, m);
+      if (split_better(o, c, false)) c = o;
+    }
+    if (lane == 0 && out_feat) out_feat[node * F + f] = c;
+    if (split_better(c, best, true)) best = c;
+  }
+  if (lane == 0) waves[w] = best;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    SplitCand b = waves[0];
+    for (uint32_t i = 1; i < kBlockThreads / 64; ++i)
+      if (split_better(waves[i], b, true)) b = waves[i];
+    out_node[node] = b;
+  }
+}
+
 // ------------------------------------------------------ Montgomery conversion
 template <int KP>
 __global__ __launch_bounds__(kBlockThreads) void k_mont_convert(DKey key, const uint32_t *in, uint64_t count,
@@ -877,6 +990,15 @@ hipError_t launch_ct_div(int KP, const DKey &k, const uint32_t *num, const uint3
     hipLaunchKernelGGL(k_ct_div<1>, grid, dim3(kBlockThreads), 0, s, k, num, den, count, batch, out, n_bad);
   else
     hipLaunchKernelGGL(k_ct_div<2>, grid, dim3(kBlockThreads), 0, s, k, num, den, count, batch, out, n_bad);
+  return hipGetLastError();
+}
+
+hipError_t launch_split(const int64_t *hist, const int64_t *minus, uint32_t nodes, uint32_t F, uint32_t B,
+                        double scale, double lam, double gamma, double mcw, int64_t *derived, void *out_feat,
+                        void *out_node, hipStream_t s) {
+  if (!nodes) return hipSuccess;
+  hipLaunchKernelGGL(k_split, dim3(nodes), dim3(kBlockThreads), 0, s, hist, minus, F, B, scale, lam, gamma, mcw,
+                     derived, (SplitCand *)out_feat, (SplitCand *)out_node);
   return hipGetLastError();
 }
 

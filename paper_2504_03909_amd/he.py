@@ -27,7 +27,7 @@ EXPORTED = (
     "he_key_free", "he_encode", "he_encrypt", "he_encrypt_public", "he_to_mont", "he_from_mont",
     "he_hist_aggregate", "he_hist_aggregate_ex", "he_decrypt", "he_probe_int_mul", "he_last_error",
     "he_hist_autotune", "he_hist_plan_create", "he_hist_plan_launch", "he_hist_plan_free",
-    "he_obfuscators", "he_encrypt_obfuscated", "he_hist_subtract",
+    "he_obfuscators", "he_encrypt_obfuscated", "he_hist_subtract", "he_split_find",
 )
 
 
@@ -72,6 +72,8 @@ _encrypt = _sig("he_encrypt", _i32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp])
 _encrypt_pub = _sig("he_encrypt_public", _i32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp])
 _obf = _sig("he_obfuscators", _i32, [_vp, _u64, _vp, _u64, _u64, _vp, _vp])
 _enc_obf = _sig("he_encrypt_obfuscated", _i32, [_vp, _vp, _u64, _vp, _vp, _vp])
+_f64 = ctypes.c_double
+_split = _sig("he_split_find", _i32, [_vp, _vp, _u32, _u32, _u32, _u32, _f64, _f64, _f64, _vp, _vp, _vp, _vp])
 _sub = _sig("he_hist_subtract", _i32, [_vp, _vp, _vp, _u64, _u32, _vp, _vp, _vp])
 _to_mont = _sig("he_to_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
 _from_mont = _sig("he_from_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
@@ -256,6 +258,36 @@ def hist_subtract(key: Key, parent: torch.Tensor, child: torch.Tensor, out: Opti
     return out
 
 
+def split_find(hist: torch.Tensor, minus: Optional[torch.Tensor] = None, frac_bits: int = 32,
+               lam: float = 1.0, gamma: float = 0.0, min_child_weight: float = 1.0,
+               derived: Optional[torch.Tensor] = None, per_feature: bool = False, stream=None):
+    """Best splits from decrypted histograms hist int64 [nodes, F, B, 2]
+    (the node histogram is hist - minus when minus is given).  Returns a dict
+    of tensors: gain (float64), feature, bin (int32), g_left, h_left (int64)
+    per node, and the same per (node, feature) under "per_feature"."""
+    assert hist.dtype == torch.int64 and hist.dim() == 4 and hist.shape[-1] == 2
+    nodes, F, B, _ = hist.shape
+    hist = hist.contiguous()
+    if minus is not None:
+        assert minus.shape == hist.shape and minus.dtype == torch.int64
+        minus = minus.contiguous()
+    if derived is not None:
+        assert derived.shape == hist.shape and derived.dtype == torch.int64 and derived.is_contiguous()
+    out_node = torch.empty((nodes, 4), dtype=torch.int64, device=hist.device)   # 32-byte records
+    out_feat = torch.empty((nodes, F, 4), dtype=torch.int64, device=hist.device) if per_feature else None
+    _check(_split(_ptr(hist), _ptr(minus), nodes, F, B, frac_bits, lam, gamma, min_child_weight,
+                  _ptr(derived), _ptr(out_feat), _ptr(out_node), _stream(stream)))
+
+    def unpack(rec):
+        fb = rec[..., 1:2].view(torch.int32)   # (feature, bin) int32 pair
+        return {"gain": rec[..., 0].view(torch.float64), "feature": fb[..., 0], "bin": fb[..., 1],
+                "g_left": rec[..., 2], "h_left": rec[..., 3]}
+    res = unpack(out_node)
+    if per_feature:
+        res["per_feature"] = unpack(out_feat)
+    return res
+
+
 def to_mont(key: Key, ct: torch.Tensor, out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     out = torch.empty_like(ct) if out is None else out
     _check(_to_mont(key.handle, _ptr(ct), ct.numel() // (2 * key.limbs), _ptr(out), _stream(stream)))
@@ -337,12 +369,16 @@ class HistPlan:
             pass
 
 
-def decrypt(key: Key, ct: torch.Tensor, raw: bool = False, stream=None):
+def decrypt(key: Key, ct: torch.Tensor, raw: bool = False, out: Optional[torch.Tensor] = None, stream=None):
     """Signed int64 plaintexts of ct (int32 [..., 2L]); optionally the raw
     plaintexts int32 [..., L] and the overflow count tensor."""
     count = ct.numel() // (2 * key.limbs)
     shape = ct.shape[:-1]
-    m = torch.empty(shape, dtype=torch.int64, device=ct.device)
+    if out is None:
+        m = torch.empty(shape, dtype=torch.int64, device=ct.device)
+    else:
+        assert out.dtype == torch.int64 and out.is_contiguous() and out.numel() == count
+        m = out
     rw = torch.empty((*shape, key.limbs), dtype=torch.int32, device=ct.device) if raw else None
     ovf = torch.zeros(1, dtype=torch.int32, device=ct.device)
     _check(_decrypt(key.handle, _ptr(ct.contiguous()), count, _ptr(m), _ptr(rw), _ptr(ovf), _stream(stream)))

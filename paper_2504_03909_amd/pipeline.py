@@ -127,3 +127,90 @@ def _sibling_levels(res: Resident, levels: Sequence[Sequence[torch.Tensor]], bin
         slot_node = small + large
         run.hists.append(node_hist)
     return run
+
+
+@dataclass
+class RoundResult:
+    """Per level: the plaintext histograms int64 [nodes, F, B, 2] in node
+    order, and the best split of every node (he.split_find's dict)."""
+    plain: List[torch.Tensor] = field(default_factory=list)
+    splits: List[dict] = field(default_factory=list)
+
+
+def tree_round(res: Resident, sk: he.Key, levels: Sequence[Sequence[torch.Tensor]], bins: torch.Tensor,
+               n_bins: int, sibling: Optional[str] = None, lam: float = 1.0, gamma: float = 0.0,
+               min_child_weight: float = 1.0, frac_bits: int = 32, chunk: int = 0, stream=None) -> RoundResult:
+    """The histogram work of one tree, level by level: the passive party's
+    aggregation, the active party's decryption and split finding.
+
+    sibling=None: every node is aggregated and decrypted.
+    sibling="encrypted": the smaller child of every parent is aggregated, the
+      larger one is the parent's encrypted histogram divided by it; all are
+      decrypted.
+    sibling="plain": only the smaller children are aggregated and decrypted;
+      the larger child's plaintext histogram is the parent's minus the
+      smaller one's, formed inside the split finder.
+    The children of node i of one level are nodes 2i and 2i + 1 of the next."""
+    key = res.key
+    F = bins.shape[0]
+    dev = res.ctm.device
+    out = RoundResult()
+
+    def split(hist, minus=None, derived=None):
+        return he.split_find(hist, minus, frac_bits, lam, gamma, min_child_weight, derived=derived, stream=stream)
+
+    def in_node_order(slot_vals, slot_node):
+        order = torch.as_tensor(sorted(range(len(slot_node)), key=lambda s: slot_node[s]), device=dev)
+        return {k: v.index_select(0, order) for k, v in slot_vals.items()} if isinstance(slot_vals, dict) \
+            else slot_vals.index_select(0, order)
+
+    if sibling is None:
+        for lvl in levels:
+            jobs = [he.Job(idx, bins, n_bins) for idx in lvl]
+            he.hist_aggregate(key, res.ctm, jobs, form=he.HE_FORM_MONT, chunk=chunk, stream=stream)
+            enc = torch.stack([j.hist for j in jobs])
+            plain = he.decrypt(sk, enc, stream=stream)[0]
+            out.plain.append(plain)
+            out.splits.append(split(plain))
+        return out
+    if sibling not in ("encrypted", "plain"):
+        raise ValueError(sibling)
+
+    shape = (F, n_bins, 2)
+    L2 = 2 * key.limbs
+    # level buffers in slot order [smaller children..., larger children...]
+    enc_prev = torch.empty((1, *shape, L2), dtype=torch.int32, device=dev)
+    he.hist_aggregate(key, res.ctm, [he.Job(levels[0][0], bins, n_bins, hist=enc_prev[0])], form=he.HE_FORM_MONT,
+                      chunk=chunk, stream=stream)
+    plain_prev = he.decrypt(sk, enc_prev, stream=stream)[0]
+    out.plain.append(plain_prev)
+    out.splits.append(split(plain_prev))
+    slot_node = [0]
+    for lvl in levels[1:]:
+        P = len(slot_node)
+        enc = torch.empty((2 if sibling == "encrypted" else 1, P, *shape, L2), dtype=torch.int32, device=dev)
+        jobs, small, large = [], [], []
+        for s, u in enumerate(slot_node):
+            a, b = 2 * u, 2 * u + 1
+            sm, lg = (a, b) if lvl[a].numel() <= lvl[b].numel() else (b, a)
+            jobs.append(he.Job(lvl[sm], bins, n_bins, hist=enc[0, s]))
+            small.append(sm)
+            large.append(lg)
+        he.hist_aggregate(key, res.ctm, jobs, form=he.HE_FORM_MONT, chunk=chunk, stream=stream)
+        plain = torch.empty((2, P, *shape), dtype=torch.int64, device=dev)
+        if sibling == "encrypted":
+            he.hist_subtract(key, enc_prev, enc[0], out=enc[1], stream=stream)
+            he.decrypt(sk, enc, out=plain, stream=stream)
+            sp_small, sp_large = split(plain[0]), split(plain[1])
+        else:
+            he.decrypt(sk, enc[0], out=plain[0], stream=stream)
+            sp_small = split(plain[0])
+            sp_large = split(plain_prev, minus=plain[0], derived=plain[1])
+        slot_node = small + large
+        slots = plain.view(2 * P, *shape)
+        sp = {k: torch.cat([sp_small[k], sp_large[k]]) for k in sp_small}
+        out.plain.append(in_node_order(slots, slot_node))
+        out.splits.append(in_node_order(sp, slot_node))
+        enc_prev = enc.view(-1, *shape, L2) if sibling == "encrypted" else None
+        plain_prev = slots
+    return out

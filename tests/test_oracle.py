@@ -309,3 +309,61 @@ def test_limb_roundtrip():
     limbs = P.to_limbs(x, 128)
     assert limbs[0] == 12345 and limbs[127] == 1 << 31
     assert P.from_limbs(limbs) == x
+
+
+# ------------------------------------------------------------ split finding
+def test_split_gain_hand_values():
+    from oracle import split as S
+    # G_L = 2, H_L = 1, G_R = -2, H_R = 1, lambda = 1: 1/2 (4/2 + 4/2 - 0/3) = 2
+    one = 1 << 32
+    assert S.split_gain(2 * one, one, 0, 2 * one, 32, 1.0, 0.0, 0.0) == 2.0
+    # gamma is subtracted once; lambda = 0 and H_L = 0 is not admissible
+    assert S.split_gain(2 * one, one, 0, 2 * one, 32, 1.0, 0.5, 0.0) == 1.5
+    assert S.split_gain(one, 0, one, one, 32, 0.0, 0.0, 0.0) is None
+    # min_child_weight
+    assert S.split_gain(one, one, 2 * one, 3 * one, 32, 1.0, 0.0, 1.5) is None
+
+
+def test_split_from_samples_brute_force():
+    # Against the definition over samples: for every candidate bin, sum the
+    # samples with bin <= b directly (no running sums) and take the argmax.
+    from oracle import split as S
+    rng = np.random.default_rng(21)
+    n, F, B = 400, 5, 12
+    g = rng.integers(-(1 << 33), 1 << 33, size=n)
+    h = rng.integers(0, 1 << 32, size=n)
+    bins = rng.integers(0, B, size=(F, n))
+    hist = [[(int(g[bins[f] == b].sum()), int(h[bins[f] == b].sum())) for b in range(B)] for f in range(F)]
+    per_feat, per_node = S.best_splits([hist], 32, 1.0, 0.0, 0.25)
+    G, H = int(g.sum()), int(h.sum())
+    best_all = (-math.inf, -1, -1)
+    for f in range(F):
+        best = (-math.inf, -1)
+        for b in range(B - 1):
+            left = bins[f] <= b
+            gl, hl = int(g[left].sum()), int(h[left].sum())
+            s = 2.0 ** -32
+            if hl * s >= 0.25 and (H - hl) * s >= 0.25:
+                val = 0.5 * (((gl * s) ** 2 / (hl * s + 1) + ((G - gl) * s) ** 2 / ((H - hl) * s + 1))
+                             - (G * s) ** 2 / (H * s + 1))
+                if val > best[0]:
+                    best = (val, b)
+        assert per_feat[0][f].bin == best[1]
+        assert per_feat[0][f].gain == pytest.approx(best[0], rel=1e-12)
+        if best[0] > best_all[0]:
+            best_all = (best[0], f, best[1])
+    assert (per_node[0].feature, per_node[0].bin) == best_all[1:]
+
+
+def test_split_planted_boundary():
+    # Samples in bins < 5 have g = -1, the rest g = +1 (h = 1): the best split
+    # of that feature is after bin 4, with G_L = -(count of bins < 5).
+    from oracle import split as S
+    rng = np.random.default_rng(3)
+    bins = rng.integers(0, 16, size=1000)
+    one = 1 << 32
+    hist = [(int(((bins == b) * (-1 if b < 5 else 1)).sum()) * one, int((bins == b).sum()) * one)
+            for b in range(16)]
+    s = S.best_split_feature(hist, 32, 1.0, 0.0, 1.0)
+    assert s.bin == 4 and s.g_left == -int((bins < 5).sum()) * one
+    assert S.best_split_feature(hist[:1], 32, 1.0, 0.0, 1.0) == S.NO_SPLIT

@@ -376,14 +376,23 @@ def bench_tree(args):
     _, t_dec = _timed(lambda: pipeline.decrypt_levels(key, run_plain), "tree decrypt")
     # whole rounds: aggregation + decryption + split finding, three ways
     rounds, round_splits = {}, {}
-    for mode in (None, "encrypted", "plain"):
-        rr, tr = _timed(lambda: pipeline.tree_round(res, key, levels, bins, Kt, sibling=mode),
-                        f"tree round sibling={mode}")
-        rounds[str(mode)] = round(tr, 3)
-        round_splits[str(mode)] = rr.splits
+    for mode, pk in ((None, False), ("encrypted", False), ("plain", False), ("plain", True)):
+        rr, tr = _timed(lambda: pipeline.tree_round(res, key, levels, bins, Kt, sibling=mode, packed=pk),
+                        f"tree round sibling={mode} packed={pk}")
+        name = str(mode) + ("_packed" if pk else "")
+        rounds[name] = round(tr, 3)
+        round_splits[name] = rr.splits
         del rr
-    rounds_same = all(torch.equal(a[k], b[k]) for m in ("encrypted", "plain")
+    rounds_same = all(torch.equal(a[k], b[k]) for m in ("encrypted", "plain", "plain_packed")
                       for a, b in zip(round_splits["None"], round_splits[m]) for k in a)
+    # decryption of one node histogram (32,768 ciphertexts): plain vs packed
+    h0 = run_plain.hists[0][0]
+    he.decrypt(key, h0)
+    _, t_dec1 = _timed(lambda: he.decrypt(key, h0))
+    pk0, s0 = he.pack(key, h0)
+    he.decrypt_packed(key, pk0, h0.numel() // h0.shape[-1], s0)
+    _, t_pack1 = _timed(lambda: he.pack(key, h0))
+    _, t_decp1 = _timed(lambda: he.decrypt_packed(key, pk0, h0.numel() // h0.shape[-1], s0))
     contrib = 2 * Jt * sum(int(n.numel()) for lvl in levels for n in lvl)
     contrib_sib = 2 * Jt * (Mt + sum(min(int(lvl[i].numel()), int(lvl[i + 1].numel()))
                                      for lvl in levels[1:] for i in range(0, len(lvl), 2)))
@@ -407,7 +416,9 @@ def bench_tree(args):
         "subtract_524288_ms": round(sub_ms, 3),
         "subtract_per_s": round(n_sub / (sub_ms / 1e3), 1),
         "round_s": {"direct": rounds["None"], "sibling_encrypted": rounds["encrypted"],
-                    "sibling_plain": rounds["plain"]},
+                    "sibling_plain": rounds["plain"], "sibling_plain_packed": rounds["plain_packed"]},
+        "node_decrypt_32768_ms": {"plain": round(t_dec1 * 1e3, 3), "pack": round(t_pack1 * 1e3, 3),
+                                  "decrypt_packed": round(t_decp1 * 1e3, 3), "slots": s0},
         "round_splits_identical": bool(rounds_same),
         "total_s_one_job_per_launch": round(t_enc + t_plain + t_dec, 3),
     }
@@ -446,6 +457,9 @@ def bench_batched(args):
     plan.launch()
     _, t_graph = _timed(lambda: plan.launch())
     same = all(torch.equal(a.hist, b.hist) and torch.equal(a.hist, c.hist) for a, b, c in zip(ja, jb, jc))
+    # work counters at the tuned shape: products joining real partials vs executed
+    _, cnt = he.hist_aggregate_counted(key, ctm, jobs(), form=he.HE_FORM_MONT, chunk=chunk, split=split)
+    mm_real, mm_done, mm_conv = (int(x) for x in cnt.cpu().tolist())
     L = key.limbs
     prod = contrib * (2 * (2 * L) ** 2 + 2 * L)
     return {
@@ -462,6 +476,9 @@ def bench_batched(args):
                               "graph_replay": round(contrib / t_graph, 1)},
         "alu_frac_graph_replay": round(prod / t_graph / PEAK_MUL32_PER_S, 4),
         "results_identical": bool(same),
+        "montgomery_products": {"joining_real_partials": mm_real, "executed": mm_done,
+                                "conversions_out": mm_conv,
+                                "executed_over_needed": round(mm_done / max(1, mm_real + mm_conv), 4)},
     }
 
 

@@ -194,6 +194,20 @@ int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t rows, int c
                      const he_hist_job *jobs, uint32_t n_jobs, uint32_t *chunk, uint32_t *split,
                      float *ms, hipStream_t stream);
 
+/* Work-count check of the aggregation: he_hist_aggregate_ex with an explicit
+ * work-item length (chunk, 0 = default) and groups per item (split, 1 or 2),
+ * that also adds, into the device counters mm_count[3] (not cleared):
+ *   [0] the Montgomery products that join two partial products of real
+ *       samples -- for every (job, feature, slot) the node's sample count
+ *       minus its number of non-empty bins, the algorithm's count;
+ *   [1] the products the kernels executed, padding of uneven work items and
+ *       the conversions out of Montgomery form included;
+ *   [2] the conversions out of Montgomery form (one per histogram entry).
+ * The conversion of canonical input rows into Montgomery form is not counted. */
+int he_hist_aggregate_counted(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
+                              const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk, uint32_t split,
+                              uint64_t *mm_count, hipStream_t stream);
+
 /* A batched aggregation captured once into a HIP graph (all of its kernels,
  * with a workspace the plan owns), to be replayed with one launch, e.g. once
  * per tree level per boosting round.  Each replay reads the buffers that the
@@ -207,6 +221,15 @@ int he_hist_plan_create(const he_key *key, const uint32_t *ct, uint64_t rows, in
                         he_hist_plan **out);
 int he_hist_plan_launch(he_hist_plan *plan, hipStream_t stream);
 void he_hist_plan_free(he_hist_plan *plan);
+
+/* Encrypted addition of two ciphertext arrays (Sec. III-C: addition of
+ * plaintexts is the product of ciphertexts mod n^2): out[i] = a[i] b[i] mod
+ * n^2.  Uses: re-randomising returned histograms (multiply by obfuscators
+ * from he_obfuscators, i.e. encryptions of 0 under fresh r, which needs only
+ * the public key), and combining partial histograms of sample shards.
+ * a, b, out: device uint32[count][2L] canonical; out may alias a or b. */
+int he_ct_mul(const he_key *key, const uint32_t *a, const uint32_t *b, uint64_t count, uint32_t *out,
+              hipStream_t stream);
 
 /* Encrypted histogram subtraction (the sibling trick of tree building: the
  * samples of a node split into its two children, so the larger child's
@@ -264,6 +287,29 @@ int he_split_find(const int64_t *hist, const int64_t *minus, uint32_t nodes, uin
  * HE_ERR_NOPRIV for a public key. */
 int he_decrypt(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m,
                uint32_t *raw, uint32_t *n_overflow, hipStream_t stream);
+
+/* Ciphertext packing for cheaper decryption.  The holder of encrypted
+ * histograms (public key only) folds `slots` consecutive ciphertexts into
+ * one: packed = prod_j c_j^(2^(64 j)) (1 + K n) mod n^2 with
+ * K = sum_j 2^(64 j + 63), an encryption of sum_j 2^(64 j) (m_j + 2^63)
+ * (additive homomorphism, Sec. III-C; multiplying by 1 + K n adds K).  The
+ * key holder decrypts count / slots ciphertexts instead of count; each slot
+ * value must lie in [-2^63, 2^63).  Costs 64 squarings mod n^2 per slot.
+ * slots in [1, (n_bits - 1) / 64] (31 for 2048-bit keys, 15 for 1024-bit);
+ * he_pack_slots gives the count the library would pick for `count`
+ * ciphertexts on this device (enough packed ciphertexts to occupy it).
+ * ct: device uint32[count][2L] canonical; packed: device
+ * uint32[ceil(count / slots)][2L] (the last may hold fewer slots). */
+uint32_t he_pack_slots(const he_key *key, uint64_t count);
+int he_pack(const he_key *key, const uint32_t *ct, uint64_t count, uint32_t slots, uint32_t *packed,
+            hipStream_t stream);
+/* Decrypts he_pack's output: m: device int64[count] (the original order).
+ * Plaintexts with bits above their last slot (which a slot value outside the
+ * signed 64-bit range at the top slot, or a negative total, produces) are
+ * counted into *n_overflow (device uint32, optional, not cleared).
+ * HE_ERR_NOPRIV for a public key. */
+int he_decrypt_packed(const he_key *key, const uint32_t *packed, uint64_t count, uint32_t slots, int64_t *m,
+                      uint32_t *n_overflow, hipStream_t stream);
 
 /* Measurement probe for the roofline denominator: launches `blocks` blocks
  * of 256 threads that each run `iters` iterations of 8 independent 32x32->64

@@ -235,11 +235,46 @@ def add(pk: PublicKey, c1: int, c2: int) -> int:
     return c1 * c2 % pk.n2
 
 
+def rerandomize(pk: PublicKey, c: int, r: int) -> int:
+    """c times a fresh encryption of 0 (r' = r): the same plaintext under
+    randomness multiplied by r."""
+    return add(pk, c, encrypt(pk, 0, r))
+
+
 def subtract(pk: PublicKey, c1: int, c2: int) -> int:
     """Encrypted subtraction: c1 times the inverse of c2 mod n^2, an
     encryption of m1 - m2 (the inverse of E(m; r) is E(-m; r^-1)).  Raises
     ValueError when c2 is not a unit mod n^2."""
     return c1 * pow(c2, -1, pk.n2) % pk.n2
+
+
+PACK_SLOT_BITS = 64
+
+
+def pack_offset(slots: int) -> int:
+    """K = sum over slots j of 2^(64 j + 63): shifts every slot's signed
+    value into [0, 2^64)."""
+    return sum(1 << (PACK_SLOT_BITS * j + PACK_SLOT_BITS - 1) for j in range(slots))
+
+
+def pack(pk: PublicKey, cts: Sequence[int]) -> int:
+    """Several ciphertexts folded into one with the public key: the product
+    of c_j^(2^(64 j)) and of g^K = 1 + K n, an encryption of
+    sum_j 2^(64 j) (m_j + 2^63).  Needs 64 len(cts) < log2 n."""
+    n2 = pk.n2
+    acc = 1
+    for j, c in enumerate(cts):
+        acc = acc * pow(c, 1 << (PACK_SLOT_BITS * j), n2) % n2
+    return acc * (1 + pack_offset(len(cts)) * pk.n) % n2
+
+
+def unpack(m: int, slots: int) -> List[int]:
+    """The slot values of a decrypted packed plaintext m in [0, n)."""
+    out = []
+    for j in range(slots):
+        field = (m >> (PACK_SLOT_BITS * j)) & ((1 << PACK_SLOT_BITS) - 1)
+        out.append(field - (1 << (PACK_SLOT_BITS - 1)))
+    return out
 
 
 def decrypt(sk: PrivateKey, c: int) -> int:

@@ -130,7 +130,7 @@ struct Buf {
   size_t bytes = 0;
 };
 struct Workspace {
-  Buf tab, tmp, hist;
+  Buf tab, tmp, hist, unpack;
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
@@ -344,6 +344,15 @@ int he_split_find(const int64_t *hist, const int64_t *minus, uint32_t nodes, uin
   return HE_OK;
 }
 
+int he_ct_mul(const he_key *key, const uint32_t *a, const uint32_t *b, uint64_t count, uint32_t *out,
+              hipStream_t stream) {
+  if (!key) return fail(HE_ERR_ARG, "null key");
+  if (count == 0) return HE_OK;
+  if (!a || !b || !out) return fail(HE_ERR_ARG, "null a, b or out");
+  HE_TRY_HIP(he::launch_ct_mul(kp_of(key), key->dk, a, b, count, out, stream));
+  return HE_OK;
+}
+
 int he_to_mont(const he_key *key, const uint32_t *in, uint64_t count, uint32_t *out, hipStream_t stream) {
   if (!key) return fail(HE_ERR_ARG, "null key");
   if (count == 0) return HE_OK;
@@ -378,6 +387,42 @@ int he_decrypt(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m
   if (rc) return rc;
   HE_TRY_HIP(he::launch_dec(KP, key->dk, ct, count, (uint32_t *)w->tmp.p, m, raw, n_overflow,
                             (uint32_t *)w->tab.p, grid, G, stream));
+  return HE_OK;
+}
+
+uint32_t he_pack_slots(const he_key *key, uint64_t count) {
+  if (!key) return 0;
+  return he::pack_slots((int)key->n_bits, count);
+}
+
+int he_pack(const he_key *key, const uint32_t *ct, uint64_t count, uint32_t slots, uint32_t *packed,
+            hipStream_t stream) {
+  if (!key) return fail(HE_ERR_ARG, "null key");
+  if (slots < 1 || slots > (key->n_bits - 1) / 64) return fail(HE_ERR_ARG, "slots must be in [1, (n_bits - 1) / 64]");
+  if (count == 0) return HE_OK;
+  if (!ct || !packed) return fail(HE_ERR_ARG, "null ct or packed");
+  HE_TRY_HIP(he::launch_pack(kp_of(key), key->dk, ct, count, slots, packed, stream));
+  return HE_OK;
+}
+
+int he_decrypt_packed(const he_key *key, const uint32_t *packed, uint64_t count, uint32_t slots, int64_t *m,
+                      uint32_t *n_overflow, hipStream_t stream) {
+  if (!key) return fail(HE_ERR_ARG, "null key");
+  if (!key->priv) return fail(HE_ERR_NOPRIV, "decryption needs p and q");
+  if (slots < 1 || slots > (key->n_bits - 1) / 64) return fail(HE_ERR_ARG, "slots must be in [1, (n_bits - 1) / 64]");
+  if (count == 0) return HE_OK;
+  if (!packed || !m) return fail(HE_ERR_ARG, "null packed or m");
+  const uint64_t n_packed = (count + slots - 1) / slots;
+  const size_t L = key->n_bits / 32;
+  Workspace *w = workspace(stream);
+  const size_t raw_bytes = (n_packed * L * sizeof(uint32_t) + 255) & ~(size_t)255;
+  int rc = ensure(w->unpack, raw_bytes + n_packed * sizeof(int64_t), stream);
+  if (rc) return rc;
+  uint32_t *raw = (uint32_t *)w->unpack.p;
+  int64_t *whole = (int64_t *)((char *)w->unpack.p + raw_bytes);  // signed decode of the whole plaintext, unused
+  rc = he_decrypt(key, packed, n_packed, whole, raw, nullptr, stream);
+  if (rc) return rc;
+  HE_TRY_HIP(he::launch_unpack(raw, count, slots, (uint32_t)L, m, n_overflow, stream));
   return HE_OK;
 }
 
@@ -496,8 +541,9 @@ he::HistWs bind_layout(const HistLayout &lay, char *base) {
 // Enqueues every kernel of one batch on `stream` (no allocation, no
 // memset: safe to capture into a graph).
 int enqueue_hist(const he_key *key, const uint32_t *ct, uint64_t rows, const HistLayout &lay, char *base,
-                 hipStream_t stream) {
-  const he::HistWs ws = bind_layout(lay, base);
+                 hipStream_t stream, uint64_t *mm_count = nullptr) {
+  he::HistWs ws = bind_layout(lay, base);
+  ws.mm_count = (unsigned long long *)mm_count;
   const int KP = kp_of(key);
   const uint32_t *ctm = ct;
   if (lay.convert) {
@@ -510,7 +556,7 @@ int enqueue_hist(const he_key *key, const uint32_t *ct, uint64_t rows, const His
 }
 
 int hist_run(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form, const he_hist_job *jobs,
-             uint32_t n_jobs, uint32_t chunk, uint32_t split, hipStream_t stream) {
+             uint32_t n_jobs, uint32_t chunk, uint32_t split, hipStream_t stream, uint64_t *mm_count = nullptr) {
   if (n_jobs == 0) return key ? HE_OK : fail(HE_ERR_ARG, "null key");
   HistLayout lay;
   int rc = plan_layout(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, lay);
@@ -518,7 +564,7 @@ int hist_run(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form, 
   Workspace *w = workspace(stream);
   rc = ensure(w->hist, lay.bytes, stream);
   if (rc) return rc;
-  return enqueue_hist(key, ct, rows, lay, (char *)w->hist.p, stream);
+  return enqueue_hist(key, ct, rows, lay, (char *)w->hist.p, stream, mm_count);
 }
 
 // Autotuner cache: best (chunk, split) per shape class.
@@ -569,6 +615,14 @@ extern "C" int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint6
     }
   }
   return hist_run(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, stream);
+}
+
+extern "C" int he_hist_aggregate_counted(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
+                                         const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk, uint32_t split,
+                                         uint64_t *mm_count, hipStream_t stream) {
+  if (!mm_count) return fail(HE_ERR_ARG, "null mm_count");
+  if (split != 1 && split != 2) return fail(HE_ERR_ARG, "split must be 1 or 2");
+  return hist_run(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, stream, mm_count);
 }
 
 extern "C" int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,

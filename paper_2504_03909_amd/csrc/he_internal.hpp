@@ -80,6 +80,7 @@ struct HistWs {
   uint64_t total_fb, total_f, total_blocks, items_cap;
   uint32_t chunk;                                  // samples per item
   uint32_t split;                                  // groups per (item, slot): 1 or 2
+  unsigned long long *mm_count;                    // optional debug counters [3], else null
 };
 
 constexpr int kWindowBits = 5;     // exponent window width (see mont.hpp)
@@ -104,6 +105,13 @@ hipError_t launch_ct_div(int KP, const DKey &k, const uint32_t *num, const uint3
 hipError_t launch_split(const int64_t *hist, const int64_t *minus, uint32_t nodes, uint32_t F, uint32_t B,
                         double scale, double lam, double gamma, double mcw, int64_t *derived, void *out_feat,
                         void *out_node, hipStream_t s);
+hipError_t launch_ct_mul(int KP, const DKey &k, const uint32_t *a, const uint32_t *b, uint64_t count,
+                         uint32_t *out, hipStream_t s);
+hipError_t launch_pack(int KP, const DKey &k, const uint32_t *ct, uint64_t count, uint32_t slots,
+                       uint32_t *packed, hipStream_t s);
+hipError_t launch_unpack(const uint32_t *raw, uint64_t count, uint32_t slots, uint32_t L, int64_t *m,
+                         uint32_t *n_overflow, hipStream_t s);
+uint32_t pack_slots(int n_bits, uint64_t count);
 hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64_t count,
                                uint32_t *out, bool to_mont, hipStream_t s);
 hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count,

@@ -473,6 +473,106 @@ __global__ __launch_bounds__(kBlockThreads) void k_split(const int64_t *hist, co
   }
 }
 
+// ------------------------------------------------ ciphertext products
+// out[i] = a[i] b[i] mod n^2 (canonical in and out): the encrypted sum of two
+// ciphertext arrays.  MM(a, b) = a b R^-1, then MM(., R^2) = a b.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_ct_mul(DKey key, const uint32_t *a, const uint32_t *b,
+                                                         uint64_t count, uint32_t *out) {
+  constexpr int KN2 = 4 * KP, SN2 = 64 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SN2;
+  uint64_t i = (uint64_t)blockIdx.x * 16 + gi;
+  const bool valid = i < count;
+  if (!valid) i = count - 1;
+  const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
+  uint32_t x[KN2], y[KN2];
+  ld<KN2>(x, a + i * SN2);
+  ld<KN2>(y, b + i * SN2);
+  mont_mul<KN2>(x, x, y, M, lds);
+  ld<KN2>(y, key.n2.R2);
+  mont_mul<KN2>(x, x, y, M, lds);
+  if (valid) st<KN2>(out + i * SN2, x);
+}
+
+// ------------------------------------------------------ packing
+// Folds `slots` consecutive ciphertexts into one (public key only):
+// prod_j c_j^(2^(64 j)) (1 + K n) mod n^2 with K = sum_j 2^(64 j + 63), an
+// encryption of sum_j 2^(64 j) (m_j + 2^63), by Horner's rule from the top
+// slot down (64 squarings per slot) in Montgomery form.  The last packed
+// ciphertext may hold fewer slots; the wave's loops run over `slots` and its
+// missing slots multiply by one.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_pack(DKey key, const uint32_t *__restrict__ ct, uint64_t count,
+                                                       uint32_t slots, uint32_t *__restrict__ packed) {
+  constexpr int KN2 = 4 * KP, SN2 = 64 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SN2;
+  const uint64_t n_packed = (count + slots - 1) / slots;
+  uint64_t p = (uint64_t)blockIdx.x * 16 + gi;
+  const bool valid = p < n_packed;
+  if (!valid) p = n_packed - 1;
+  const uint64_t first = p * slots;
+  const uint32_t my_slots = (uint32_t)min((uint64_t)slots, count - first);
+  const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
+  uint32_t r2[KN2], acc[KN2], x[KN2];
+  set_zero(x);
+  ld<KN2>(r2, key.n2.R2);
+  // top slot into Montgomery form; a shorter (last) packed ciphertext starts
+  // from the Montgomery one instead
+  const bool full = my_slots == slots;
+  ld<KN2>(acc, key.n2.R1);
+  if (full) ld<KN2>(x, ct + (first + slots - 1) * SN2);
+  mont_mul<KN2>(x, x, r2, M, lds);
+  select(acc, full, x, acc);
+#pragma unroll 1
+  for (uint32_t j = slots - 1; j-- > 0;) {
+#pragma unroll 1
+    for (int t = 0; t < 64; ++t) mont_mul<KN2>(acc, acc, acc, M, lds);
+    const bool have = j < my_slots;
+    if (have) ld<KN2>(x, ct + (first + j) * SN2);
+    else ld<KN2>(x, key.n2.R1);
+    mont_mul<KN2>(x, x, r2, M, lds);
+    uint32_t t[KN2];
+    mont_mul<KN2>(t, acc, x, M, lds);
+    select(acc, have, t, acc);
+  }
+  // f = 1 + K n: K has bit 31 of every odd limb below 2 my_slots
+#pragma unroll
+  for (int i = 0; i < KN2; ++i) {
+    const uint32_t idx = glane() * KN2 + i;
+    x[i] = ((idx & 1u) && (idx >> 1) < my_slots) ? 0x80000000u : 0u;
+  }
+  ld<KN2>(r2, key.nR_n2);
+  mont_mul<KN2>(x, x, r2, M, lds);  // K n mod n^2
+  add_one<KN2>(x);
+  mont_mul<KN2>(acc, acc, x, M, lds);  // leaves Montgomery form
+  if (valid) st<KN2>(packed + p * SN2, acc);
+}
+
+// Slot values of decrypted packed plaintexts raw[n_packed][L]: value i is
+// the 64-bit field (i mod slots) of plaintext i / slots, minus 2^63.  A
+// plaintext with bits above its last slot (a slot sum outside the signed
+// 64-bit range at the top, or a negative total) is counted into *n_overflow.
+__global__ void k_unpack(const uint32_t *__restrict__ raw, uint64_t count, uint32_t slots, uint32_t L,
+                         int64_t *__restrict__ m, uint32_t *__restrict__ n_overflow) {
+  const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  const uint64_t p = i / slots;
+  const uint32_t j = (uint32_t)(i - p * slots);
+  const uint32_t my_slots = (uint32_t)min((uint64_t)slots, count - p * slots);
+  const uint32_t *w = raw + p * L;
+  const uint64_t v = (uint64_t)w[2 * j] | ((uint64_t)w[2 * j + 1] << 32);
+  m[i] = (int64_t)(v ^ 0x8000000000000000ull);
+  if (j == my_slots - 1 && n_overflow) {
+    bool high = false;
+    for (uint32_t k = 2 * my_slots; k < L; ++k) high = high || w[k] != 0u;
+    if (high) atomicAdd(n_overflow, 1u);
+  }
+}
+
 // ------------------------------------------------------ Montgomery conversion
 template <int KP>
 __global__ __launch_bounds__(kBlockThreads) void k_mont_convert(DKey key, const uint32_t *in, uint64_t count,
@@ -847,6 +947,17 @@ __global__ __launch_bounds__(kBlockThreads) void k_hist_chunk(DKey key, const ui
     } else if (it < n_items) {
       st<K>(ws.partials + (it * 2 + slot) * S, acc);
     }
+    if (ws.mm_count && glane() == 0) {
+      // products joining two real partials (the algorithm's count) and
+      // products this group executed, masked padding included
+      uint64_t real = my_len ? my_len - 1 : 0, done = trip ? trip - 1 : 0;
+      if (split) {
+        done += 1;
+        real += (sub == 0 && my_len >= 1 && ws.items[it].len >= 2) ? 1 : 0;
+      }
+      atomicAdd(&ws.mm_count[0], (unsigned long long)real);
+      atomicAdd(&ws.mm_count[1], (unsigned long long)done);
+    }
   }
 }
 
@@ -898,6 +1009,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_hist_final(DKey key, HistWs w
     set_small(b, 1u);
     mont_mul<K>(acc, acc, b, M, lds);  // out of Montgomery form
     if (half == 0) st<K>(J.hist + (fb * 2 + slot) * S, acc);
+    if (ws.mm_count && glane() == 0) {
+      const uint64_t real = (my_n ? my_n - 1 : 0) + ((half == 0 && n_hi) ? 1 : 0);
+      const uint64_t done = (n_lo ? n_lo - 1 : 0) + (n_hi ? 1 : 0) + 1;
+      atomicAdd(&ws.mm_count[0], (unsigned long long)real);
+      atomicAdd(&ws.mm_count[1], (unsigned long long)done);
+      if (half == 0) atomicAdd(&ws.mm_count[2], 1ull);
+    }
   }
 }
 
@@ -1000,6 +1118,50 @@ hipError_t launch_split(const int64_t *hist, const int64_t *minus, uint32_t node
   hipLaunchKernelGGL(k_split, dim3(nodes), dim3(kBlockThreads), 0, s, hist, minus, F, B, scale, lam, gamma, mcw,
                      derived, (SplitCand *)out_feat, (SplitCand *)out_node);
   return hipGetLastError();
+}
+
+hipError_t launch_ct_mul(int KP, const DKey &k, const uint32_t *a, const uint32_t *b, uint64_t count,
+                         uint32_t *out, hipStream_t s) {
+  if (!count) return hipSuccess;
+  const dim3 grid(blocks_for(count, 16));
+  if (KP == 1)
+    hipLaunchKernelGGL(k_ct_mul<1>, grid, dim3(kBlockThreads), 0, s, k, a, b, count, out);
+  else
+    hipLaunchKernelGGL(k_ct_mul<2>, grid, dim3(kBlockThreads), 0, s, k, a, b, count, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack(int KP, const DKey &k, const uint32_t *ct, uint64_t count, uint32_t slots,
+                       uint32_t *packed, hipStream_t s) {
+  if (!count) return hipSuccess;
+  const dim3 grid(blocks_for((count + slots - 1) / slots, 16));
+  if (KP == 1)
+    hipLaunchKernelGGL(k_pack<1>, grid, dim3(kBlockThreads), 0, s, k, ct, count, slots, packed);
+  else
+    hipLaunchKernelGGL(k_pack<2>, grid, dim3(kBlockThreads), 0, s, k, ct, count, slots, packed);
+  return hipGetLastError();
+}
+
+hipError_t launch_unpack(const uint32_t *raw, uint64_t count, uint32_t slots, uint32_t L, int64_t *m,
+                         uint32_t *n_overflow, hipStream_t s) {
+  if (!count) return hipSuccess;
+  hipLaunchKernelGGL(k_unpack, dim3(blocks_for(count, 256)), dim3(256), 0, s, raw, count, slots, L, m, n_overflow);
+  return hipGetLastError();
+}
+
+uint32_t pack_slots(int n_bits, uint64_t count) {
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 1;
+  }
+  // enough packed ciphertexts for one 16-lane group per wave slot of a
+  // wave per SIMD; beyond that, as many slots as the plaintext holds
+  const uint64_t groups = (uint64_t)cus * 4 * 4;
+  const uint64_t s = (count + groups - 1) / groups;
+  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(s, (uint64_t)(n_bits - 1) / 64));
 }
 
 hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64_t count,

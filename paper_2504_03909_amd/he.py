@@ -28,6 +28,7 @@ EXPORTED = (
     "he_hist_aggregate", "he_hist_aggregate_ex", "he_decrypt", "he_probe_int_mul", "he_last_error",
     "he_hist_autotune", "he_hist_plan_create", "he_hist_plan_launch", "he_hist_plan_free",
     "he_obfuscators", "he_encrypt_obfuscated", "he_hist_subtract", "he_split_find",
+    "he_hist_aggregate_counted", "he_ct_mul", "he_pack_slots", "he_pack", "he_decrypt_packed",
 )
 
 
@@ -74,9 +75,15 @@ _obf = _sig("he_obfuscators", _i32, [_vp, _u64, _vp, _u64, _u64, _vp, _vp])
 _enc_obf = _sig("he_encrypt_obfuscated", _i32, [_vp, _vp, _u64, _vp, _vp, _vp])
 _f64 = ctypes.c_double
 _split = _sig("he_split_find", _i32, [_vp, _vp, _u32, _u32, _u32, _u32, _f64, _f64, _f64, _vp, _vp, _vp, _vp])
+_pack_slots = _sig("he_pack_slots", _u32, [_vp, _u64])
+_pack = _sig("he_pack", _i32, [_vp, _vp, _u64, _u32, _vp, _vp])
+_dec_packed = _sig("he_decrypt_packed", _i32, [_vp, _vp, _u64, _u32, _vp, _vp, _vp])
+_ct_mul = _sig("he_ct_mul", _i32, [_vp, _vp, _vp, _u64, _vp, _vp])
 _sub = _sig("he_hist_subtract", _i32, [_vp, _vp, _vp, _u64, _u32, _vp, _vp, _vp])
 _to_mont = _sig("he_to_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
 _from_mont = _sig("he_from_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
+_hist_counted = _sig("he_hist_aggregate_counted", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32,
+                                                         _u32, _u32, _vp, _vp])
 _hist = _sig("he_hist_aggregate_ex", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32, _u32, _vp])
 _decrypt = _sig("he_decrypt", _i32, [_vp, _vp, _u64, _vp, _vp, _vp, _vp])
 _probe = _sig("he_probe_int_mul", _i32, [_u64, _u32, ctypes.POINTER(_u64), _vp])
@@ -246,6 +253,25 @@ def encrypt_obfuscated(key: Key, m: torch.Tensor, rho: torch.Tensor, out: Option
     return out
 
 
+def ct_mul(key: Key, a: torch.Tensor, b: torch.Tensor, out: Optional[torch.Tensor] = None,
+           stream=None) -> torch.Tensor:
+    """a * b mod n^2 elementwise (an encryption of m_a + m_b)."""
+    assert a.shape == b.shape and a.shape[-1] == 2 * key.limbs
+    a, b = a.contiguous(), b.contiguous()
+    if out is None:
+        out = torch.empty_like(a)
+    _check(_ct_mul(key.handle, _ptr(a), _ptr(b), a.numel() // (2 * key.limbs), _ptr(out), _stream(stream)))
+    return out
+
+
+def rerandomize(key: Key, ct: torch.Tensor, seed: int, offset: int = 0, stream=None) -> torch.Tensor:
+    """ct * E(0; r') mod n^2 with fresh r' from the seeded stream (public key
+    suffices): same plaintexts, unlinkable ciphertexts."""
+    count = ct.numel() // (2 * key.limbs)
+    rho = obfuscators(key, count, seed=seed, offset=offset, stream=stream, device=ct.device)
+    return ct_mul(key, ct, rho.view(ct.shape), out=torch.empty_like(ct), stream=stream)
+
+
 def hist_subtract(key: Key, parent: torch.Tensor, child: torch.Tensor, out: Optional[torch.Tensor] = None,
                   batch: int = 0, n_bad: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
     """parent * child^-1 mod n^2 elementwise (an encryption of m_parent - m_child)."""
@@ -326,6 +352,17 @@ def hist_aggregate(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = 
     return [j.hist for j in jobs]
 
 
+def hist_aggregate_counted(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = HE_FORM_CANONICAL,
+                           chunk: int = 0, split: int = 2, stream=None):
+    """hist_aggregate plus the work counters: returns (hists, [real products,
+    executed products, conversions out of Montgomery form])."""
+    arr = (HistJob * len(jobs))(*[j.as_c(key) for j in jobs])
+    cnt = torch.zeros(3, dtype=torch.int64, device=ct.device)
+    _check(_hist_counted(key.handle, _ptr(ct), ct.shape[0], form, arr, len(jobs), chunk, split, _ptr(cnt),
+                         _stream(stream)))
+    return [j.hist for j in jobs], cnt
+
+
 def hist_autotune(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = HE_FORM_CANONICAL,
                   stream=None):
     """Times the batched aggregation of these jobs over the candidate
@@ -383,6 +420,31 @@ def decrypt(key: Key, ct: torch.Tensor, raw: bool = False, out: Optional[torch.T
     ovf = torch.zeros(1, dtype=torch.int32, device=ct.device)
     _check(_decrypt(key.handle, _ptr(ct.contiguous()), count, _ptr(m), _ptr(rw), _ptr(ovf), _stream(stream)))
     return m, rw, ovf
+
+
+def pack_slots(key: Key, count: int) -> int:
+    return int(_pack_slots(key.handle, count))
+
+
+def pack(key: Key, ct: torch.Tensor, slots: int = 0, stream=None):
+    """Folds ct (int32 [..., 2L], canonical) into ceil(count / slots)
+    ciphertexts; slots 0 = the library's choice.  Returns (packed, slots)."""
+    count = ct.numel() // (2 * key.limbs)
+    slots = slots or pack_slots(key, count)
+    packed = torch.empty(((count + slots - 1) // slots, 2 * key.limbs), dtype=torch.int32, device=ct.device)
+    _check(_pack(key.handle, _ptr(ct.contiguous()), count, slots, _ptr(packed), _stream(stream)))
+    return packed, slots
+
+
+def decrypt_packed(key: Key, packed: torch.Tensor, count: int, slots: int, out: Optional[torch.Tensor] = None,
+                   stream=None):
+    """Signed int64 [count] values of packed ciphertexts, and the overflow count tensor."""
+    if out is None:
+        out = torch.empty(count, dtype=torch.int64, device=packed.device)
+    assert out.dtype == torch.int64 and out.is_contiguous() and out.numel() == count
+    ovf = torch.zeros(1, dtype=torch.int32, device=packed.device)
+    _check(_dec_packed(key.handle, _ptr(packed.contiguous()), count, slots, _ptr(out), _ptr(ovf), _stream(stream)))
+    return out, ovf
 
 
 def probe_int_mul(iters: int, blocks: int, stream=None) -> int:

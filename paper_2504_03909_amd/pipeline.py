@@ -137,9 +137,25 @@ class RoundResult:
     splits: List[dict] = field(default_factory=list)
 
 
+def decrypt_hist(key: he.Key, sk: he.Key, enc: torch.Tensor, out: Optional[torch.Tensor] = None,
+                 packed: bool = False, stream=None) -> torch.Tensor:
+    """Signed sums of encrypted histograms enc int32 [..., 2L] -> int64 [...].
+    packed: the holder of the ciphertexts folds them with he.pack (public
+    key) and the key holder decrypts the packed ones."""
+    if not packed:
+        return he.decrypt(sk, enc, out=out, stream=stream)[0]
+    shape = enc.shape[:-1]
+    if out is None:
+        out = torch.empty(shape, dtype=torch.int64, device=enc.device)
+    pk, slots = he.pack(key, enc, stream=stream)
+    he.decrypt_packed(sk, pk, out.numel(), slots, out=out.view(-1), stream=stream)
+    return out
+
+
 def tree_round(res: Resident, sk: he.Key, levels: Sequence[Sequence[torch.Tensor]], bins: torch.Tensor,
                n_bins: int, sibling: Optional[str] = None, lam: float = 1.0, gamma: float = 0.0,
-               min_child_weight: float = 1.0, frac_bits: int = 32, chunk: int = 0, stream=None) -> RoundResult:
+               min_child_weight: float = 1.0, frac_bits: int = 32, chunk: int = 0, packed: bool = False,
+               stream=None) -> RoundResult:
     """The histogram work of one tree, level by level: the passive party's
     aggregation, the active party's decryption and split finding.
 
@@ -150,6 +166,7 @@ def tree_round(res: Resident, sk: he.Key, levels: Sequence[Sequence[torch.Tensor
     sibling="plain": only the smaller children are aggregated and decrypted;
       the larger child's plaintext histogram is the parent's minus the
       smaller one's, formed inside the split finder.
+    packed: the returned histograms are packed before decryption.
     The children of node i of one level are nodes 2i and 2i + 1 of the next."""
     key = res.key
     F = bins.shape[0]
@@ -169,7 +186,7 @@ def tree_round(res: Resident, sk: he.Key, levels: Sequence[Sequence[torch.Tensor
             jobs = [he.Job(idx, bins, n_bins) for idx in lvl]
             he.hist_aggregate(key, res.ctm, jobs, form=he.HE_FORM_MONT, chunk=chunk, stream=stream)
             enc = torch.stack([j.hist for j in jobs])
-            plain = he.decrypt(sk, enc, stream=stream)[0]
+            plain = decrypt_hist(key, sk, enc, packed=packed, stream=stream)
             out.plain.append(plain)
             out.splits.append(split(plain))
         return out
@@ -182,7 +199,7 @@ def tree_round(res: Resident, sk: he.Key, levels: Sequence[Sequence[torch.Tensor
     enc_prev = torch.empty((1, *shape, L2), dtype=torch.int32, device=dev)
     he.hist_aggregate(key, res.ctm, [he.Job(levels[0][0], bins, n_bins, hist=enc_prev[0])], form=he.HE_FORM_MONT,
                       chunk=chunk, stream=stream)
-    plain_prev = he.decrypt(sk, enc_prev, stream=stream)[0]
+    plain_prev = decrypt_hist(key, sk, enc_prev, packed=packed, stream=stream)
     out.plain.append(plain_prev)
     out.splits.append(split(plain_prev))
     slot_node = [0]
@@ -200,10 +217,10 @@ def tree_round(res: Resident, sk: he.Key, levels: Sequence[Sequence[torch.Tensor
         plain = torch.empty((2, P, *shape), dtype=torch.int64, device=dev)
         if sibling == "encrypted":
             he.hist_subtract(key, enc_prev, enc[0], out=enc[1], stream=stream)
-            he.decrypt(sk, enc, out=plain, stream=stream)
+            decrypt_hist(key, sk, enc, out=plain, packed=packed, stream=stream)
             sp_small, sp_large = split(plain[0]), split(plain[1])
         else:
-            he.decrypt(sk, enc[0], out=plain[0], stream=stream)
+            decrypt_hist(key, sk, enc[0], out=plain[0], packed=packed, stream=stream)
             sp_small = split(plain[0])
             sp_large = split(plain_prev, minus=plain[0], derived=plain[1])
         slot_node = small + large

@@ -253,3 +253,33 @@ def test_tree_depth6_full_size(he):
         b = int(np.bincount(bins[f][node], minlength=K).argmax())
         members = node[bins[f][node] == b]
         assert he.limbs_to_ints(hh[f, b, t][None])[0] == closed_form(pk, bits, r_seed, m, members, t)
+
+
+@pytest.mark.parametrize("split", [1, 2])
+@pytest.mark.parametrize("chunk", [1, 7, 64, 5000])
+def test_work_counters(he, small, split, chunk):
+    """The device's count of Montgomery products that join two real partial
+    products equals, for every (job, feature, slot), |S| minus the number of
+    non-empty bins; one conversion per histogram entry; executed products
+    (padding included) bound it from above; the histograms are unchanged."""
+    import torch
+    say(f"work counters chunk={chunk} split={split}")
+    c = small
+    jobs = make_jobs(he, c["tables"], c["shapes"])
+    he.hist_aggregate(c["k"], c["ct"], jobs, chunk=64)
+    want = [j.hist.clone() for j in jobs]
+    jobs2 = make_jobs(he, c["tables"], c["shapes"])
+    hists, cnt = he.hist_aggregate_counted(c["k"], c["ct"], jobs2, chunk=chunk, split=split)
+    for h, w in zip(hists, want):
+        assert torch.equal(h, w)
+    real = conv = 0
+    for sh in c["shapes"]:
+        B, F, f0 = sh["n_bins"], sh["n_features"], sh["f0"]
+        idx = sh["sample_idx"].astype(np.int64)
+        for f in range(F):
+            nonempty = np.unique(c["tables"][B][f0 + f][idx]).size if idx.size else 0
+            real += 2 * (idx.size - nonempty)
+        conv += F * B * 2
+    got = host(cnt).tolist()
+    assert got[0] == real and got[2] == conv
+    assert got[1] >= real + conv

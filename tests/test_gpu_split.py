@@ -124,8 +124,8 @@ def test_split_end_to_end_after_decrypt(he):
 
 def test_tree_round_sibling_modes_agree(he):
     """1024-bit key, 4,000 samples, 6 features x 32 Zipf bins, depth-4 tree:
-    direct, encrypted-sibling and plaintext-sibling rounds give identical
-    plaintext histograms and splits; every node's split equals the oracle's
+    direct, encrypted-sibling and plaintext-sibling rounds (the last also with
+    packed decryption) give identical plaintext histograms and splits; every node's split equals the oracle's
     split of its exact plaintext histogram."""
     import torch
     import oracle.paillier as P
@@ -143,8 +143,9 @@ def test_tree_round_sibling_modes_agree(he):
     bd = torch.from_numpy(bins).cuda()
     lv = [[torch.from_numpy(n.view(np.int32)).cuda() for n in lvl] for lvl in levels]
     runs = {mode: pipeline.tree_round(res, k, lv, bd, K, sibling=mode) for mode in (None, "encrypted", "plain")}
+    runs["plain_packed"] = pipeline.tree_round(res, k, lv, bd, K, sibling="plain", packed=True)
     base = runs[None]
-    for mode in ("encrypted", "plain"):
+    for mode in ("encrypted", "plain", "plain_packed"):
         for a, b in zip(base.plain, runs[mode].plain):
             assert torch.equal(a, b), mode
         for sa, sb in zip(base.splits, runs[mode].splits):

@@ -1,6 +1,6 @@
 """GPU parity of encrypted histogram subtraction (parent times the inverse
-of a child mod n^2) against the oracle, and of the sibling tree mode against
-direct aggregation of every node.  Expected ciphertexts come from the
+of a child mod n^2) and of ciphertext products / re-randomisation against the
+oracle, and of the sibling tree mode against direct aggregation of every node.  Expected ciphertexts come from the
 oracle's ``subtract``; for histograms, from the identity that the parent's
 product divided by one child's is the other child's product."""
 import functools
@@ -159,3 +159,43 @@ def test_sibling_tree_equals_direct(he):
                 want = np.stack([np.bincount(bins[f][idx], weights=m[idx, t].astype(np.float64), minlength=K)
                                  for t in range(2)], axis=-1)
                 assert np.array_equal(dmh[f], np.rint(want).astype(np.int64))
+
+
+@pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
+@pytest.mark.parametrize("count", [1, 37, 1000])
+def test_ct_mul_bit_exact(he, bits, seed, count):
+    say(f"ct_mul {bits} count={count}")
+    sk, k = keys(bits, seed)
+    pk = sk.public
+    rng = np.random.default_rng(count + bits + 1)
+    a = W.random_units(pk.n2, count, rng)
+    b = W.random_units(pk.n2, count, rng)
+    a[0], b[0] = 1, pk.n2 - 1
+    da, db = dev(he.ints_to_limbs(a, 2 * k.limbs)), dev(he.ints_to_limbs(b, 2 * k.limbs))
+    got = he.limbs_to_ints(host(he.ct_mul(k, da, db)))
+    assert got == [P.add(pk, x, y) for x, y in zip(a, b)]
+    he.ct_mul(k, da, db, out=da)  # in place
+    assert he.limbs_to_ints(host(da)) == got
+
+
+def test_rerandomize_histogram_public_key(he):
+    """A passive party (public key only) re-randomises an encrypted histogram:
+    every ciphertext changes, equals the oracle's c E(0; r') for the seeded
+    r', and decrypts to the same sums."""
+    import torch
+    say("rerandomize histogram, public key")
+    sk, k = keys(1024, 1)
+    pk = sk.public
+    kpub = he.Key.public(1024, pk.n)
+    rng = np.random.default_rng(8)
+    count = 300
+    ms = [int(x) for x in rng.integers(-(1 << 40), 1 << 40, size=count)]
+    rs = W.random_units(pk.n, count, rng)
+    cts = [P.encrypt(pk, m, r) for m, r in zip(ms, rs)]
+    h = dev(he.ints_to_limbs(cts, 2 * k.limbs)).view(30, 10, -1)
+    hr = he.rerandomize(kpub, h, seed=4242, offset=5)
+    got = he.limbs_to_ints(host(hr))
+    want = [P.rerandomize(pk, c, P.seeded_r(pk.n, 1024, 4242, 5 + i)) for i, c in enumerate(cts)]
+    assert got == want and all(g != c for g, c in zip(got, cts))
+    dm, _, _ = he.decrypt(k, hr)
+    assert host(dm).reshape(-1).tolist() == ms

@@ -152,6 +152,43 @@ def test_subtract_closed_form(bits, seed):
         assert P.subtract(pk, P.add(pk, c1, c2), c2) == c1
 
 
+@pytest.mark.parametrize("bits,seed", [(256, 3), (1024, 1)])
+def test_rerandomize_closed_form(bits, seed):
+    # E(m; r1) E(0; r) = E(m; r1 r): same plaintext, randomness multiplied.
+    sk = real_key(bits, seed)
+    pk = sk.public
+    rng = random.Random(17)
+    for _ in range(10):
+        m = rng.randrange(-(1 << 50), 1 << 50)
+        r1, r = rng.randrange(1, pk.n), rng.randrange(1, pk.n)
+        c = P.rerandomize(pk, P.encrypt(pk, m, r1), r)
+        assert c == P.encrypt(pk, m, r1 * r % pk.n)
+        assert P.decode(P.decrypt(sk, c), pk.n) == m
+
+
+@pytest.mark.parametrize("bits,seed", [(256, 3), (1024, 1)])
+def test_pack_closed_form_and_roundtrip(bits, seed):
+    # pack(E(m_j; r_j)) = E(sum_j 2^(64 j) (m_j + 2^63); prod_j r_j^(2^(64 j))),
+    # and the slots of its decryption are the m_j (slot values at the edges of
+    # the signed 64-bit range included).
+    sk = real_key(bits, seed)
+    pk = sk.public
+    rng = random.Random(23)
+    max_slots = (bits - 1) // 64
+    for slots in (1, 2, max_slots):
+        ms = [rng.randrange(-(1 << 63), 1 << 63) for _ in range(slots)]
+        ms[0] = -(1 << 63)
+        ms[-1] = (1 << 63) - 1
+        rs = [rng.randrange(1, pk.n) for _ in range(slots)]
+        c = P.pack(pk, [P.encrypt(pk, m, r) for m, r in zip(ms, rs)])
+        plain = sum((m + (1 << 63)) << (64 * j) for j, m in enumerate(ms))
+        rp = 1
+        for j, r in enumerate(rs):
+            rp = rp * pow(r, 1 << (64 * j), pk.n) % pk.n
+        assert c == P.encrypt(pk, plain, rp)
+        assert P.unpack(P.decrypt(sk, c), slots) == ms
+
+
 def test_subtract_histograms_gives_sibling():
     # A parent node's samples split into two children: the parent's encrypted
     # histogram divided by one child's equals the other child's, slot by slot.

@@ -41,36 +41,39 @@ __device__ __forceinline__ uint32_t glane() { return __lane_id() & (G - 1u); }
 // Every lane of the group reads the group's first / last lane.
 //   G = 16: row_newbcast:0 / :15;  G = 8: row_newbcast:0 on banks 0-1 and :8
 //   on banks 2-3 (resp. :7 / :15);  G = 4: quad_perm [0,0,0,0] / [3,3,3,3].
+// Full row and bank masks with every lane reading a valid source lane write
+// every lane, so these use mov_dpp (no "old" value to set up first).
 template <int G = 16>
 __device__ __forceinline__ uint32_t bcast_first(uint32_t v) {
   static_assert(G == 4 || G == 8 || G == 16, "group width");
   if constexpr (G == 16) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x150, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x150, 0xF, 0xF, false);
   } else if constexpr (G == 8) {
     const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x150, 0xF, 0x3, false);
     return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x158, 0xF, 0xC, false);
   } else {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x00, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x00, 0xF, 0xF, false);
   }
 }
 template <int G = 16>
 __device__ __forceinline__ uint32_t bcast_last(uint32_t v) {
   static_assert(G == 4 || G == 8 || G == 16, "group width");
   if constexpr (G == 16) {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x15F, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x15F, 0xF, 0xF, false);
   } else if constexpr (G == 8) {
     const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x157, 0xF, 0x3, false);
     return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x15F, 0xF, 0xC, false);
   } else {
-    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xFF, 0xF, 0xF, false);
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xFF, 0xF, 0xF, false);
   }
 }
 // Lane l reads lane l+1 of its group; the group's last lane reads 0
-// (row_shl:1; for G < 16 the lane that would read across a group edge inside
-// the row is cleared).
+// (row_shl:1 with bound_ctrl, which writes 0 where the source is outside the
+// row; for G < 16 the lane that would read across a group edge inside the
+// row is cleared).
 template <int G = 16>
 __device__ __forceinline__ uint32_t from_next(uint32_t v) {
-  const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x101, 0xF, 0xF, true);
+  const uint32_t t = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x101, 0xF, 0xF, true);
   if constexpr (G == 16) return t;
   else return glane<G>() == G - 1 ? 0u : t;
 }
@@ -81,14 +84,14 @@ __device__ __forceinline__ uint32_t from_next(uint32_t v) {
 // edge fix-up; G = 8 has no 8-lane rotation and uses from_next.
 template <int G = 16>
 __device__ __forceinline__ uint32_t rotate_next(uint32_t v) {
-  if constexpr (G == 4) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x39, 0xF, 0xF, false);
-  else if constexpr (G == 16) return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x12F, 0xF, 0xF, false);
+  if constexpr (G == 4) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x39, 0xF, 0xF, false);
+  else if constexpr (G == 16) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12F, 0xF, 0xF, false);
   else return from_next<G>(v);
 }
 // Lane l reads lane l-1 of its group; the group's first lane reads 0 (row_shr:1).
 template <int G = 16>
 __device__ __forceinline__ uint32_t from_prev(uint32_t v) {
-  const uint32_t t = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);
+  const uint32_t t = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x111, 0xF, 0xF, true);
   if constexpr (G == 16) return t;
   else return glane<G>() == 0 ? 0u : t;
 }

@@ -23,7 +23,7 @@ COMMON = [
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wno-unused-result", f"-I{os.path.join(ROOT, 'include')}", f"-I{CSRC}",
 ]
-SOURCES = ["he_kernels.hip", "he_api.cpp"]
+SOURCES = ["he_kernels.hip", "he_api.cpp", "ckks.hip"]
 
 
 def hipcc() -> str:

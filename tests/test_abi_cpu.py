@@ -1,5 +1,5 @@
 """CPU-side checks of the C ABI library: it loads, exports every function
-include/he.h declares, and its host-side argument checks reject bad input
+the headers in include/ declare, and its host-side argument checks reject bad input
 without touching a GPU.  The host bignum that derives the per-key constants is
 checked through a small g++ harness against Python integer arithmetic."""
 import ctypes
@@ -10,12 +10,13 @@ import subprocess
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "he.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in sorted(os.listdir(os.path.join(ROOT, "include")))
+           if h.endswith(".h")]
 LIB = os.path.join(ROOT, "paper_2504_03909_amd", "libhe_mi355x.so")
 
 
 def declared_functions():
-    src = open(HEADER).read()
+    src = "".join(open(h).read() for h in HEADERS)
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
     return sorted(set(re.findall(r"\b(he_[a-z0-9_]+)\s*\(", src)))
 
@@ -40,8 +41,8 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_binding_lists_every_declared_symbol():
-    from paper_2504_03909_amd import he  # loads the library, no GPU call
-    assert sorted(he.EXPORTED) == declared_functions()
+    from paper_2504_03909_amd import ckks, he  # load the library, no GPU call
+    assert sorted(he.EXPORTED + ckks.EXPORTED) == declared_functions()
 
 
 def test_host_side_argument_errors(lib):
@@ -61,6 +62,14 @@ def test_host_side_argument_errors(lib):
     assert lib.he_hist_subtract(None, None, None, 1, 0, None, None, None) == -1
     lib.he_encrypt_obfuscated.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_uint64] + [ctypes.c_void_p] * 3
     assert lib.he_encrypt_obfuscated(None, None, 1, None, None, None) == -1
+    lib.he_ckks_create.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p]
+    lib.he_ckks_last_error.restype = ctypes.c_char_p
+    h2 = ctypes.c_void_p()
+    assert lib.he_ckks_create(9, 40, 1, ctypes.byref(h2)) == -1
+    assert b"log_n" in lib.he_ckks_last_error()
+    assert lib.he_ckks_create(14, 70, 1, ctypes.byref(h2)) == -1
+    lib.he_ckks_encrypt.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_uint64] * 3 + [ctypes.c_void_p] * 2
+    assert lib.he_ckks_encrypt(None, None, 1, 0, 0, None, None) == -1
     lib.he_probe_int_mul.argtypes = [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
     assert lib.he_probe_int_mul(0, 0, None, None) == -1
 

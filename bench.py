@@ -16,6 +16,9 @@ Other workloads (each prints its own JSON line; not the default):
                          one launch per job vs one batched launch vs graph replay
     --workload served    request loop (Poisson arrivals, two keys, four parties):
                          continuous batching vs FIFO one-request-per-launch
+    --workload horizontal  secure horizontal round with CKKS: 5 clients encrypt
+                         G and H vectors of 7,680 values, the server adds, clients
+                         decrypt; plus batched encryption throughput
 """
 from __future__ import annotations
 
@@ -152,7 +155,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", default="pass", choices=("pass", "tree", "batched", "served"))
+    ap.add_argument("--workload", default="pass", choices=("pass", "tree", "batched", "served", "horizontal"))
     ap.add_argument("--requests", type=int, default=300)
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -179,7 +182,8 @@ def main():
         print(json.dumps({"calibration_copy_bytes": 4 * n}), flush=True)
         return
     if args.workload != "pass":
-        line = {"tree": bench_tree, "batched": bench_batched, "served": bench_served}[args.workload](args)
+        line = {"tree": bench_tree, "batched": bench_batched, "served": bench_served,
+                "horizontal": bench_horizontal}[args.workload](args)
         print(json.dumps(line), flush=True)
         return
     stream = torch.cuda.current_stream()
@@ -479,6 +483,71 @@ def bench_batched(args):
         "montgomery_products": {"joining_real_partials": mm_real, "executed": mm_done,
                                 "conversions_out": mm_conv,
                                 "executed_over_needed": round(mm_done / max(1, mm_real + mm_conv), 4)},
+    }
+
+
+def bench_horizontal(args):
+    """Secure horizontal round (CKKS, N = 2^14, three 30-bit primes, scale
+    2^40): 5 clients each encode and encrypt a G and an H vector of 7,680
+    values, the server adds the 5 ciphertexts of each, a client decrypts and
+    decodes the two sums.  Then 1,000 vectors encrypted in one call."""
+    import numpy as np
+    import torch
+    from paper_2504_03909_amd import ckks
+    clients, length = 5, 7680
+    ctx = ckks.Context(14, 40, KEY_SEED)
+    rng = np.random.default_rng(DATA_SEED)
+    G = rng.normal(0, 200, size=(clients, length))
+    H = rng.uniform(0, 500, size=(clients, length))
+    z = torch.from_numpy(np.concatenate([G, H])).cuda()
+    stream = torch.cuda.current_stream()
+
+    def round_(marks):
+        marks[0].record(stream)
+        pt = ctx.encode(z)
+        marks[1].record(stream)
+        ct = ctx.encrypt(pt, seed=R_SEED)
+        marks[2].record(stream)
+        acc = ct[[0, clients]].contiguous()
+        for c in range(1, clients):
+            acc = ctx.add(acc, ct[[c, clients + c]].contiguous())
+        marks[3].record(stream)
+        dec = ctx.decrypt(acc)
+        marks[4].record(stream)
+        out = ctx.decode(dec, length)
+        marks[5].record(stream)
+        return out
+
+    ev = lambda: torch.cuda.Event(enable_timing=True)
+    round_([ev() for _ in range(6)])
+    torch.cuda.synchronize()
+    runs = []
+    for _ in range(max(1, args.steps)):
+        mk = [ev() for _ in range(6)]
+        out = round_(mk)
+        torch.cuda.synchronize()
+        runs.append([mk[i].elapsed_time(mk[i + 1]) for i in range(5)] + [mk[0].elapsed_time(mk[5])])
+    st = np.median(np.array(runs), axis=0)
+    err = float(np.abs(out.cpu().numpy() - np.stack([G.sum(0), H.sum(0)])).max())
+    # throughput: 1,000 vectors in one call
+    zb = torch.from_numpy(rng.normal(0, 200, size=(1000, length))).cuda()
+    ptb = ctx.encode(zb)
+    ctb = ctx.encrypt(ptb, seed=R_SEED + 1)
+    _, t_enc = _timed(lambda: ctx.encrypt(ptb, seed=R_SEED + 1, out=ctb), "ckks encrypt 1000")
+    _, t_code = _timed(lambda: ctx.encode(zb), "ckks encode 1000")
+    _, t_dec = _timed(lambda: ctx.decode(ctx.decrypt(ctb), length), "ckks decrypt+decode 1000")
+    return {
+        "metric": "secure horizontal round time and CKKS vector encryptions/s",
+        "workload": "CKKS N=16384, 3 x 30-bit primes, scale 2^40; 5 clients x (G, H) vectors of 7680 values",
+        "round_ms": round(float(st[5]), 3),
+        "stages_ms": {"encode_10": round(float(st[0]), 3), "encrypt_10": round(float(st[1]), 3),
+                      "server_add_8": round(float(st[2]), 3), "decrypt_2": round(float(st[3]), 3),
+                      "decode_2": round(float(st[4]), 3)},
+        "max_abs_error": err,
+        "batch_1000": {"encrypt_ms": round(t_enc * 1e3, 3), "encode_ms": round(t_code * 1e3, 3),
+                       "decrypt_decode_ms": round(t_dec * 1e3, 3),
+                       "vector_encryptions_per_s": round(1000 / t_enc, 1),
+                       "values_encrypted_per_s": round(1000 * length / t_enc, 1)},
     }
 
 

@@ -44,7 +44,7 @@ MI355X_HBM_BPS = 8.0e12
 # by a 256 MiB copy (profiles/enc_crt_2048_100k_counters.md).  Valid for the
 # kernel build those passes ran on; set to None when the encryption kernels
 # change until the passes are repeated.
-ENC_LAUNCH_TRAFFIC_BYTES = None
+ENC_LAUNCH_TRAFFIC_BYTES = 3.0654e10
 
 
 def mm_products(s: int) -> int:
@@ -215,6 +215,11 @@ def main():
         marks[4].record(stream)
         return dm, ovf
 
+    # Setup: one encryption of the gradients so the autotuner can pick the
+    # histogram work shape for this shape class (used by every step below).
+    he.encrypt(key, he.encode(grads), seed=R_SEED, out=ct.view(-1, 2 * L))
+    tuned_chunk, tuned_split, tuned_ms = (he.hist_autotune(key, ct, [he.Job(idx, bins, K)])
+                                          if args.chunk == 0 else (args.chunk, 2, None))
     for _ in range(args.warmup):
         step([ev() for _ in range(5)])
     torch.cuda.synchronize()
@@ -260,6 +265,20 @@ def main():
     obf_same = bool(torch.equal(ct_obf, ct.view(-1, 2 * L)))
     t_off, t_on = obf_marks[0].elapsed_time(obf_marks[1]), obf_marks[1].elapsed_time(obf_marks[2])
     del rho, ct_obf
+    # Beside the step: packed decryption of the same 16,384 histogram
+    # ciphertexts (the passive party folds 4 per ciphertext).
+    pk_marks = [ev() for _ in range(3)]
+    packed, slots = he.pack(key, hist)
+    he.decrypt_packed(key, packed, J * K * 2, slots)
+    pk_marks[0].record(stream)
+    packed, slots = he.pack(key, hist)
+    pk_marks[1].record(stream)
+    dm_packed, _ = he.decrypt_packed(key, packed, J * K * 2, slots)
+    pk_marks[2].record(stream)
+    torch.cuda.synchronize()
+    packed_same = bool(torch.equal(dm_packed.view(dm.shape), dm))
+    t_pack, t_dpk = pk_marks[0].elapsed_time(pk_marks[1]), pk_marks[1].elapsed_time(pk_marks[2])
+    ms_packed_pass = ms_step - avg["decrypt"] + t_pack + t_dpk
 
     enc_products = crt_encrypt_products(p, q, L)
     achieved = 2 * M * enc_products / (avg["encrypt"] / 1e3)
@@ -280,7 +299,8 @@ def main():
             "workload": "2048-bit key, 100000 samples, 32 features x 256 Zipf(1.1) bins, root node: "
                         "encode + encrypt 200000 + encrypted histogram + CRT decrypt 16384",
             "key_bits": KEY_BITS, "samples": M, "features": J, "bins": K, "r": "seeded",
-            "encrypt_path": "crt", "chunk": args.chunk or 64,
+            "encrypt_path": "crt", "hist_chunk": tuned_chunk, "hist_split": tuned_split,
+            "hist_shape": "autotuned before timing" if args.chunk == 0 else "given",
         },
         "stages": {
             "encode_ms": round(avg["encode"], 3),
@@ -314,6 +334,10 @@ def main():
             "products_per_ciphertext": enc_products,
         },
         "parity_self_check": bool(ok),
+        "packed_decryption": {"slots": slots, "pack_ms": round(t_pack, 3), "decrypt_ms": round(t_dpk, 3),
+                              "equals_decrypt": packed_same,
+                              "pass_ms_with_it": round(ms_packed_pass, 3),
+                              "pass_encryptions_per_s_with_it": round(2 * M / (ms_packed_pass / 1e3), 1)},
         "obfuscated_encryption": {
             "offline_obfuscators_ms": round(t_off, 3),
             "online_encrypt_ms": round(t_on, 3),

@@ -27,7 +27,7 @@ mod n; encrypted addition is the product of ciphertexts mod n^2, and
 encrypted subtraction (a node's histogram "minus" one child's, for the
 sibling) multiplies by the inverse mod n^2.
 
-Readings where the paper is silent (each is also listed in the design doc):
+Readings where the paper is silent:
 key sizes 1024/2048 bits with p, q of exactly half the bits (top two bits set);
 fixed-point encoding rint(x * 2^32) with round-half-even and negatives taken
 mod n; r drawn from a counter-based SplitMix64 word stream reduced mod n;

@@ -86,6 +86,7 @@ struct HistWs {
 constexpr int kWindowBits = 5;     // exponent window width (see mont.hpp)
 constexpr int kSampleBlock = 4096;   // samples per bucketing block
 constexpr int kBlockThreads = 256;   // 4 waves
+constexpr int kHistGroup = 16;      // lanes per integer in the histogram kernels (8 measured slower)
 
 // ---- launchers (he_kernels.hip) ------------------------------------------------
 // KP = limbs per lane of a prime: 1 for 1024-bit keys, 2 for 2048-bit keys.

@@ -874,86 +874,98 @@ __global__ __launch_bounds__(256) void k_hist_scatter(HistWs ws) {
   }
 }
 
-// Product of the ciphertexts of one item (chunk) per (item, slot).  With
-// split 2 a wave takes one item: groups 0/1 take slot g/h of the first half
-// of the chunk, groups 2/3 of the second half, and the halves are combined at
-// the end.  With split 1 a wave takes two items, one group per (item, slot).
-// Output in Montgomery form.
-template <int KP>
+// Product of the ciphertexts of one item (chunk) per (item, slot), in
+// groups of G lanes (GW = 64 / G groups per wave; bit 0 of a group's index is
+// the slot g/h).  With split 2 an item is taken by four groups: bit 1 of the
+// group index picks the first or second half of the chunk, the halves are
+// combined at the end, and a wave takes GW / 4 items.  With split 1 a wave
+// takes GW / 2 items, one group per (item, slot).  Output in Montgomery form.
+// Every loop bound is the maximum over the wave's items, so the cross-lane
+// steps of the arithmetic always run on the whole wave.
+template <int KP, int G>
 __global__ __launch_bounds__(kBlockThreads) void k_hist_chunk(DKey key, const uint32_t *__restrict__ ctm,
                                                              HistWs ws) {
-  constexpr int K = 4 * KP, S = 64 * KP;
-  __shared__ __align__(16) uint32_t lds_all[16 * S];
-  const uint32_t g = group_in_wave();
-  const uint32_t wrow = wave_in_block() * 4;
+  constexpr int S = 64 * KP, K = S / G, GW = 64 / G;
+  __shared__ __align__(16) uint32_t lds_all[(kBlockThreads / 64) * GW * S];
+  const uint32_t g = (threadIdx.x & 63u) / G;
+  const uint32_t wrow = wave_in_block() * GW;
   uint32_t *lds = lds_all + (wrow + g) * S;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  const uint32_t slot = g & 1u, sub = g >> 1;
+  const uint32_t slot = g & 1u;
   const bool split = ws.split == 2;
-  const Mod<K> M = load_mod<K>(key.n2.N, key.n2.ninv);
+  const uint32_t half = (g >> 1) & 1u;
+  const Mod<K> M = load_mod<K, G>(key.n2.N, key.n2.ninv);
   uint32_t one[K];
-  ld<K>(one, key.n2.R1);
+  ld<K, G>(one, key.n2.R1);
   const uint64_t n_items = *ws.n_items;
-  const uint64_t per_wave = split ? 1 : 2;
+  const uint64_t per_wave = split ? GW / 4 : GW / 2;
   for (uint64_t w0 = gw * per_wave; w0 < n_items; w0 += nw * per_wave) {
     // this group's sample run and the wave-wide trip count
+    const uint64_t it = w0 + (split ? (g >> 2) : (g >> 1));
+    const bool valid = it < n_items;
+    const HistItem item = ws.items[valid ? it : n_items - 1];
+    uint32_t trip = 0;
+    for (uint64_t w = w0; w < w0 + per_wave && w < n_items; ++w) {
+      const uint32_t l = ws.items[w].len;
+      trip = max(trip, split ? (l + 1) >> 1 : l);
+    }
     uint64_t start;
-    uint32_t my_len, trip;
-    uint64_t it;
+    uint32_t my_len;
     if (split) {
-      it = w0;
-      const HistItem item = ws.items[it];
       const uint32_t len_lo = (item.len + 1) >> 1;
-      my_len = sub ? item.len >> 1 : len_lo;
-      start = item.start + (sub ? len_lo : 0u);
-      trip = len_lo;
+      my_len = valid ? (half ? item.len >> 1 : len_lo) : 0u;
+      start = item.start + (half ? len_lo : 0u);
     } else {
-      const HistItem a = ws.items[w0];
-      const bool has_b = w0 + 1 < n_items;
-      const HistItem b = ws.items[has_b ? w0 + 1 : w0];
-      const uint32_t len_b = has_b ? b.len : 0u;
-      it = w0 + sub;
-      my_len = sub ? len_b : a.len;
-      start = sub ? b.start : a.start;
-      trip = max(a.len, len_b);
+      my_len = valid ? item.len : 0u;
+      start = item.start;
     }
     const uint32_t *pp = ws.perm + start;
     uint32_t acc[K], b[K];
     if (my_len)
-      ld<K>(acc, ctm + ((uint64_t)pp[0] * 2 + slot) * S);
+      ld<K, G>(acc, ctm + ((uint64_t)pp[0] * 2 + slot) * S);
     else
       copy(acc, one);
     const uint32_t last = my_len ? my_len - 1 : 0u;
-    if (trip > 1) ld<K>(b, ctm + ((uint64_t)pp[min(1u, last)] * 2 + slot) * S);
+    if (trip > 1) {
+      if (my_len)
+        ld<K, G>(b, ctm + ((uint64_t)pp[min(1u, last)] * 2 + slot) * S);
+      else
+        copy(b, one);
+    }
 #pragma unroll 1
     for (uint32_t k = 1; k < trip; ++k) {
       uint32_t nb[K];
-      if (k + 1 < trip) ld<K>(nb, ctm + ((uint64_t)pp[min(k + 1, last)] * 2 + slot) * S);
+      if (k + 1 < trip) {
+        if (my_len)
+          ld<K, G>(nb, ctm + ((uint64_t)pp[min(k + 1, last)] * 2 + slot) * S);
+        else
+          copy(nb, one);
+      }
       uint32_t t[K];
-      mont_mul<K>(t, acc, b, M, lds);
+      mont_mul<K, G>(t, acc, b, M, lds);
       select(acc, k < my_len, t, acc);
       if (k + 1 < trip) copy(b, nb);
     }
     if (split) {
       // combine the two halves
-      st<K>(lds, acc);
+      st<K, G>(lds, acc);
       __builtin_amdgcn_wave_barrier();
       uint32_t other[K];
-      ld<K>(other, lds_all + (wrow + (g ^ 2u)) * S);
+      ld<K, G>(other, lds_all + (wrow + (g ^ 2u)) * S);
       __builtin_amdgcn_wave_barrier();
-      mont_mul<K>(acc, acc, other, M, lds);
-      if (sub == 0) st<K>(ws.partials + (it * 2 + slot) * S, acc);
-    } else if (it < n_items) {
-      st<K>(ws.partials + (it * 2 + slot) * S, acc);
+      mont_mul<K, G>(acc, acc, other, M, lds);
+      if (half == 0 && valid) st<K, G>(ws.partials + (it * 2 + slot) * S, acc);
+    } else if (valid) {
+      st<K, G>(ws.partials + (it * 2 + slot) * S, acc);
     }
-    if (ws.mm_count && glane() == 0) {
+    if (ws.mm_count && glane<G>() == 0) {
       // products joining two real partials (the algorithm's count) and
       // products this group executed, masked padding included
       uint64_t real = my_len ? my_len - 1 : 0, done = trip ? trip - 1 : 0;
       if (split) {
         done += 1;
-        real += (sub == 0 && my_len >= 1 && ws.items[it].len >= 2) ? 1 : 0;
+        real += (half == 0 && my_len >= 1 && item.len >= 2) ? 1 : 0;
       }
       atomicAdd(&ws.mm_count[0], (unsigned long long)real);
       atomicAdd(&ws.mm_count[1], (unsigned long long)done);
@@ -962,56 +974,71 @@ __global__ __launch_bounds__(kBlockThreads) void k_hist_chunk(DKey key, const ui
 }
 
 // Final product over the chunks of one (job, feature, bin), conversion out of
-// Montgomery form, and the store into the job's histogram.  One entry per
-// wave, chunks split between the two group pairs like k_hist_chunk.
-template <int KP>
+// Montgomery form, and the store into the job's histogram.  GW / 4 entries
+// per wave, each taken by four groups (slot g/h x first/second half of its
+// chunks) like k_hist_chunk.
+template <int KP, int G>
 __global__ __launch_bounds__(kBlockThreads) void k_hist_final(DKey key, HistWs ws) {
-  constexpr int K = 4 * KP, S = 64 * KP;
-  __shared__ __align__(16) uint32_t lds_all[16 * S];
-  const uint32_t g = group_in_wave();
-  const uint32_t wrow = wave_in_block() * 4;
+  constexpr int S = 64 * KP, K = S / G, GW = 64 / G, EPW = GW / 4;
+  __shared__ __align__(16) uint32_t lds_all[(kBlockThreads / 64) * GW * S];
+  const uint32_t g = (threadIdx.x & 63u) / G;
+  const uint32_t wrow = wave_in_block() * GW;
   uint32_t *lds = lds_all + (wrow + g) * S;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  const uint32_t slot = g & 1u, half = g >> 1;
-  const Mod<K> M = load_mod<K>(key.n2.N, key.n2.ninv);
+  const uint32_t slot = g & 1u, half = (g >> 1) & 1u;
+  const Mod<K> M = load_mod<K, G>(key.n2.N, key.n2.ninv);
   uint32_t one[K];
-  ld<K>(one, key.n2.R1);
-  for (uint64_t e = gw; e < ws.total_fb; e += nw) {
-    const uint32_t jn = find_job_by_fb(ws.jobs, ws.n_jobs, e);
+  ld<K, G>(one, key.n2.R1);
+  for (uint64_t e0 = gw * EPW; e0 < ws.total_fb; e0 += nw * EPW) {
+    const uint64_t e = e0 + (g >> 2);
+    const bool valid = e < ws.total_fb;
+    const uint64_t ee = valid ? e : ws.total_fb - 1;
+    const uint32_t jn = find_job_by_fb(ws.jobs, ws.n_jobs, ee);
     const DJob J = ws.jobs[jn];
-    const uint64_t fb = e - J.fb_off;
-    const uint32_t nch = ws.fch[e], first = ws.fitem[e];
+    const uint64_t fb = ee - J.fb_off;
+    const uint32_t nch = valid ? ws.fch[ee] : 0u, first = ws.fitem[ee];
     const uint32_t n_lo = (nch + 1) >> 1, n_hi = nch >> 1;
     const uint32_t my_n = half ? n_hi : n_lo;
     const uint64_t p0 = (uint64_t)first + (half ? n_lo : 0u);
+    // wave-wide bounds over the wave's entries
+    uint32_t lo_max = 0, hi_any = 0;
+    for (uint64_t w = e0; w < e0 + EPW && w < ws.total_fb; ++w) {
+      lo_max = max(lo_max, (ws.fch[w] + 1) >> 1);
+      hi_any |= ws.fch[w] >> 1;
+    }
     uint32_t acc[K], b[K];
     if (my_n)
-      ld<K>(acc, ws.partials + (p0 * 2 + slot) * S);
+      ld<K, G>(acc, ws.partials + (p0 * 2 + slot) * S);
     else
       copy(acc, one);
 #pragma unroll 1
-    for (uint32_t k = 1; k < n_lo; ++k) {
+    for (uint32_t k = 1; k < lo_max; ++k) {
       const uint32_t kk = min(k, my_n ? my_n - 1 : 0u);
-      ld<K>(b, ws.partials + ((p0 + kk) * 2 + slot) * S);
+      if (my_n)
+        ld<K, G>(b, ws.partials + ((p0 + kk) * 2 + slot) * S);
+      else
+        copy(b, one);
       uint32_t t[K];
-      mont_mul<K>(t, acc, b, M, lds);
+      mont_mul<K, G>(t, acc, b, M, lds);
       select(acc, k < my_n, t, acc);
     }
-    if (n_hi) {  // wave-uniform: one entry per wave
-      st<K>(lds, acc);
+    if (hi_any) {  // wave-uniform
+      st<K, G>(lds, acc);
       __builtin_amdgcn_wave_barrier();
       uint32_t other[K];
-      ld<K>(other, lds_all + (wrow + (g ^ 2u)) * S);
+      ld<K, G>(other, lds_all + (wrow + (g ^ 2u)) * S);
       __builtin_amdgcn_wave_barrier();
-      mont_mul<K>(acc, acc, other, M, lds);
+      uint32_t t[K];
+      mont_mul<K, G>(t, acc, other, M, lds);
+      select(acc, n_hi != 0u, t, acc);
     }
-    set_small(b, 1u);
-    mont_mul<K>(acc, acc, b, M, lds);  // out of Montgomery form
-    if (half == 0) st<K>(J.hist + (fb * 2 + slot) * S, acc);
-    if (ws.mm_count && glane() == 0) {
+    set_small<K, G>(b, 1u);
+    mont_mul<K, G>(acc, acc, b, M, lds);  // out of Montgomery form
+    if (half == 0 && valid) st<K, G>(J.hist + (fb * 2 + slot) * S, acc);
+    if (ws.mm_count && glane<G>() == 0 && valid) {
       const uint64_t real = (my_n ? my_n - 1 : 0) + ((half == 0 && n_hi) ? 1 : 0);
-      const uint64_t done = (n_lo ? n_lo - 1 : 0) + (n_hi ? 1 : 0) + 1;
+      const uint64_t done = (lo_max ? lo_max - 1 : 0) + (hi_any ? 1 : 0) + 1;
       atomicAdd(&ws.mm_count[0], (unsigned long long)real);
       atomicAdd(&ws.mm_count[1], (unsigned long long)done);
       if (half == 0) atomicAdd(&ws.mm_count[2], 1ull);
@@ -1221,9 +1248,10 @@ static hipError_t hist(const DKey &k, const uint32_t *ctm, const DJob *host_jobs
   hipLaunchKernelGGL(k_hist_items, dim3((uint32_t)ws.total_f), dim3(256), 0, s, ws);
   if (ws.total_blocks)
     hipLaunchKernelGGL(k_hist_scatter, dim3((uint32_t)ws.total_blocks), dim3(256), 0, s, ws);
-  hipLaunchKernelGGL(k_hist_chunk<KP>, dim3(chunk_grid), dim3(kBlockThreads), 0, s, k, ctm, ws);
-  const uint32_t fgrid = (uint32_t)std::min<uint64_t>(blocks_for(ws.total_fb, 4), 1u << 20);
-  hipLaunchKernelGGL(k_hist_final<KP>, dim3(fgrid), dim3(kBlockThreads), 0, s, k, ws);
+  hipLaunchKernelGGL((k_hist_chunk<KP, kHistGroup>), dim3(chunk_grid), dim3(kBlockThreads), 0, s, k, ctm, ws);
+  constexpr uint32_t entries_per_block = 4 * (64 / kHistGroup) / 4;
+  const uint32_t fgrid = (uint32_t)std::min<uint64_t>(blocks_for(ws.total_fb, entries_per_block), 1u << 20);
+  hipLaunchKernelGGL((k_hist_final<KP, kHistGroup>), dim3(fgrid), dim3(kBlockThreads), 0, s, k, ws);
   return hipGetLastError();
 }
 hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *host_jobs,
@@ -1278,7 +1306,9 @@ uint32_t resident_blocks(int KP, int kind, int G) {
       else if (G == 8) fn = one ? (const void *)k_dec_a<1, 8> : (const void *)k_dec_a<2, 8>;
       else fn = one ? (const void *)k_dec_a<1, 16> : (const void *)k_dec_a<2, 16>;
       break;
-    default: fn = one ? (const void *)k_hist_chunk<1> : (const void *)k_hist_chunk<2>; break;
+    default:
+      fn = one ? (const void *)k_hist_chunk<1, kHistGroup> : (const void *)k_hist_chunk<2, kHistGroup>;
+      break;
   }
   c = occupancy_blocks(fn);
   return c;

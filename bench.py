@@ -279,6 +279,15 @@ def main():
     packed_same = bool(torch.equal(dm_packed.view(dm.shape), dm))
     t_pack, t_dpk = pk_marks[0].elapsed_time(pk_marks[1]), pk_marks[1].elapsed_time(pk_marks[2])
     ms_packed_pass = ms_step - avg["decrypt"] + t_pack + t_dpk
+    # Multiply-rate probe: 8 multiply-add chains per lane on 2,048 blocks of
+    # 256 threads, the measured counterpart of the derived peak.
+    he.probe_int_mul(64, 2048)
+    pr_marks = [ev(), ev()]
+    pr_marks[0].record(stream)
+    n_probe = he.probe_int_mul(4096, 2048)
+    pr_marks[1].record(stream)
+    torch.cuda.synchronize()
+    probe_rate = n_probe / (pr_marks[0].elapsed_time(pr_marks[1]) / 1e3)
 
     enc_products = crt_encrypt_products(p, q, L)
     achieved = 2 * M * enc_products / (avg["encrypt"] / 1e3)
@@ -328,6 +337,8 @@ def main():
             "unit": "T mul32/s",
             "frac": round(achieved / PEAK_MUL32_PER_S, 4),
             "traffic": ENC_LAUNCH_TRAFFIC_BYTES,
+            "probe_measured": round(probe_rate / 1e12, 3),
+            "frac_of_probe": round(achieved / probe_rate, 4),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
             "algorithmic_bytes_per_launch": 2 * M * (8 + 4 * 2 * L),
             "algorithmic_products_per_launch": 2 * M * enc_products,

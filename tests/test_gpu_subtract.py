@@ -199,3 +199,23 @@ def test_rerandomize_histogram_public_key(he):
     assert got == want and all(g != c for g, c in zip(got, cts))
     dm, _, _ = he.decrypt(k, hr)
     assert host(dm).reshape(-1).tolist() == ms
+
+
+def test_shard_partials_combine_to_whole(he):
+    """The combine step of sample sharding: histograms of two disjoint sample
+    shards, multiplied slot by slot, equal the histogram of all samples."""
+    import torch
+    say("shard partial histograms combine")
+    sk, k = keys(2048, 2)
+    s = W.streams(21)
+    M, J, K = 30000, 16, 64
+    g = W.gradients(M, s[1])
+    bins = dev(W.bins_zipf(J, M, K, s[2]))
+    ct = he.encrypt(k, he.encode(dev(g.reshape(-1))), seed=8).view(M, 2, -1)
+    perm = np.random.default_rng(3).permutation(M)
+    a = np.sort(perm[: M // 3]).astype(np.int32)
+    b = np.sort(perm[M // 3:]).astype(np.int32)
+    (ha,) = he.hist_aggregate(k, ct, [he.Job(dev(a), bins, K)])
+    (hb,) = he.hist_aggregate(k, ct, [he.Job(dev(b), bins, K)])
+    (hall,) = he.hist_aggregate(k, ct, [he.Job(torch.arange(M, dtype=torch.int32, device="cuda"), bins, K)])
+    assert torch.equal(he.ct_mul(k, ha, hb), hall)

@@ -93,7 +93,7 @@ __global__ void k_encode(const double *__restrict__ x, uint64_t count, uint32_t 
 // the same for the whole wave.  Output cpq[i][P] (S_P2 limbs, canonical).
 // G = lanes per integer (kEncGroup).
 template <int KP, int G>
-__global__ __launch_bounds__(kBlockThreads) void k_enc_crt_a(
+__global__ __launch_bounds__(kBlockThreads, 3) void k_enc_crt_a(
     DKey key, const int64_t *__restrict__ m, uint64_t count, const uint32_t *__restrict__ r,
     uint64_t seed, uint64_t roff, uint32_t *__restrict__ cpq, uint32_t *__restrict__ tabs) {
   constexpr int SP = 16 * KP, SP2 = 32 * KP, L = SP2;
@@ -600,7 +600,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_mont_convert(DKey key, const 
 //   x = c^(P-1) mod P^2,  m_P = ((x - 1) / P) h_P mod P.
 // Work unit = (prime, 64/G consecutive ciphertexts); G = lanes per integer.
 template <int KP, int G>
-__global__ __launch_bounds__(kBlockThreads) void k_dec_a(DKey key, const uint32_t *__restrict__ ct,
+__global__ __launch_bounds__(kBlockThreads, 3) void k_dec_a(DKey key, const uint32_t *__restrict__ ct,
                                                         uint64_t count, uint32_t *__restrict__ mpq,
                                                         uint32_t *__restrict__ tabs) {
   constexpr int SP = 16 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
@@ -883,7 +883,7 @@ __global__ __launch_bounds__(256) void k_hist_scatter(HistWs ws) {
 // Every loop bound is the maximum over the wave's items, so the cross-lane
 // steps of the arithmetic always run on the whole wave.
 template <int KP, int G>
-__global__ __launch_bounds__(kBlockThreads) void k_hist_chunk(DKey key, const uint32_t *__restrict__ ctm,
+__global__ __launch_bounds__(kBlockThreads, 5) void k_hist_chunk(DKey key, const uint32_t *__restrict__ ctm,
                                                              HistWs ws) {
   constexpr int S = 64 * KP, K = S / G, GW = 64 / G;
   __shared__ __align__(16) uint32_t lds_all[(kBlockThreads / 64) * GW * S];
@@ -1321,12 +1321,22 @@ uint64_t table_bytes_per_block(int KP, int kind, int G) {
 
 // Group width for a CRT exponentiation kernel (kind 0 encryption, 2
 // decryption) over `count` ciphertexts: the narrowest group (more limbs per
-// lane, less cross-lane work per product) whose launch still has enough
-// waves to fill every resident slot of the device.
+// lane, less cross-lane work per product) whose launch still gives every
+// SIMD at least two waves; below that, wider groups buy parallelism.
 int pick_group(int KP, int kind, uint64_t count) {
+  (void)KP;
+  (void)kind;
+  static int cus = 0;
+  if (!cus) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+      cus = 1;
+  }
+  const uint64_t need = 2ull * 4 * (uint64_t)cus;  // two waves on each of the 4 SIMDs per CU
   for (int G : {4, 8}) {
     const uint64_t waves = 2 * ((count + 64 / G - 1) / (64 / G));
-    if (waves >= (uint64_t)resident_blocks(KP, kind, G) * 4) return G;
+    if (waves >= need) return G;
   }
   return 16;
 }

@@ -93,7 +93,7 @@ __global__ void k_encode(const double *__restrict__ x, uint64_t count, uint32_t 
 // the same for the whole wave.  Output cpq[i][P] (S_P2 limbs, canonical).
 // G = lanes per integer (kEncGroup).
 template <int KP, int G>
-__global__ __launch_bounds__(kBlockThreads, 3) void k_enc_crt_a(
+__global__ __launch_bounds__(kBlockThreads, 4) void k_enc_crt_a(
     DKey key, const int64_t *__restrict__ m, uint64_t count, const uint32_t *__restrict__ r,
     uint64_t seed, uint64_t roff, uint32_t *__restrict__ cpq, uint32_t *__restrict__ tabs) {
   constexpr int SP = 16 * KP, SP2 = 32 * KP, L = SP2;

@@ -39,12 +39,12 @@ KEY_SEED, R_SEED, DATA_SEED = 2, 2024, 1
 # (v_mad_u64_u32) per lane per clock.
 PEAK_MUL32_PER_S = 256 * 64 * 2.4e9
 MI355X_HBM_BPS = 8.0e12
-# HBM-side bytes of one encryption launch (k_enc_crt_a + k_enc_crt_b over
-# 200,000 ciphertexts), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled
+# HBM-side bytes of one encryption launch (k_enc_p1 + k_enc_p2 + k_enc_crt_b
+# over 200,000 ciphertexts), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled
 # by a 256 MiB copy (profiles/enc_crt_2048_100k_counters.md).  Valid for the
 # kernel build those passes ran on; set to None when the encryption kernels
 # change until the passes are repeated.
-ENC_LAUNCH_TRAFFIC_BYTES = 3.8767e10
+ENC_LAUNCH_TRAFFIC_BYTES = None
 
 
 def mm_products(s: int) -> int:
@@ -330,7 +330,7 @@ def main():
         "step_latency_ms": {"p50": round(percentile(stage_ms["step"], 0.5), 3),
                             "p99": round(percentile(stage_ms["step"], 0.99), 3)},
         "roofline": {
-            "kernel": "k_enc_crt_a + k_enc_crt_b (CRT encryption)",
+            "kernel": "k_enc_p1 + k_enc_p2 + k_enc_crt_b (CRT encryption)",
             "bound": "alu",
             "achieved": round(achieved / 1e12, 3),
             "peak": round(PEAK_MUL32_PER_S / 1e12, 3),

@@ -182,15 +182,19 @@ int encrypt_impl(const he_key *key, const int64_t *m, uint64_t count, const uint
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
   if (key->priv && !force_pub) {
-    const int G = he::pick_group(KP, 0, count);
-    const uint64_t per_wave = 64 / G;
-    const uint32_t grid = persistent_grid(KP, 0, (2 * ((count + per_wave - 1) / per_wave) + 3) / 4, G);
-    int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 0, G), stream);
+    // kind 4: the mod-P exponentiation (A1); kind 0: the lift mod P^2 (A2)
+    const int G1 = he::pick_group(KP, 4, count), G2 = he::pick_group(KP, 0, count);
+    const uint32_t grid1 = persistent_grid(KP, 4, (2 * ((count + 64 / G1 - 1) / (64 / G1)) + 3) / 4, G1);
+    const uint32_t grid2 = persistent_grid(KP, 0, (2 * ((count + 64 / G2 - 1) / (64 / G2)) + 3) / 4, G2);
+    int rc = ensure(w->tab, std::max(grid1 * he::table_bytes_per_block(KP, 4, G1),
+                                     grid2 * he::table_bytes_per_block(KP, 0, G2)), stream);
     if (rc) return rc;
-    rc = ensure(w->tmp, count * 2 * L * sizeof(uint32_t), stream);
+    // c_P per (ciphertext, prime) (2L limbs per ciphertext), then t per (ciphertext, prime) (L limbs)
+    rc = ensure(w->tmp, count * 3 * L * sizeof(uint32_t), stream);
     if (rc) return rc;
-    HE_TRY_HIP(he::launch_enc_crt(KP, key->dk, m, count, r, r_seed, r_offset, (uint32_t *)w->tmp.p, ct,
-                                  (uint32_t *)w->tab.p, grid, G, stream));
+    uint32_t *cpq = (uint32_t *)w->tmp.p, *tq = cpq + count * 2 * L;
+    HE_TRY_HIP(he::launch_enc_crt(KP, key->dk, m, count, r, r_seed, r_offset, tq, cpq, ct, (uint32_t *)w->tab.p,
+                                  grid1, G1, grid2, G2, stream));
   } else {
     const uint32_t grid = persistent_grid(KP, 1, ((count + 3) / 4 + 3) / 4);
     int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 1), stream);

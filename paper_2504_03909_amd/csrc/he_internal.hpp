@@ -92,9 +92,9 @@ constexpr int kHistGroup = 16;      // lanes per integer in the histogram kernel
 // KP = limbs per lane of a prime: 1 for 1024-bit keys, 2 for 2048-bit keys.
 hipError_t launch_encode(const double *x, uint64_t count, uint32_t frac_bits, int64_t *m,
                          uint32_t *n_bad, hipStream_t s);
-hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count,
-                          const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *cpq,
-                          uint32_t *ct, uint32_t *tab, uint32_t grid, int G, hipStream_t s);
+hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
+                          uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab, uint32_t grid1,
+                          int G1, uint32_t grid2, int G2, hipStream_t s);
 hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
                           const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *ct,
                           uint32_t *tab, uint32_t grid, hipStream_t s);

@@ -87,24 +87,29 @@ __global__ void k_encode(const double *__restrict__ x, uint64_t count, uint32_t 
 }
 
 // ----------------------------------------------------------- CRT encryption
-// Phase A: for each (ciphertext i, prime P) compute
-//   c_P = (1 + m n) r^n mod P^2,  r^n mod P^2 = (r^(Q mod (P-1)) mod P)^P mod P^2.
-// Work unit = (prime, 64/G consecutive ciphertexts) so that the exponent is
-// the same for the whole wave.  Output cpq[i][P] (S_P2 limbs, canonical).
-// G = lanes per integer (kEncGroup).
+// Phase A, for each (ciphertext i, prime P):
+//   c_P = (1 + m n) r^n mod P^2,  r^n mod P^2 = (r^(Q mod (P-1)) mod P)^P mod P^2,
+// in two kernels so that each runs at its own group width: A1 computes
+// t = r^(Q mod (P-1)) mod P (mod-P arithmetic, 2-lane groups for large
+// counts), A2 lifts omega = t^P mod P^2 and forms c_P (4-lane groups).  Work
+// unit = (prime, 64/G consecutive ciphertexts) so that the exponent is the
+// same for the whole wave.
+
+// A1: t[i][P] (S_P limbs, canonical).
 template <int KP, int G>
-__global__ __launch_bounds__(kBlockThreads, 4) void k_enc_crt_a(
-    DKey key, const int64_t *__restrict__ m, uint64_t count, const uint32_t *__restrict__ r,
-    uint64_t seed, uint64_t roff, uint32_t *__restrict__ cpq, uint32_t *__restrict__ tabs) {
-  constexpr int SP = 16 * KP, SP2 = 32 * KP, L = SP2;
-  constexpr int K1 = SP / G, K2 = SP2 / G;  // limbs per lane mod P and mod P^2
+__global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p1(DKey key, uint64_t count,
+                                                           const uint32_t *__restrict__ r, uint64_t seed,
+                                                           uint64_t roff, uint32_t *__restrict__ tq,
+                                                           uint32_t *__restrict__ tabs) {
+  constexpr int SP = 16 * KP, L = 32 * KP;
+  constexpr int K1 = SP / G;  // limbs per lane mod P
   constexpr int NG = 64 / G, GB = kBlockThreads / G;
-  __shared__ __align__(16) uint32_t lds_all[GB * SP2];
+  __shared__ __align__(16) uint32_t lds_all[GB * SP];
   const uint32_t g = (threadIdx.x & 63u) / G;
-  uint32_t *lds = lds_all + (threadIdx.x / G) * SP2;
+  uint32_t *lds = lds_all + (threadIdx.x / G) * SP;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * SP2);
+  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * SP);
   const uint64_t nunits = 2 * ((count + NG - 1) / NG);
   const uint64_t W = (uint64_t)SP + 1;  // stream words per r
 
@@ -114,45 +119,61 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_crt_a(
     uint64_t i = (qd >> 1) * NG + g;
     const bool valid = i < count;
     if (!valid) i = count - 1;
-    uint32_t w[K2];
-    {
-      const Mod<K1> Mp = load_mod<K1, G>(P.P.N, P.P.ninv);
-      // x = Montgomery form of r mod P
-      uint32_t x[K1], t0[K1], t1[K1], c[K1];
-      if (r) {
-        ld<K1, G>(t0, r + i * L);
-        ld<K1, G>(t1, r + i * L + SP);
-        ld<K1, G>(c, P.P.R2);
-        mont_mul<K1, G>(t0, t0, c, Mp, lds);
-        ld<K1, G>(c, P.P.R3);
-        mont_mul<K1, G>(t1, t1, c, Mp, lds);
-        add_mod<K1, G>(x, t0, t1, Mp);
-      } else {
-        const uint64_t base = (roff + i) * W;
-        uint32_t t2[K1];
-        seeded_limbs<K1, G>(t0, seed, base, 0, 2 * SP + 2);
-        seeded_limbs<K1, G>(t1, seed, base, SP, 2 * SP + 2);
-        seeded_limbs<K1, G>(t2, seed, base, 2 * SP, 2 * SP + 2);
-        ld<K1, G>(c, P.P.R2);
-        mont_mul<K1, G>(t0, t0, c, Mp, lds);
-        ld<K1, G>(c, P.P.R3);
-        mont_mul<K1, G>(t1, t1, c, Mp, lds);
-        ld<K1, G>(c, P.P.R4);
-        mont_mul<K1, G>(t2, t2, c, Mp, lds);
-        add_mod<K1, G>(x, t0, t1, Mp);
-        add_mod<K1, G>(x, x, t2, Mp);
-      }
-      // t = r^(Q mod (P-1)) mod P, canonical
-      ld<K1, G>(c, P.P.R1);
-      mont_pow<K1, G>(x, P.e_enc.e, P.e_enc.nwin, tab, c, Mp, lds);
-      set_small<K1, G>(c, 1u);
-      mont_mul<K1, G>(x, x, c, Mp, lds);
-      relayout<K1, K2, G>(w, x, lds);
+    const Mod<K1> Mp = load_mod<K1, G>(P.P.N, P.P.ninv);
+    // x = Montgomery form of r mod P: r's S_P-limb words w_k (two for an
+    // explicit r, three for the seeded one) times R^(k+2) mod P, summed; one
+    // word in registers at a time
+    uint32_t x[K1], t[K1], c[K1];
+    const uint64_t base = (roff + i) * W;
+    const int words = r ? 2 : 3;
+    set_zero(x);
+#pragma unroll 1
+    for (int k = 0; k < words; ++k) {
+      if (r)
+        ld<K1, G>(t, r + i * L + k * SP);
+      else
+        seeded_limbs<K1, G>(t, seed, base, k * SP, 2 * SP + 2);
+      ld<K1, G>(c, k == 0 ? P.P.R2 : (k == 1 ? P.P.R3 : P.P.R4));
+      mont_mul<K1, G>(t, t, c, Mp, lds);
+      add_mod<K1, G>(x, x, t, Mp);
     }
+    // t = r^(Q mod (P-1)) mod P, canonical
+    ld<K1, G>(c, P.P.R1);
+    mont_pow<K1, G>(x, P.e_enc.e, P.e_enc.nwin, tab, c, Mp, lds);
+    set_small<K1, G>(c, 1u);
+    mont_mul<K1, G>(x, x, c, Mp, lds);
+    if (valid) st<K1, G>(tq + (i * 2 + which) * SP, x);
+  }
+}
+
+// A2: cpq[i][P] (S_P2 limbs, canonical) from t.
+template <int KP, int G>
+__global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p2(DKey key, const int64_t *__restrict__ m,
+                                                           uint64_t count, const uint32_t *__restrict__ tq,
+                                                           uint32_t *__restrict__ cpq, uint32_t *__restrict__ tabs) {
+  constexpr int SP = 16 * KP, SP2 = 32 * KP;
+  constexpr int K1 = SP / G, K2 = SP2 / G;  // limbs per lane mod P and mod P^2
+  constexpr int NG = 64 / G, GB = kBlockThreads / G;
+  __shared__ __align__(16) uint32_t lds_all[GB * SP2];
+  const uint32_t g = (threadIdx.x & 63u) / G;
+  uint32_t *lds = lds_all + (threadIdx.x / G) * SP2;
+  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
+  const uint64_t nw = (uint64_t)gridDim.x * 4;
+  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * SP2);
+  const uint64_t nunits = 2 * ((count + NG - 1) / NG);
+
+  for (uint64_t qd = gw; qd < nunits; qd += nw) {
+    const int which = (int)(qd & 1);
+    const DPrime &P = key.pr[which];
+    uint64_t i = (qd >> 1) * NG + g;
+    const bool valid = i < count;
+    if (!valid) i = count - 1;
     const Mod<K2> M2 = load_mod<K2, G>(P.P2.N, P.P2.ninv);
+    uint32_t w[K2];
     {
       // omega = t^P mod P^2 (Montgomery form)
       uint32_t c2[K2];
+      ld_part<K2, G>(w, tq + (i * 2 + which) * SP, SP);
       ld<K2, G>(c2, P.P2.R2);
       mont_mul<K2, G>(w, w, c2, M2, lds);
       ld<K2, G>(c2, P.P2.R1);
@@ -1079,29 +1100,41 @@ hipError_t launch_encode(const double *x, uint64_t count, uint32_t frac_bits, in
   return hipGetLastError();
 }
 
+template <int KP, int G>
+static void launch_p1(const DKey &k, uint64_t count, const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *tq,
+                      uint32_t *tab, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_enc_p1<KP, G>), dim3(grid), dim3(kBlockThreads), 0, s, k, count, r, seed, roff, tq, tab);
+}
+template <int KP, int G>
+static void launch_p2(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *tq, uint32_t *cpq,
+                      uint32_t *tab, uint32_t grid, hipStream_t s) {
+  hipLaunchKernelGGL((k_enc_p2<KP, G>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, tq, cpq, tab);
+}
 template <int KP>
-static hipError_t enc_crt(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r,
-                          uint64_t seed, uint64_t roff, uint32_t *cpq, uint32_t *ct, uint32_t *tab,
-                          uint32_t grid, int G, hipStream_t s) {
-  if (G == 4)
-    hipLaunchKernelGGL((k_enc_crt_a<KP, 4>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff,
-                       cpq, tab);
-  else if (G == 8)
-    hipLaunchKernelGGL((k_enc_crt_a<KP, 8>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff,
-                       cpq, tab);
-  else
-    hipLaunchKernelGGL((k_enc_crt_a<KP, 16>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff,
-                       cpq, tab);
+static hipError_t enc_crt(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
+                          uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab, uint32_t grid1,
+                          int G1, uint32_t grid2, int G2, hipStream_t s) {
+  switch (G1) {
+    case 2: launch_p1<KP, 2>(k, count, r, seed, roff, tq, tab, grid1, s); break;
+    case 4: launch_p1<KP, 4>(k, count, r, seed, roff, tq, tab, grid1, s); break;
+    case 8: launch_p1<KP, 8>(k, count, r, seed, roff, tq, tab, grid1, s); break;
+    default: launch_p1<KP, 16>(k, count, r, seed, roff, tq, tab, grid1, s); break;
+  }
+  switch (G2) {
+    case 4: launch_p2<KP, 4>(k, m, count, tq, cpq, tab, grid2, s); break;
+    case 8: launch_p2<KP, 8>(k, m, count, tq, cpq, tab, grid2, s); break;
+    default: launch_p2<KP, 16>(k, m, count, tq, cpq, tab, grid2, s); break;
+  }
   hipLaunchKernelGGL(k_enc_crt_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k,
                      (const uint32_t *)cpq, count, ct);
   return hipGetLastError();
 }
-hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count,
-                          const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *cpq,
-                          uint32_t *ct, uint32_t *tab, uint32_t grid, int G, hipStream_t s) {
+hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
+                          uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab, uint32_t grid1,
+                          int G1, uint32_t grid2, int G2, hipStream_t s) {
   if (!count) return hipSuccess;
-  return KP == 1 ? enc_crt<1>(k, m, count, r, seed, roff, cpq, ct, tab, grid, G, s)
-                 : enc_crt<2>(k, m, count, r, seed, roff, cpq, ct, tab, grid, G, s);
+  return KP == 1 ? enc_crt<1>(k, m, count, r, seed, roff, tq, cpq, ct, tab, grid1, G1, grid2, G2, s)
+                 : enc_crt<2>(k, m, count, r, seed, roff, tq, cpq, ct, tab, grid1, G1, grid2, G2, s);
 }
 
 hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
@@ -1286,36 +1319,36 @@ uint32_t ct_div_batch(uint64_t count) {
   return (uint32_t)std::max<uint64_t>(1, (count + groups - 1) / groups);
 }
 
-static int gidx(int G) { return G == 4 ? 0 : (G == 8 ? 1 : 2); }
+static int gidx(int G) { return G == 2 ? 0 : (G == 4 ? 1 : (G == 8 ? 2 : 3)); }
 
-uint32_t resident_blocks(int KP, int kind, int G) {
-  static uint32_t cache[2][4][3] = {};
-  uint32_t &c = cache[KP - 1][kind][gidx(G)];
-  if (c) return c;
-  const void *fn = nullptr;
-  const bool one = KP == 1;
+template <int KP>
+static const void *kernel_of(int kind, int G) {
   switch (kind) {
     case 0:
-      if (G == 4) fn = one ? (const void *)k_enc_crt_a<1, 4> : (const void *)k_enc_crt_a<2, 4>;
-      else if (G == 8) fn = one ? (const void *)k_enc_crt_a<1, 8> : (const void *)k_enc_crt_a<2, 8>;
-      else fn = one ? (const void *)k_enc_crt_a<1, 16> : (const void *)k_enc_crt_a<2, 16>;
-      break;
-    case 1: fn = one ? (const void *)k_enc_pub<1> : (const void *)k_enc_pub<2>; break;
+      return G == 4 ? (const void *)k_enc_p2<KP, 4> : G == 8 ? (const void *)k_enc_p2<KP, 8>
+                                                             : (const void *)k_enc_p2<KP, 16>;
+    case 1: return (const void *)k_enc_pub<KP>;
     case 2:
-      if (G == 4) fn = one ? (const void *)k_dec_a<1, 4> : (const void *)k_dec_a<2, 4>;
-      else if (G == 8) fn = one ? (const void *)k_dec_a<1, 8> : (const void *)k_dec_a<2, 8>;
-      else fn = one ? (const void *)k_dec_a<1, 16> : (const void *)k_dec_a<2, 16>;
-      break;
-    default:
-      fn = one ? (const void *)k_hist_chunk<1, kHistGroup> : (const void *)k_hist_chunk<2, kHistGroup>;
-      break;
+      return G == 4 ? (const void *)k_dec_a<KP, 4> : G == 8 ? (const void *)k_dec_a<KP, 8>
+                                                            : (const void *)k_dec_a<KP, 16>;
+    case 4:
+      return G == 2 ? (const void *)k_enc_p1<KP, 2> : G == 4 ? (const void *)k_enc_p1<KP, 4>
+                      : G == 8 ? (const void *)k_enc_p1<KP, 8> : (const void *)k_enc_p1<KP, 16>;
+    default: return (const void *)k_hist_chunk<KP, kHistGroup>;
   }
-  c = occupancy_blocks(fn);
+}
+
+uint32_t resident_blocks(int KP, int kind, int G) {
+  static uint32_t cache[2][5][4] = {};
+  uint32_t &c = cache[KP - 1][kind][gidx(G)];
+  if (c) return c;
+  c = occupancy_blocks(KP == 1 ? kernel_of<1>(kind, G) : kernel_of<2>(kind, G));
   return c;
 }
 
 uint64_t table_bytes_per_block(int KP, int kind, int G) {
-  const uint64_t S = kind == 1 ? 64 * KP : 32 * KP;  // public path tables are mod n^2
+  // limbs of the modulus the kernel's exponentiation tables work in
+  const uint64_t S = kind == 1 ? 64 * KP : (kind == 4 ? 16 * KP : 32 * KP);
   return (uint64_t)(kBlockThreads / G) * kTable * S * sizeof(uint32_t);
 }
 
@@ -1325,7 +1358,6 @@ uint64_t table_bytes_per_block(int KP, int kind, int G) {
 // SIMD at least two waves; below that, wider groups buy parallelism.
 int pick_group(int KP, int kind, uint64_t count) {
   (void)KP;
-  (void)kind;
   static int cus = 0;
   if (!cus) {
     int dev = 0;
@@ -1334,7 +1366,9 @@ int pick_group(int KP, int kind, uint64_t count) {
       cus = 1;
   }
   const uint64_t need = 2ull * 4 * (uint64_t)cus;  // two waves on each of the 4 SIMDs per CU
-  for (int G : {4, 8}) {
+  // the mod-P kernel of encryption (kind 4) also has 2-lane groups
+  for (int G : {2, 4, 8}) {
+    if (G == 2 && kind != 4) continue;
     const uint64_t waves = 2 * ((count + 64 / G - 1) / (64 / G));
     if (waves >= need) return G;
   }

@@ -2,7 +2,8 @@
 //
 // One big integer of S = G K little-endian 32-bit limbs lives in a "group" of
 // G consecutive lanes (G = 16: one DPP row; G = 8: half a row; G = 4: one
-// quad): lane l of the group holds limbs l*K .. l*K+K-1 in VGPRs.  A wave64
+// quad; G = 2: half a quad): lane l of the group holds limbs l*K .. l*K+K-1
+// in VGPRs.  A wave64
 // works on 64/G independent integers at once, and every cross-lane step of the
 // arithmetic is a DPP operation (shift by one lane, broadcast of the group's
 // first or last lane) or one wave-wide ballot.  Smaller groups give each lane
@@ -40,31 +41,36 @@ __device__ __forceinline__ uint32_t glane() { return __lane_id() & (G - 1u); }
 // ---- DPP group operations -------------------------------------------------
 // Every lane of the group reads the group's first / last lane.
 //   G = 16: row_newbcast:0 / :15;  G = 8: row_newbcast:0 on banks 0-1 and :8
-//   on banks 2-3 (resp. :7 / :15);  G = 4: quad_perm [0,0,0,0] / [3,3,3,3].
+//   on banks 2-3 (resp. :7 / :15);  G = 4: quad_perm [0,0,0,0] / [3,3,3,3];
+//   G = 2: quad_perm [0,0,2,2] / [1,1,3,3].
 // Full row and bank masks with every lane reading a valid source lane write
 // every lane, so these use mov_dpp (no "old" value to set up first).
 template <int G = 16>
 __device__ __forceinline__ uint32_t bcast_first(uint32_t v) {
-  static_assert(G == 4 || G == 8 || G == 16, "group width");
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16, "group width");
   if constexpr (G == 16) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x150, 0xF, 0xF, false);
   } else if constexpr (G == 8) {
     const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x150, 0xF, 0x3, false);
     return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x158, 0xF, 0xC, false);
-  } else {
+  } else if constexpr (G == 4) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x00, 0xF, 0xF, false);
+  } else {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xA0, 0xF, 0xF, false);  // quad_perm [0,0,2,2]
   }
 }
 template <int G = 16>
 __device__ __forceinline__ uint32_t bcast_last(uint32_t v) {
-  static_assert(G == 4 || G == 8 || G == 16, "group width");
+  static_assert(G == 2 || G == 4 || G == 8 || G == 16, "group width");
   if constexpr (G == 16) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x15F, 0xF, 0xF, false);
   } else if constexpr (G == 8) {
     const int t = __builtin_amdgcn_update_dpp(0, (int)v, 0x157, 0xF, 0x3, false);
     return (uint32_t)__builtin_amdgcn_update_dpp(t, (int)v, 0x15F, 0xF, 0xC, false);
-  } else {
+  } else if constexpr (G == 4) {
     return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xFF, 0xF, 0xF, false);
+  } else {
+    return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xF5, 0xF, 0xF, false);  // quad_perm [1,1,3,3]
   }
 }
 // Lane l reads lane l+1 of its group; the group's last lane reads 0
@@ -78,13 +84,15 @@ __device__ __forceinline__ uint32_t from_next(uint32_t v) {
   else return glane<G>() == G - 1 ? 0u : t;
 }
 // Lane l reads lane l+1 of its group, the group's last lane reads the group's
-// first lane (G = 4: quad_perm [1,2,3,0]; G = 16: row_ror:15).  Used for the
-// one-limb shift of a Montgomery step, where the first lane's value is the
-// cleared lowest column and therefore 0, so this equals from_next without the
-// edge fix-up; G = 8 has no 8-lane rotation and uses from_next.
+// first lane (G = 2: quad_perm [1,0,3,2]; G = 4: quad_perm [1,2,3,0]; G = 16:
+// row_ror:15).  Used for the one-limb shift of a Montgomery step, where the
+// first lane's value is the cleared lowest column and therefore 0, so this
+// equals from_next without the edge fix-up; G = 8 has no 8-lane rotation and
+// uses from_next.
 template <int G = 16>
 __device__ __forceinline__ uint32_t rotate_next(uint32_t v) {
-  if constexpr (G == 4) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x39, 0xF, 0xF, false);
+  if constexpr (G == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
+  else if constexpr (G == 4) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x39, 0xF, 0xF, false);
   else if constexpr (G == 16) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12F, 0xF, 0xF, false);
   else return from_next<G>(v);
 }
@@ -98,7 +106,8 @@ __device__ __forceinline__ uint32_t from_prev(uint32_t v) {
 
 template <int G>
 constexpr uint64_t group_top_mask() {
-  return G == 16 ? 0x8000800080008000ull : (G == 8 ? 0x8080808080808080ull : 0x8888888888888888ull);
+  return G == 16 ? 0x8000800080008000ull
+                 : (G == 8 ? 0x8080808080808080ull : (G == 4 ? 0x8888888888888888ull : 0xAAAAAAAAAAAAAAAAull));
 }
 
 // Carry lookahead across the lanes of every group at once.  gen: the lane

@@ -45,7 +45,13 @@ int fail(int code, const std::string &msg) {
   } while (0)
 
 he::DMod mk_mod(const uint32_t *base, const hekey::ModOff &o) {
-  return he::DMod{base + o.N, base + o.R1, base + o.R2, base + o.R3, base + o.R4, o.ninv};
+  he::DMod m{base + o.N, base + o.R1, base + o.R2, base + o.R3, base + o.R4, o.ninv, {}, {}, {}};
+  for (int v = 0; v < he29::kVariants; ++v) {
+    m.N29[v] = base + o.N29[v];
+    m.R1_29[v] = base + o.R1_29[v];
+    m.R2_29[v] = base + o.R2_29[v];
+  }
+  return m;
 }
 he::DExp mk_exp(const uint32_t *base, const hekey::ExpOff &o) { return he::DExp{base + o.e, o.nwin}; }
 

@@ -4,13 +4,19 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "radix29.hpp"
+
 namespace he {
 
 // One Montgomery modulus N of S limbs (R = 2^(32 S)); device pointers into
-// the key's constant blob, each S limbs.
+// the key's constant blob, each S limbs.  The radix-2^29 form (R' =
+// 2^(29 S29), one set per limb-count variant) serves the exponentiations.
 struct DMod {
   const uint32_t *N, *R1, *R2, *R3, *R4;  // N, R^k mod N
   uint32_t ninv;                          // -N^-1 mod 2^32
+  const uint32_t *N29[he29::kVariants];   // N in S29 limbs of 29 bits
+  const uint32_t *R1_29[he29::kVariants]; // R' mod N
+  const uint32_t *R2_29[he29::kVariants]; // R'^2 mod N
 };
 
 // Exponent as limbs with one zero limb of padding, and its window count.

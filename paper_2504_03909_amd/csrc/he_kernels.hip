@@ -11,6 +11,7 @@
 
 #include "he_internal.hpp"
 #include "mont.hpp"
+#include "mont29.hpp"
 
 namespace he {
 
@@ -103,13 +104,14 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p1(DKey key, uint64_t 
                                                            uint32_t *__restrict__ tabs) {
   constexpr int SP = 16 * KP, L = 32 * KP;
   constexpr int K1 = SP / G;  // limbs per lane mod P
+  constexpr int S29 = he29::limbs_for_group(SP, G), ROW = S29 > SP ? S29 : SP;
   constexpr int NG = 64 / G, GB = kBlockThreads / G;
-  __shared__ __align__(16) uint32_t lds_all[GB * SP];
+  __shared__ __align__(16) uint32_t lds_all[GB * ROW];
   const uint32_t g = (threadIdx.x & 63u) / G;
-  uint32_t *lds = lds_all + (threadIdx.x / G) * SP;
+  uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * SP);
+  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * S29);
   const uint64_t nunits = 2 * ((count + NG - 1) / NG);
   const uint64_t W = (uint64_t)SP + 1;  // stream words per r
 
@@ -120,9 +122,9 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p1(DKey key, uint64_t 
     const bool valid = i < count;
     if (!valid) i = count - 1;
     const Mod<K1> Mp = load_mod<K1, G>(P.P.N, P.P.ninv);
-    // x = Montgomery form of r mod P: r's S_P-limb words w_k (two for an
-    // explicit r, three for the seeded one) times R^(k+2) mod P, summed; one
-    // word in registers at a time
+    // x = r mod P: r's S_P-limb words w_k (two for an explicit r, three for
+    // the seeded one), each times R^k mod P by a Montgomery product with
+    // R^(k+1) mod P, summed; one word in registers at a time
     uint32_t x[K1], t[K1], c[K1];
     const uint64_t base = (roff + i) * W;
     const int words = r ? 2 : 3;
@@ -133,15 +135,12 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p1(DKey key, uint64_t 
         ld<K1, G>(t, r + i * L + k * SP);
       else
         seeded_limbs<K1, G>(t, seed, base, k * SP, 2 * SP + 2);
-      ld<K1, G>(c, k == 0 ? P.P.R2 : (k == 1 ? P.P.R3 : P.P.R4));
+      ld<K1, G>(c, k == 0 ? P.P.R1 : (k == 1 ? P.P.R2 : P.P.R3));
       mont_mul<K1, G>(t, t, c, Mp, lds);
       add_mod<K1, G>(x, x, t, Mp);
     }
     // t = r^(Q mod (P-1)) mod P, canonical
-    ld<K1, G>(c, P.P.R1);
-    mont_pow<K1, G>(x, P.e_enc.e, P.e_enc.nwin, tab, c, Mp, lds);
-    set_small<K1, G>(c, 1u);
-    mont_mul<K1, G>(x, x, c, Mp, lds);
+    pow29<K1, G>(x, P.e_enc.e, P.e_enc.nwin, tab, P.P, lds);
     if (valid) st<K1, G>(tq + (i * 2 + which) * SP, x);
   }
 }
@@ -153,13 +152,14 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p2(DKey key, const int
                                                            uint32_t *__restrict__ cpq, uint32_t *__restrict__ tabs) {
   constexpr int SP = 16 * KP, SP2 = 32 * KP;
   constexpr int K1 = SP / G, K2 = SP2 / G;  // limbs per lane mod P and mod P^2
+  constexpr int S29 = he29::limbs_for_group(SP2, G), ROW = S29 > SP2 ? S29 : SP2;
   constexpr int NG = 64 / G, GB = kBlockThreads / G;
-  __shared__ __align__(16) uint32_t lds_all[GB * SP2];
+  __shared__ __align__(16) uint32_t lds_all[GB * ROW];
   const uint32_t g = (threadIdx.x & 63u) / G;
-  uint32_t *lds = lds_all + (threadIdx.x / G) * SP2;
+  uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * SP2);
+  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * S29);
   const uint64_t nunits = 2 * ((count + NG - 1) / NG);
 
   for (uint64_t qd = gw; qd < nunits; qd += nw) {
@@ -168,17 +168,11 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p2(DKey key, const int
     uint64_t i = (qd >> 1) * NG + g;
     const bool valid = i < count;
     if (!valid) i = count - 1;
-    const Mod<K2> M2 = load_mod<K2, G>(P.P2.N, P.P2.ninv);
+    // omega = t^P mod P^2, canonical
     uint32_t w[K2];
-    {
-      // omega = t^P mod P^2 (Montgomery form)
-      uint32_t c2[K2];
-      ld_part<K2, G>(w, tq + (i * 2 + which) * SP, SP);
-      ld<K2, G>(c2, P.P2.R2);
-      mont_mul<K2, G>(w, w, c2, M2, lds);
-      ld<K2, G>(c2, P.P2.R1);
-      mont_pow<K2, G>(w, P.e_lift.e, P.e_lift.nwin, tab, c2, M2, lds);
-    }
+    ld_part<K2, G>(w, tq + (i * 2 + which) * SP, SP);
+    pow29<K2, G>(w, P.e_lift.e, P.e_lift.nwin, tab, P.P2, lds);
+    const Mod<K2> M2 = load_mod<K2, G>(P.P2.N, P.P2.ninv);
     uint32_t f[K2];
     {
       // u = (m mod P) Q mod P, then f = 1 + m n mod P^2 = 1 + P u
@@ -194,8 +188,10 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p2(DKey key, const int
       ld<K2, G>(c2, P.PR_P2);
       mont_mul<K2, G>(f, f, c2, M2, lds);
       add_one<K2, G>(f);
+      ld<K2, G>(c2, P.P2.R2);
+      mont_mul<K2, G>(f, f, c2, M2, lds);  // Montgomery form of f
     }
-    // c_P = omega f mod P^2 (the Montgomery factor of omega cancels)
+    // c_P = omega f mod P^2 (the Montgomery factor of f cancels)
     mont_mul<K2, G>(w, w, f, M2, lds);
     if (valid) st<K2, G>(cpq + (i * 2 + which) * SP2, w);
   }
@@ -626,12 +622,13 @@ __global__ __launch_bounds__(kBlockThreads, 3) void k_dec_a(DKey key, const uint
                                                         uint32_t *__restrict__ tabs) {
   constexpr int SP = 16 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
   constexpr int K1 = SP / G, K2 = SP2 / G, NG = 64 / G, GB = kBlockThreads / G;
-  __shared__ __align__(16) uint32_t lds_all[GB * SP2];
+  constexpr int S29 = he29::limbs_for_group(SP2, G), ROW = S29 > SP2 ? S29 : SP2;
+  __shared__ __align__(16) uint32_t lds_all[GB * ROW];
   const uint32_t g = (threadIdx.x & 63u) / G;
-  uint32_t *lds = lds_all + (threadIdx.x / G) * SP2;
+  uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * SP2);
+  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * S29);
   const uint64_t nunits = 2 * ((count + NG - 1) / NG);
   for (uint64_t qd = gw; qd < nunits; qd += nw) {
     const int which = (int)(qd & 1);
@@ -643,18 +640,16 @@ __global__ __launch_bounds__(kBlockThreads, 3) void k_dec_a(DKey key, const uint
     {
       const Mod<K2> M2 = load_mod<K2, G>(P.P2.N, P.P2.ninv);
       uint32_t x[K2], y[K2], c[K2];
-      // c mod P^2 in Montgomery form: c = c0 + c1 R'
+      // c mod P^2 = c0 + c1 R' mod P^2 (halves c0, c1; R' = 2^(32 S_P2)),
+      // each half by a Montgomery product with R' resp. R'^2
       ld<K2, G>(x, ct + i * SN2);
       ld<K2, G>(y, ct + i * SN2 + SP2);
-      ld<K2, G>(c, P.P2.R2);
+      ld<K2, G>(c, P.P2.R1);
       mont_mul<K2, G>(x, x, c, M2, lds);
-      ld<K2, G>(c, P.P2.R3);
+      ld<K2, G>(c, P.P2.R2);
       mont_mul<K2, G>(y, y, c, M2, lds);
       add_mod<K2, G>(x, x, y, M2);
-      ld<K2, G>(c, P.P2.R1);
-      mont_pow<K2, G>(x, P.e_dec.e, P.e_dec.nwin, tab, c, M2, lds);
-      set_small<K2, G>(c, 1u);
-      mont_mul<K2, G>(x, x, c, M2, lds);  // canonical, = 1 mod P
+      pow29<K2, G>(x, P.e_dec.e, P.e_dec.nwin, tab, P.P2, lds);  // canonical, = 1 mod P
       set_small<K2, G>(c, 1u);
       sub_plain<K2, G>(x, x, c);          // x - 1 = k P
       relayout<K2, K1, G>(lo, x, lds);
@@ -1347,8 +1342,10 @@ uint32_t resident_blocks(int KP, int kind, int G) {
 }
 
 uint64_t table_bytes_per_block(int KP, int kind, int G) {
-  // limbs of the modulus the kernel's exponentiation tables work in
-  const uint64_t S = kind == 1 ? 64 * KP : (kind == 4 ? 16 * KP : 32 * KP);
+  // limbs of the modulus the kernel's exponentiation tables work in (the
+  // CRT kernels' tables hold radix-2^29 limbs)
+  const uint64_t S = kind == 1 ? 64 * KP
+                               : (uint64_t)he29::limbs_for_group(kind == 4 ? 16 * KP : 32 * KP, G);
   return (uint64_t)(kBlockThreads / G) * kTable * S * sizeof(uint32_t);
 }
 

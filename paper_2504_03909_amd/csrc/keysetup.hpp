@@ -6,6 +6,7 @@
 #include <vector>
 
 #include "hostbn.hpp"
+#include "radix29.hpp"
 
 namespace hekey {
 
@@ -23,11 +24,27 @@ struct Blob {
     words.resize((words.size() + 3) & ~size_t(3), 0u);
     return off;
   }
+  // Appends x as exactly `limbs` limbs of 29 bits (one per 32-bit word),
+  // 16-byte aligned; throws if it does not fit.
+  size_t put29(const Limbs &x, size_t limbs) {
+    if (hebn::bit_length(x) > he29::kBits * limbs) throw std::runtime_error("value exceeds 29-bit limbs");
+    const size_t off = words.size();
+    words.resize(off + limbs, 0u);
+    for (size_t i = 0; i < limbs; ++i) {
+      uint32_t v = 0;
+      for (int k = 0; k < he29::kBits; ++k) v |= (uint32_t)hebn::bit(x, he29::kBits * i + k) << k;
+      words[off + i] = v;
+    }
+    words.resize((words.size() + 3) & ~size_t(3), 0u);
+    return off;
+  }
 };
 
 struct ModOff {  // Montgomery modulus N of S limbs, R = 2^(32 S)
   size_t N, R1, R2, R3, R4;
   uint32_t ninv;
+  // radix-2^29 form per variant: N, R mod N and R^2 mod N with R = 2^(29 S29)
+  size_t N29[he29::kVariants], R1_29[he29::kVariants], R2_29[he29::kVariants];
 };
 struct ExpOff {
   size_t e;
@@ -61,6 +78,13 @@ inline ModOff put_mod(Blob &b, const Limbs &N, size_t S) {
   m.R3 = b.put(R3, S);
   m.R4 = b.put(R4, S);
   m.ninv = hebn::neg_inv32(N[0]);
+  for (int v = 0; v < he29::kVariants; ++v) {
+    const size_t S29 = (size_t)he29::limbs((int)S, v);
+    const Limbs Q1 = hebn::mod(pow2(he29::kBits * S29), N);
+    m.N29[v] = b.put29(N, S29);
+    m.R1_29[v] = b.put29(Q1, S29);
+    m.R2_29[v] = b.put29(hebn::mulmod(Q1, Q1, N), S29);
+  }
   return m;
 }
 

@@ -1,0 +1,300 @@
+// Radix-2^29 Montgomery exponentiation for gfx950 (group layout as in
+// mont.hpp: G lanes per integer, lane l holding limbs l*K .. l*K+K-1).
+//
+// With 29-bit limbs every partial product is below 2^58, and a 64-bit column
+// accumulator can absorb every product a column receives while it lives in
+// one lane: a column enters the lane's top below 2^29, takes two products
+// (a_i b_j and q_i n_j, each below 2^58 (1 + 2^-20) for limbs up to
+// 2^29 + 2^8) in each of the K steps it takes to reach the lane's bottom,
+// plus one fold carry below 2^36, and is then folded, so it stays below
+// 2^64 for K <= 31.  A product is one
+// v_mad_u64_u32 and nothing else; the 32-bit-limb code in mont.hpp needs a
+// second instruction per product for the carry out of the 64-bit column.
+// The price is 29/32 of the bits per limb (about 1.1x the limbs and steps).
+//
+// The fold of a step: q_i = c_0 (-N^-1) mod 2^29 clears the low 29 bits of
+// the group's lowest column; every lane then passes the low 29 bits of its
+// lowest column down to the previous lane's new top column (lane 0 passes
+// zero) and adds the rest (c_0 >> 29) to its next column, which has that
+// weight after the shift.
+//
+// Between products an integer is "settled": limbs below 2^29 except each
+// lane's second limb, below 2^29 + 2^8 (one carry pass inside the lane, the
+// lane's carry added to the next lane's lowest limb).  With R = 2^(29 S29) >
+// 4N, operands below 2N give a product below 2N, so there is no conditional
+// subtraction until the exponentiation ends.
+//
+// Every function must be called by all 64 lanes of the wave.
+#pragma once
+#include "mont.hpp"
+#include "radix29.hpp"
+
+namespace he {
+
+constexpr uint32_t kMask29 = (1u << he29::kBits) - 1u;
+
+template <int K>
+struct Mod29 {
+  uint32_t n[K];  // this lane's 29-bit limbs of N
+  uint32_t ninv;  // -N^-1 mod 2^29
+};
+
+// Lane-local K words at lane offset glane * K (64-bit accesses for even K).
+template <int K, int G>
+__device__ __forceinline__ void ld29(uint32_t (&x)[K], const uint32_t *p) {
+  p += glane<G>() * K;
+  if constexpr (K % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < K; j += 4) {
+      const uint4 v = *reinterpret_cast<const uint4 *>(p + j);
+      x[j] = v.x; x[j + 1] = v.y; x[j + 2] = v.z; x[j + 3] = v.w;
+    }
+  } else if constexpr (K % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < K; j += 2) {
+      const uint2 v = *reinterpret_cast<const uint2 *>(p + j);
+      x[j] = v.x; x[j + 1] = v.y;
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < K; ++j) x[j] = p[j];
+  }
+}
+template <int K, int G>
+__device__ __forceinline__ void st29(uint32_t *p, const uint32_t (&x)[K]) {
+  p += glane<G>() * K;
+  if constexpr (K % 4 == 0) {
+#pragma unroll
+    for (int j = 0; j < K; j += 4)
+      *reinterpret_cast<uint4 *>(p + j) = make_uint4(x[j], x[j + 1], x[j + 2], x[j + 3]);
+  } else if constexpr (K % 2 == 0) {
+#pragma unroll
+    for (int j = 0; j < K; j += 2) *reinterpret_cast<uint2 *>(p + j) = make_uint2(x[j], x[j + 1]);
+  } else {
+#pragma unroll
+    for (int j = 0; j < K; ++j) p[j] = x[j];
+  }
+}
+
+template <int K, int G>
+__device__ __forceinline__ Mod29<K> load_mod29(const DMod &D) {
+  Mod29<K> m;
+  ld29<K, G>(m.n, D.N29[he29::variant(G)]);
+  m.ninv = D.ninv & kMask29;
+  return m;
+}
+
+
+// One step for multiplier limb ai (see the header comment).
+template <int K, int G>
+__device__ __forceinline__ void step29(uint64_t (&C)[K], uint32_t ai, const uint32_t (&b)[K],
+                                       const Mod29<K> &M) {
+  static_assert(K >= 2 && K <= 31, "column bound needs 2 <= K <= 31");
+#pragma unroll
+  for (int j = 0; j < K; ++j) C[j] += (uint64_t)ai * b[j];
+  const uint32_t q = bcast_first<G>(mul_lo32((uint32_t)C[0], M.ninv) & kMask29);
+#pragma unroll
+  for (int j = 0; j < K; ++j) C[j] += (uint64_t)q * M.n[j];
+  const uint32_t nb = rotate_next<G>((uint32_t)C[0] & kMask29);
+  C[1] += C[0] >> he29::kBits;
+#pragma unroll
+  for (int j = 0; j + 1 < K; ++j) C[j] = C[j + 1];
+  C[K - 1] = nb;
+  // The sums are opaque from one step to the next (an empty asm per column,
+  // no instruction), so the compiler keeps one accumulator per column instead
+  // of reassociating several steps' products into extra registers.
+#pragma unroll
+  for (int j = 0; j < K; ++j) asm("" : "+v"(C[j]));
+}
+
+// t = a b R'^-1 mod N (settled, below 2N) with a (settled, below 2N) in this
+// group's LDS row and b (settled, below 2N) in registers.  t may alias b.
+template <int K, int G>
+__device__ __forceinline__ void mm29_lds(uint32_t (&t)[K], const uint32_t *a_lds, const uint32_t (&b)[K],
+                                         const Mod29<K> &M) {
+  constexpr int S = G * K;
+  constexpr int U = K % 2 == 0 ? K : 2 * K;  // steps per loop iteration (even: 64-bit LDS reads)
+  static_assert(S % U == 0, "unroll must divide the limb count");
+  uint64_t C[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) C[j] = 0;
+#pragma unroll 1
+  for (int i0 = 0; i0 < S; i0 += U) {
+    uint32_t av[U];
+#pragma unroll
+    for (int h = 0; h < U; h += 2) {
+      const uint2 v = *reinterpret_cast<const uint2 *>(a_lds + i0 + h);
+      av[h] = v.x; av[h + 1] = v.y;
+    }
+#pragma unroll
+    for (int s = 0; s < U; ++s) step29<K, G>(C, av[s], b, M);
+  }
+  // settle: one carry pass in the lane, the lane's carry (below 2^36) into
+  // the next lane's lowest limb; the group's top carry is zero (result < 2N)
+  uint64_t c = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint64_t s = C[j] + c;
+    t[j] = (uint32_t)s & kMask29;
+    c = s >> he29::kBits;
+  }
+  const uint32_t cl = from_prev<G>((uint32_t)c), ch = from_prev<G>((uint32_t)(c >> 32));
+  const uint64_t s0 = (uint64_t)t[0] + (((uint64_t)ch << 32) | cl);
+  t[0] = (uint32_t)s0 & kMask29;
+  t[1] += (uint32_t)(s0 >> he29::kBits);
+}
+
+// t = a b R'^-1 mod N, both operands in registers; `lds` is this group's row
+// (at least S29 words).  t may alias a or b.
+template <int K, int G>
+__device__ __forceinline__ void mm29(uint32_t (&t)[K], const uint32_t (&a)[K], const uint32_t (&b)[K],
+                                     const Mod29<K> &M, uint32_t *lds) {
+  st29<K, G>(lds, a);
+  __builtin_amdgcn_wave_barrier();
+  mm29_lds<K, G>(t, lds, b, M);
+  __builtin_amdgcn_wave_barrier();
+}
+
+// t = a b R'^-1 mod N with a read from global memory (this lane's K words
+// at a + glane * K) into the LDS row and b in registers.  t may alias b.
+// Nothing of a stays in registers across the product.
+template <int K, int G>
+__device__ __forceinline__ void mm29_mem(uint32_t (&t)[K], const uint32_t *a, const uint32_t (&b)[K],
+                                         const Mod29<K> &M, uint32_t *lds) {
+  uint32_t v[K];
+  ld29<K, G>(v, a);
+  mm29<K, G>(t, v, b, M, lds);
+}
+
+// Settled t below 2N -> exact 29-bit limbs of t mod N.  One carry pass in
+// the lane (every carry is 0 or 1: only the second limb can exceed 2^29), a
+// ballot carry-lookahead across the group, then d = t - N the same way (in
+// the lane, then a borrow lookahead); t is replaced by d unless the
+// subtraction borrows out of the group's top limb.
+template <int K, int G>
+__device__ __forceinline__ void canon29(uint32_t (&t)[K], const Mod29<K> &M) {
+  uint32_t c = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint32_t s = t[j] + c;
+    t[j] = s & kMask29;
+    c = s >> he29::kBits;
+  }
+  bool prop = true;
+#pragma unroll
+  for (int j = 0; j < K; ++j) prop = prop && t[j] == kMask29;
+  uint32_t ci = carry_in<G>(c != 0u, prop) ? 1u : 0u;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint32_t s = t[j] + ci;
+    t[j] = s & kMask29;
+    ci = s >> he29::kBits;
+  }
+  uint32_t d[K];
+  uint32_t b = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint32_t s = t[j] - M.n[j] - b;
+    d[j] = s & kMask29;
+    b = s >> 31;
+  }
+  bool zprop = true;
+#pragma unroll
+  for (int j = 0; j < K; ++j) zprop = zprop && d[j] == 0u;
+  uint32_t bi = carry_in<G>(b != 0u, zprop) ? 1u : 0u;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint32_t s = d[j] - bi;
+    d[j] = s & kMask29;
+    bi = s >> 31;
+  }
+  const bool neg = bcast_last<G>((b | bi) != 0u ? 1u : 0u) != 0u;
+  select(t, neg, t, d);
+}
+
+// 32-bit limbs (K32 per lane, value below 2^(29 S29)) -> 29-bit limbs.
+template <int K32, int K, int G>
+__device__ __forceinline__ void to29(uint32_t (&t)[K], const uint32_t (&x)[K32], uint32_t *lds) {
+  constexpr int S32 = G * K32;
+  st<K32, G>(lds, x);
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint32_t bit = he29::kBits * (glane<G>() * K + j);
+    const uint32_t w = bit >> 5;
+    const uint32_t lo = w < S32 ? lds[w] : 0u;
+    const uint32_t hi = w + 1 < S32 ? lds[w + 1] : 0u;
+    t[j] = __builtin_amdgcn_alignbit(hi, lo, bit & 31u) & kMask29;
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// Exact 29-bit limbs -> 32-bit limbs (K32 per lane; bits beyond dropped).
+template <int K, int K32, int G>
+__device__ __forceinline__ void to32(uint32_t (&x)[K32], const uint32_t (&t)[K], uint32_t *lds) {
+  constexpr int S = G * K;
+  st29<K, G>(lds, t);
+  __builtin_amdgcn_wave_barrier();
+#pragma unroll
+  for (int j = 0; j < K32; ++j) {
+    const uint32_t bit = 32u * (glane<G>() * K32 + j);
+    const uint32_t k0 = bit / he29::kBits, o = bit % he29::kBits;
+    const uint64_t l0 = k0 < S ? lds[k0] : 0u;
+    const uint64_t l1 = k0 + 1 < S ? lds[k0 + 1] : 0u;
+    const uint64_t l2 = k0 + 2 < S ? lds[k0 + 2] : 0u;
+    const uint64_t v = l0 | (l1 << he29::kBits) | (l2 << (2 * he29::kBits));
+    x[j] = (uint32_t)(v >> o);
+  }
+  __builtin_amdgcn_wave_barrier();
+}
+
+// x <- x^e mod N for canonical x < N in 32-bit limbs (K32 per lane), result
+// canonical.  Left-to-right fixed 5-bit windows over `nwin` windows in the
+// radix-2^29 Montgomery domain; a multiplication by the table entry is done
+// for every window, zero digits included, so the sequence of operations does
+// not depend on the exponent.  `tab`: this group's table, kTable entries of
+// S29 words in global memory; `lds`: this group's row of at least
+// max(G K32, S29) words.
+template <int K32, int G>
+__device__ __forceinline__ void pow29(uint32_t (&x)[K32], const uint32_t *e, int nwin, uint32_t *tab,
+                                      const DMod &D, uint32_t *lds) {
+  constexpr int S29 = he29::limbs_for_group(G * K32, G);
+  constexpr int K = S29 / G;
+  constexpr int v = he29::variant(G);
+  const Mod29<K> M = load_mod29<K, G>(D);
+  uint32_t cur[K];
+  {
+    uint32_t c[K];
+    to29<K32, K, G>(cur, x, lds);
+    ld29<K, G>(c, D.R2_29[v]);
+    mm29<K, G>(cur, cur, c, M, lds);  // Montgomery form of x
+    ld29<K, G>(c, D.R1_29[v]);        // Montgomery form of 1
+    st29<K, G>(tab, c);
+    st29<K, G>(tab + S29, cur);
+  }
+  // table entries d = x^d; the multiplier x comes back from the table so
+  // that only the running power is held in registers
+#pragma unroll 1
+  for (int d = 2; d < kTable; ++d) {
+    mm29_mem<K, G>(cur, tab + S29, cur, M, lds);
+    st29<K, G>(tab + d * S29, cur);
+  }
+  __threadfence_block();
+  ld29<K, G>(cur, tab + exp_digit(e, nwin - 1) * S29);
+#pragma unroll 1
+  for (int w = nwin - 2; w >= 0; --w) {
+#pragma unroll 1
+    for (int s = 0; s < kWindow; ++s) mm29<K, G>(cur, cur, cur, M, lds);
+    mm29_mem<K, G>(cur, tab + exp_digit(e, w) * S29, cur, M, lds);
+  }
+  // leave the Montgomery domain: cur R'^-1 (a product with 1, at most N)
+  {
+    uint32_t one[K];
+    set_small<K, G>(one, 1u);
+    mm29<K, G>(cur, cur, one, M, lds);
+  }
+  canon29<K, G>(cur, M);
+  to32<K, K32, G>(x, cur, lds);
+}
+
+}  // namespace he

@@ -235,12 +235,13 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
     DKey key, const int64_t *__restrict__ m, uint64_t count, const uint32_t *__restrict__ r,
     uint64_t seed, uint64_t roff, uint32_t *__restrict__ ct, uint32_t *__restrict__ tabs) {
   constexpr int KN2 = 4 * KP, SN2 = 64 * KP, L = 32 * KP;
-  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  constexpr int S29 = he29::limbs_for_group(SN2, 16), ROW = S29 > SN2 ? S29 : SN2;
+  __shared__ __align__(16) uint32_t lds_all[16 * ROW];
   const uint32_t g = group_in_wave();
-  uint32_t *lds = lds_all + (wave_in_block() * 4 + g) * SN2;
+  uint32_t *lds = lds_all + (wave_in_block() * 4 + g) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * 4 + g) * (uint64_t)(kTable * SN2);
+  uint32_t *tab = tabs + (gw * 4 + g) * (uint64_t)(kTable * S29);
   const uint64_t nquads = (count + 3) / 4;
   const uint64_t W = (uint64_t)L / 2 + 1;
   const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
@@ -253,16 +254,21 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
       ld_part<KN2>(x, r + i * L, L);
     else
       seeded_limbs<KN2>(x, seed, (roff + i) * W, 0, L + 2);
+    // x mod n^2 (a Montgomery product with R^2 gives x R, one with 1 leaves
+    // the Montgomery domain), then x^n mod n^2
     ld<KN2>(c, key.n2.R2);
     mont_mul<KN2>(x, x, c, M, lds);
-    ld<KN2>(c, key.n2.R1);
-    mont_pow<KN2>(x, key.e_n.e, key.e_n.nwin, tab, c, M, lds);
-    // f = 1 + (m mod n) n, exact (< n^2)
+    set_small(c, 1u);
+    mont_mul<KN2>(x, x, c, M, lds);
+    pow29<KN2, 16>(x, key.e_n.e, key.e_n.nwin, tab, key.n2, lds);
+    // f = 1 + (m mod n) n, exact (< n^2), in Montgomery form
     ld_part<KN2>(c, key.n.N, L);
     signed_mod<KN2>(f, m ? m[i] : 0, c);
     ld<KN2>(c, key.nR_n2);
     mont_mul<KN2>(f, f, c, M, lds);
     add_one<KN2>(f);
+    ld<KN2>(c, key.n2.R2);
+    mont_mul<KN2>(f, f, c, M, lds);
     mont_mul<KN2>(x, x, f, M, lds);
     if (valid) st<KN2>(ct + i * SN2, x);
   }
@@ -617,7 +623,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_mont_convert(DKey key, const 
 //   x = c^(P-1) mod P^2,  m_P = ((x - 1) / P) h_P mod P.
 // Work unit = (prime, 64/G consecutive ciphertexts); G = lanes per integer.
 template <int KP, int G>
-__global__ __launch_bounds__(kBlockThreads, 3) void k_dec_a(DKey key, const uint32_t *__restrict__ ct,
+__global__ __launch_bounds__(kBlockThreads, 4) void k_dec_a(DKey key, const uint32_t *__restrict__ ct,
                                                         uint64_t count, uint32_t *__restrict__ mpq,
                                                         uint32_t *__restrict__ tabs) {
   constexpr int SP = 16 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
@@ -1344,8 +1350,8 @@ uint32_t resident_blocks(int KP, int kind, int G) {
 uint64_t table_bytes_per_block(int KP, int kind, int G) {
   // limbs of the modulus the kernel's exponentiation tables work in (the
   // CRT kernels' tables hold radix-2^29 limbs)
-  const uint64_t S = kind == 1 ? 64 * KP
-                               : (uint64_t)he29::limbs_for_group(kind == 4 ? 16 * KP : 32 * KP, G);
+  const uint64_t S = (uint64_t)he29::limbs_for_group(kind == 1 ? 64 * KP : (kind == 4 ? 16 * KP : 32 * KP),
+                                                    kind == 1 ? 16 : G);
   return (uint64_t)(kBlockThreads / G) * kTable * S * sizeof(uint32_t);
 }
 

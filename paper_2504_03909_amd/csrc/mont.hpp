@@ -748,38 +748,6 @@ __device__ __forceinline__ uint32_t exp_digit(const uint32_t *e, int w) {
   return (uint32_t)(v >> (bit & 31)) & (kTable - 1);
 }
 
-// x <- x^e mod N in Montgomery form (x is the Montgomery form of the base,
-// one = R mod N).  Left-to-right fixed 5-bit windows over `nwin` windows; a
-// multiplication by the table entry is done for every window, zero digits
-// included, so the sequence of operations does not depend on the exponent.
-// `tab` is this group's table: kTable entries of S limbs in global memory.
-template <int K, int G = 16>
-__device__ __forceinline__ void mont_pow(uint32_t (&x)[K], const uint32_t *e, int nwin,
-                                         uint32_t *tab, const uint32_t (&one)[K],
-                                         const Mod<K> &M, uint32_t *lds) {
-  constexpr int S = G * K;
-  st<K, G>(tab, one);
-  st<K, G>(tab + S, x);
-  uint32_t cur[K];
-  copy(cur, x);
-#pragma unroll 1
-  for (int d = 2; d < kTable; ++d) {
-    mont_mul<K, G>(cur, cur, x, M, lds);
-    st<K, G>(tab + d * S, cur);
-  }
-  __threadfence_block();
-  ld<K, G>(cur, tab + exp_digit(e, nwin - 1) * S);
-#pragma unroll 1
-  for (int w = nwin - 2; w >= 0; --w) {
-    uint32_t tb[K];
-    ld<K, G>(tb, tab + exp_digit(e, w) * S);
-#pragma unroll 1
-    for (int s = 0; s < kWindow; ++s) mont_mul<K, G>(cur, cur, cur, M, lds);
-    mont_mul<K, G>(cur, cur, tb, M, lds);
-  }
-  copy(x, cur);
-}
-
 // Moves an integer between limb layouts through this group's LDS row:
 // src has G*KS limbs (KS per lane), dst gets G*KD limbs (KD per lane); the
 // limbs are taken starting at `first` and limbs beyond the source are zero.

@@ -85,26 +85,30 @@ __device__ __forceinline__ Mod29<K> load_mod29(const DMod &D) {
 }
 
 
-// One step for multiplier limb ai (see the header comment).
+// One step for multiplier limb ai (see the header comment).  The lane's new
+// top column (the low 29 bits handed down by the next lane) is kept in `top`
+// and enters the next step as the addend of that column's first
+// multiply-add, so no register copy places it; C[K-1] is stale between steps.
 template <int K, int G>
-__device__ __forceinline__ void step29(uint64_t (&C)[K], uint32_t ai, const uint32_t (&b)[K],
+__device__ __forceinline__ void step29(uint64_t (&C)[K], uint32_t &top, uint32_t ai, const uint32_t (&b)[K],
                                        const Mod29<K> &M) {
   static_assert(K >= 2 && K <= 31, "column bound needs 2 <= K <= 31");
 #pragma unroll
-  for (int j = 0; j < K; ++j) C[j] += (uint64_t)ai * b[j];
+  for (int j = 0; j + 1 < K; ++j) C[j] += (uint64_t)ai * b[j];
+  C[K - 1] = (uint64_t)top + (uint64_t)ai * b[K - 1];
   const uint32_t q = bcast_first<G>(mul_lo32((uint32_t)C[0], M.ninv) & kMask29);
 #pragma unroll
   for (int j = 0; j < K; ++j) C[j] += (uint64_t)q * M.n[j];
-  const uint32_t nb = rotate_next<G>((uint32_t)C[0] & kMask29);
+  top = rotate_next<G>((uint32_t)C[0] & kMask29);
   C[1] += C[0] >> he29::kBits;
 #pragma unroll
   for (int j = 0; j + 1 < K; ++j) C[j] = C[j + 1];
-  C[K - 1] = nb;
   // The sums are opaque from one step to the next (an empty asm per column,
   // no instruction), so the compiler keeps one accumulator per column instead
   // of reassociating several steps' products into extra registers.
 #pragma unroll
-  for (int j = 0; j < K; ++j) asm("" : "+v"(C[j]));
+  for (int j = 0; j + 1 < K; ++j) asm("" : "+v"(C[j]));
+  asm("" : "+v"(top));
 }
 
 // t = a b R'^-1 mod N (settled, below 2N) with a (settled, below 2N) in this
@@ -116,8 +120,9 @@ __device__ __forceinline__ void mm29_lds(uint32_t (&t)[K], const uint32_t *a_lds
   constexpr int U = K % 2 == 0 ? K : 2 * K;  // steps per loop iteration (even: 64-bit LDS reads)
   static_assert(S % U == 0, "unroll must divide the limb count");
   uint64_t C[K];
+  uint32_t top = 0;
 #pragma unroll
-  for (int j = 0; j < K; ++j) C[j] = 0;
+  for (int j = 0; j + 1 < K; ++j) C[j] = 0;
 #pragma unroll 1
   for (int i0 = 0; i0 < S; i0 += U) {
     uint32_t av[U];
@@ -127,8 +132,9 @@ __device__ __forceinline__ void mm29_lds(uint32_t (&t)[K], const uint32_t *a_lds
       av[h] = v.x; av[h + 1] = v.y;
     }
 #pragma unroll
-    for (int s = 0; s < U; ++s) step29<K, G>(C, av[s], b, M);
+    for (int s = 0; s < U; ++s) step29<K, G>(C, top, av[s], b, M);
   }
+  C[K - 1] = top;
   // settle: one carry pass in the lane, the lane's carry (below 2^36) into
   // the next lane's lowest limb; the group's top carry is zero (result < 2N)
   uint64_t c = 0;

@@ -168,6 +168,40 @@ def test_obfuscated_encryption_bit_exact(he, bits, seed, count, offset):
     assert he.limbs_to_ints(host(rho2)) == pool.encrypt_many(pk, ms[:40], rx)
 
 
+def _group_counts(cus):
+    """Encryption counts that make the group-width rule of the CRT kernels
+    (narrowest group, 2 lanes only for the mod-p kernel, whose launch still
+    gives every SIMD two waves: 2 * ceil(count / (64 / G)) >= 8 * CUs) pick
+    each width: mod-p kernel 2, 4, 8, 16 and lift / decryption 4, 4, 8, 16."""
+    need = 8 * cus
+    return [int(32 * need / 2) + 7, int(16 * need / 2) + 5, int(8 * need / 2) + 3, 1000]
+
+
+def test_exponentiation_group_widths(he):
+    """Encryption and decryption at counts that run the radix-2^29
+    exponentiations at every group width (2, 4, 8 and 16 lanes): sampled
+    ciphertexts bit-exact against the oracle, every decryption exact."""
+    import torch
+    bits = 2048
+    sk = oracle_key(bits, 2)
+    pk = sk.public
+    k = gpu_key(bits, 2)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    rng = np.random.default_rng(31)
+    for count in _group_counts(cus):
+        say(f"group widths: {count} encryptions")
+        m = rng.integers(-(1 << 62), 1 << 62, size=count, dtype=np.int64)
+        ct = he.encrypt(k, dev(m), seed=77)
+        dm, _, ovf = he.decrypt(k, ct)
+        assert host(dm).tolist() == m.tolist()
+        assert int(host(ovf)[0]) == 0
+        pick = rng.choice(count, size=6, replace=False)
+        got = he.limbs_to_ints(host(ct)[pick])
+        want = pool.encrypt_many(pk, [int(m[i]) % pk.n for i in pick],
+                                 [P.seeded_r(pk.n, bits, 77, int(i)) for i in pick])
+        assert got == want
+
+
 # ---------------------------------------------------------- decryption
 @pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
 def test_decrypt_exact(he, bits, seed):

@@ -37,6 +37,7 @@ template <int K>
 struct Mod29 {
   uint32_t n[K];  // this lane's 29-bit limbs of N
   uint32_t ninv;  // -N^-1 mod 2^29
+  uint32_t mask;  // 2^29 - 1, held in a VGPR for the masked DPP moves
 };
 
 // Lane-local K words at lane offset glane * K (64-bit accesses for even K).
@@ -81,9 +82,48 @@ __device__ __forceinline__ Mod29<K> load_mod29(const DMod &D) {
   Mod29<K> m;
   ld29<K, G>(m.n, D.N29[he29::variant(G)]);
   m.ninv = D.ninv & kMask29;
+  m.mask = kMask29;
   return m;
 }
 
+
+// x from the group's first lane (resp. the next lane, the last lane reading
+// the first), masked to 29 bits, in one v_and_b32_dpp.  The s_nop gives the
+// DPP read of x the two wait states it needs after the VALU write of x; it
+// costs this wave an issue cycle, not a VALU slot.  8-lane groups have no
+// single DPP control for either move and use the separate move and mask.
+template <int G>
+__device__ __forceinline__ uint32_t bcast_first_m29(uint32_t x, uint32_t mask) {
+  uint32_t r;
+  if constexpr (G == 2)
+    asm("s_nop 1\n\tv_and_b32_dpp %0, %1, %2 quad_perm:[0,0,2,2] row_mask:0xf bank_mask:0xf"
+        : "=v"(r) : "v"(x), "v"(mask));
+  else if constexpr (G == 4)
+    asm("s_nop 1\n\tv_and_b32_dpp %0, %1, %2 quad_perm:[0,0,0,0] row_mask:0xf bank_mask:0xf"
+        : "=v"(r) : "v"(x), "v"(mask));
+  else if constexpr (G == 16)
+    asm("s_nop 1\n\tv_and_b32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf"
+        : "=v"(r) : "v"(x), "v"(mask));
+  else
+    r = bcast_first<G>(x) & mask;
+  return r;
+}
+template <int G>
+__device__ __forceinline__ uint32_t rotate_next_m29(uint32_t x, uint32_t mask) {
+  uint32_t r;
+  if constexpr (G == 2)
+    asm("s_nop 1\n\tv_and_b32_dpp %0, %1, %2 quad_perm:[1,0,3,2] row_mask:0xf bank_mask:0xf"
+        : "=v"(r) : "v"(x), "v"(mask));
+  else if constexpr (G == 4)
+    asm("s_nop 1\n\tv_and_b32_dpp %0, %1, %2 quad_perm:[1,2,3,0] row_mask:0xf bank_mask:0xf"
+        : "=v"(r) : "v"(x), "v"(mask));
+  else if constexpr (G == 16)
+    asm("s_nop 1\n\tv_and_b32_dpp %0, %1, %2 row_ror:15 row_mask:0xf bank_mask:0xf"
+        : "=v"(r) : "v"(x), "v"(mask));
+  else
+    r = rotate_next<G>(x) & mask;
+  return r;
+}
 
 // One step for multiplier limb ai (see the header comment).  The lane's new
 // top column (the low 29 bits handed down by the next lane) is kept in `top`
@@ -96,10 +136,10 @@ __device__ __forceinline__ void step29(uint64_t (&C)[K], uint32_t &top, uint32_t
 #pragma unroll
   for (int j = 0; j + 1 < K; ++j) C[j] += (uint64_t)ai * b[j];
   C[K - 1] = (uint64_t)top + (uint64_t)ai * b[K - 1];
-  const uint32_t q = bcast_first<G>(mul_lo32((uint32_t)C[0], M.ninv) & kMask29);
+  const uint32_t q = bcast_first_m29<G>(mul_lo32((uint32_t)C[0], M.ninv), M.mask);
 #pragma unroll
   for (int j = 0; j < K; ++j) C[j] += (uint64_t)q * M.n[j];
-  top = rotate_next<G>((uint32_t)C[0] & kMask29);
+  top = rotate_next_m29<G>((uint32_t)C[0], M.mask);
   C[1] += C[0] >> he29::kBits;
 #pragma unroll
   for (int j = 0; j + 1 < K; ++j) C[j] = C[j + 1];

@@ -20,7 +20,10 @@
  *    n_bits bits has L = n_bits / 32 limbs for n and 2L limbs for n^2, so one
  *    ciphertext occupies 2L limbs (256 B at 1024 bits, 512 B at 2048 bits).
  *  - Ciphertexts crossing the ABI are canonical residues in [0, n^2) unless a
- *    parameter says HE_FORM_MONT (Montgomery form x * 2^(64L) mod n^2).
+ *    parameter says HE_FORM_MONT: the Montgomery form x * R' mod n^2 of the
+ *    histogram kernels, a canonical residue in the same 2L-limb layout, with
+ *    R' = 2^(29 s) for their s limbs of 29 bits (s = 144 at 2048 bits, 72 at
+ *    1024 bits).
  *  - Pointers documented as "device" are HIP device pointers owned by the
  *    caller; the library never frees or retains them after the call returns.
  *    Pointers documented as "host" are read or written before return.
@@ -137,8 +140,9 @@ int he_obfuscators(const he_key *key, uint64_t count, const uint32_t *r, uint64_
 int he_encrypt_obfuscated(const he_key *key, const int64_t *m, uint64_t count, const uint32_t *rho,
                           uint32_t *ct, hipStream_t stream);
 
-/* Montgomery conversion of ciphertexts: out = in * 2^(64L) mod n^2 (to_mont)
- * or in * 2^(-64L) mod n^2 (from_mont).  Device uint32[count][2L]; in-place
+/* Montgomery conversion of ciphertexts: out = in * R' mod n^2 (to_mont) or
+ * in * R'^-1 mod n^2 (from_mont), R' as for HE_FORM_MONT above (the radix-2^29
+ * Montgomery factor of the histogram kernels).  Device uint32[count][2L]; in-place
  * (in == out) is allowed.  Keeps gradients resident in the form the
  * histogram kernels consume, so the conversion is paid once per round. */
 int he_to_mont(const he_key *key, const uint32_t *in, uint64_t count, uint32_t *out,

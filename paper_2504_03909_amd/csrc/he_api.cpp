@@ -517,7 +517,9 @@ int plan_layout(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_for
   lay.o_nitems = take(4);
   lay.o_items = take(std::max<uint64_t>(lay.items_cap, 1) * sizeof(he::HistItem));
   lay.o_perm = take(std::max<uint64_t>(lay.total_perm, 1) * 4);
-  lay.o_part = take(std::max<uint64_t>(lay.items_cap, 1) * 2 * S * 4);
+  // partial products in the histogram kernels' 29-bit limbs
+  const uint64_t S29 = (uint64_t)he29::limbs_for_group((int)S, he::kHistGroup);
+  lay.o_part = take(std::max<uint64_t>(lay.items_cap, 1) * 2 * S29 * 4);
   lay.convert = ct_form == HE_FORM_CANONICAL && rows > 0;
   lay.o_ctm = lay.convert ? take(rows * 2 * S * 4) : 0;
   lay.bytes = off;

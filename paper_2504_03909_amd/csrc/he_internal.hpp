@@ -82,7 +82,7 @@ struct HistWs {
   uint32_t *n_items;                               // device scalar
   HistItem *items;                                 // [items_cap]
   uint32_t *perm;                                  // [total_perm]
-  uint32_t *partials;                              // [items_cap][2][S]
+  uint32_t *partials;                              // [items_cap][2][S29], 29-bit limbs
   uint64_t total_fb, total_f, total_blocks, items_cap;
   uint32_t chunk;                                  // samples per item
   uint32_t split;                                  // groups per (item, slot): 1 or 2
@@ -92,7 +92,8 @@ struct HistWs {
 constexpr int kWindowBits = 5;     // exponent window width (see mont.hpp)
 constexpr int kSampleBlock = 4096;   // samples per bucketing block
 constexpr int kBlockThreads = 256;   // 4 waves
-constexpr int kHistGroup = 16;      // lanes per integer in the histogram kernels (8 measured slower)
+constexpr int kHistGroup = 16;      // lanes per integer in the histogram kernels
+constexpr int kHistWaves = 5;       // waves per SIMD asked of the histogram product kernel
 
 // ---- launchers (he_kernels.hip) ------------------------------------------------
 // KP = limbs per lane of a prime: 1 for 1024-bit keys, 2 for 2048-bit keys.

@@ -597,25 +597,30 @@ __global__ void k_unpack(const uint32_t *__restrict__ raw, uint64_t count, uint3
 }
 
 // ------------------------------------------------------ Montgomery conversion
-template <int KP>
+// x -> x R' mod n^2 (to_mont) or x R'^-1 mod n^2, R' the radix-2^29 factor of
+// the histogram kernels' G-lane groups; canonical 32-bit limbs in and out.
+template <int KP, int G>
 __global__ __launch_bounds__(kBlockThreads) void k_mont_convert(DKey key, const uint32_t *in, uint64_t count,
                                                                uint32_t *out, int to_mont) {
-  constexpr int KN2 = 4 * KP, SN2 = 64 * KP;
-  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
-  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
-  uint32_t *lds = lds_all + gi * SN2;
-  uint64_t i = (uint64_t)blockIdx.x * 16 + gi;
+  constexpr int SN2 = 64 * KP, K32 = SN2 / G, GB = kBlockThreads / G;
+  constexpr int S29 = he29::limbs_for_group(SN2, G), K = S29 / G, ROW = S29 > SN2 ? S29 : SN2;
+  __shared__ __align__(16) uint32_t lds_all[GB * ROW];
+  uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
+  uint64_t i = (uint64_t)blockIdx.x * GB + threadIdx.x / G;
   const bool valid = i < count;
   if (!valid) i = count - 1;
-  const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
-  uint32_t x[KN2], c[KN2];
-  ld<KN2>(x, in + i * SN2);
+  const Mod29<K> M = load_mod29<K, G>(key.n2);
+  uint32_t x[K32], t[K], c[K];
+  ld<K32, G>(x, in + i * SN2);
+  to29<K32, K, G>(t, x, lds);
   if (to_mont)
-    ld<KN2>(c, key.n2.R2);
+    ld29<K, G>(c, key.n2.R2_29[he29::variant(G)]);
   else
-    set_small(c, 1u);
-  mont_mul<KN2>(x, x, c, M, lds);
-  if (valid) st<KN2>(out + i * SN2, x);
+    set_small<K, G>(c, 1u);
+  mm29<K, G>(t, t, c, M, lds);
+  canon29<K, G>(t, M);
+  to32<K, K32, G>(x, t, lds);
+  if (valid) st<K32, G>(out + i * SN2, x);
 }
 
 // -------------------------------------------------------------- decryption
@@ -901,25 +906,29 @@ __global__ __launch_bounds__(256) void k_hist_scatter(HistWs ws) {
 // the slot g/h).  With split 2 an item is taken by four groups: bit 1 of the
 // group index picks the first or second half of the chunk, the halves are
 // combined at the end, and a wave takes GW / 4 items.  With split 1 a wave
-// takes GW / 2 items, one group per (item, slot).  Output in Montgomery form.
-// Every loop bound is the maximum over the wave's items, so the cross-lane
-// steps of the arithmetic always run on the whole wave.
+// takes GW / 2 items, one group per (item, slot).  The gathered rows are in
+// the radix-2^29 Montgomery form x R' mod n^2 (32-bit limbs); each is moved
+// to 29-bit limbs through the group's LDS row and multiplied into the
+// accumulator, which stays in 29-bit limbs; partials are stored settled in
+// 29-bit limbs (S29 words).  Every loop bound is the maximum over the wave's
+// items, so the cross-lane steps of the arithmetic always run on the whole
+// wave.
 template <int KP, int G>
-__global__ __launch_bounds__(kBlockThreads, 5) void k_hist_chunk(DKey key, const uint32_t *__restrict__ ctm,
-                                                             HistWs ws) {
-  constexpr int S = 64 * KP, K = S / G, GW = 64 / G;
-  __shared__ __align__(16) uint32_t lds_all[(kBlockThreads / 64) * GW * S];
+__global__ __launch_bounds__(kBlockThreads, kHistWaves) void k_hist_chunk(DKey key, const uint32_t *__restrict__ ctm,
+                                                                      HistWs ws) {
+  constexpr int S = 64 * KP, K32 = S / G, GW = 64 / G;
+  constexpr int S29 = he29::limbs_for_group(S, G), K = S29 / G, ROW = S29 > S ? S29 : S;
+  __shared__ __align__(16) uint32_t lds_all[(kBlockThreads / 64) * GW * ROW];
   const uint32_t g = (threadIdx.x & 63u) / G;
   const uint32_t wrow = wave_in_block() * GW;
-  uint32_t *lds = lds_all + (wrow + g) * S;
+  uint32_t *lds = lds_all + (wrow + g) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
   const uint32_t slot = g & 1u;
   const bool split = ws.split == 2;
   const uint32_t half = (g >> 1) & 1u;
-  const Mod<K> M = load_mod<K, G>(key.n2.N, key.n2.ninv);
-  uint32_t one[K];
-  ld<K, G>(one, key.n2.R1);
+  const Mod29<K> M = load_mod29<K, G>(key.n2);
+  const uint32_t *one29 = key.n2.R1_29[he29::variant(G)];  // Montgomery form of 1
   const uint64_t n_items = *ws.n_items;
   const uint64_t per_wave = split ? GW / 4 : GW / 2;
   for (uint64_t w0 = gw * per_wave; w0 < n_items; w0 += nw * per_wave) {
@@ -943,43 +952,43 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_hist_chunk(DKey key, const
       start = item.start;
     }
     const uint32_t *pp = ws.perm + start;
-    uint32_t acc[K], b[K];
-    if (my_len)
-      ld<K, G>(acc, ctm + ((uint64_t)pp[0] * 2 + slot) * S);
-    else
-      copy(acc, one);
+    // rows of groups with nothing to do read row 0 (in bounds); their
+    // products are discarded by the selects
     const uint32_t last = my_len ? my_len - 1 : 0u;
-    if (trip > 1) {
-      if (my_len)
-        ld<K, G>(b, ctm + ((uint64_t)pp[min(1u, last)] * 2 + slot) * S);
-      else
-        copy(b, one);
+    const uint32_t *base = ctm + (uint64_t)slot * S;
+    uint32_t acc[K];
+    {
+      uint32_t x[K32];
+      ld<K32, G>(x, base + (my_len ? (uint64_t)pp[0] * 2 * S : 0));
+      to29<K32, K, G>(acc, x, lds);
+      uint32_t one[K];
+      ld29<K, G>(one, one29);
+      select(acc, my_len != 0u, acc, one);
     }
+    // the row of each product is loaded at the top of its iteration (no
+    // prefetch: the registers go to the columns; the other waves of the SIMD
+    // cover the gather)
 #pragma unroll 1
     for (uint32_t k = 1; k < trip; ++k) {
-      uint32_t nb[K];
-      if (k + 1 < trip) {
-        if (my_len)
-          ld<K, G>(nb, ctm + ((uint64_t)pp[min(k + 1, last)] * 2 + slot) * S);
-        else
-          copy(nb, one);
-      }
-      uint32_t t[K];
-      mont_mul<K, G>(t, acc, b, M, lds);
-      select(acc, k < my_len, t, acc);
-      if (k + 1 < trip) copy(b, nb);
+      // past the end of this group's run the multiplier is the Montgomery
+      // form of 1, so the product leaves the accumulator's value as it is
+      uint32_t x[K32], a[K];
+      ld<K32, G>(x, base + (my_len ? (uint64_t)pp[min(k, last)] * 2 * S : 0));
+      to29<K32, K, G>(a, x, lds);
+      if (k >= my_len) ld29<K, G>(a, one29);
+      mm29<K, G>(acc, a, acc, M, lds);
     }
     if (split) {
       // combine the two halves
-      st<K, G>(lds, acc);
+      st29<K, G>(lds, acc);
       __builtin_amdgcn_wave_barrier();
       uint32_t other[K];
-      ld<K, G>(other, lds_all + (wrow + (g ^ 2u)) * S);
+      ld29<K, G>(other, lds_all + (wrow + (g ^ 2u)) * ROW);
       __builtin_amdgcn_wave_barrier();
-      mont_mul<K, G>(acc, acc, other, M, lds);
-      if (half == 0 && valid) st<K, G>(ws.partials + (it * 2 + slot) * S, acc);
+      mm29<K, G>(acc, acc, other, M, lds);
+      if (half == 0 && valid) st29<K, G>(ws.partials + (it * 2 + slot) * S29, acc);
     } else if (valid) {
-      st<K, G>(ws.partials + (it * 2 + slot) * S, acc);
+      st29<K, G>(ws.partials + (it * 2 + slot) * S29, acc);
     }
     if (ws.mm_count && glane<G>() == 0) {
       // products joining two real partials (the algorithm's count) and
@@ -1001,17 +1010,17 @@ __global__ __launch_bounds__(kBlockThreads, 5) void k_hist_chunk(DKey key, const
 // chunks) like k_hist_chunk.
 template <int KP, int G>
 __global__ __launch_bounds__(kBlockThreads) void k_hist_final(DKey key, HistWs ws) {
-  constexpr int S = 64 * KP, K = S / G, GW = 64 / G, EPW = GW / 4;
-  __shared__ __align__(16) uint32_t lds_all[(kBlockThreads / 64) * GW * S];
+  constexpr int S = 64 * KP, K32 = S / G, GW = 64 / G, EPW = GW / 4;
+  constexpr int S29 = he29::limbs_for_group(S, G), K = S29 / G, ROW = S29 > S ? S29 : S;
+  __shared__ __align__(16) uint32_t lds_all[(kBlockThreads / 64) * GW * ROW];
   const uint32_t g = (threadIdx.x & 63u) / G;
   const uint32_t wrow = wave_in_block() * GW;
-  uint32_t *lds = lds_all + (wrow + g) * S;
+  uint32_t *lds = lds_all + (wrow + g) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
   const uint32_t slot = g & 1u, half = (g >> 1) & 1u;
-  const Mod<K> M = load_mod<K, G>(key.n2.N, key.n2.ninv);
-  uint32_t one[K];
-  ld<K, G>(one, key.n2.R1);
+  const Mod29<K> M = load_mod29<K, G>(key.n2);
+  const uint32_t *one29 = key.n2.R1_29[he29::variant(G)];  // Montgomery form of 1
   for (uint64_t e0 = gw * EPW; e0 < ws.total_fb; e0 += nw * EPW) {
     const uint64_t e = e0 + (g >> 2);
     const bool valid = e < ws.total_fb;
@@ -1030,34 +1039,30 @@ __global__ __launch_bounds__(kBlockThreads) void k_hist_final(DKey key, HistWs w
       hi_any |= ws.fch[w] >> 1;
     }
     uint32_t acc[K], b[K];
-    if (my_n)
-      ld<K, G>(acc, ws.partials + (p0 * 2 + slot) * S);
-    else
-      copy(acc, one);
+    ld29<K, G>(acc, my_n ? ws.partials + (p0 * 2 + slot) * S29 : one29);
 #pragma unroll 1
     for (uint32_t k = 1; k < lo_max; ++k) {
-      const uint32_t kk = min(k, my_n ? my_n - 1 : 0u);
-      if (my_n)
-        ld<K, G>(b, ws.partials + ((p0 + kk) * 2 + slot) * S);
-      else
-        copy(b, one);
-      uint32_t t[K];
-      mont_mul<K, G>(t, acc, b, M, lds);
-      select(acc, k < my_n, t, acc);
+      // past this group's partials the multiplier is the Montgomery form of 1
+      ld29<K, G>(b, k < my_n ? ws.partials + ((p0 + k) * 2 + slot) * S29 : one29);
+      mm29<K, G>(acc, b, acc, M, lds);
     }
     if (hi_any) {  // wave-uniform
-      st<K, G>(lds, acc);
+      st29<K, G>(lds, acc);
       __builtin_amdgcn_wave_barrier();
       uint32_t other[K];
-      ld<K, G>(other, lds_all + (wrow + (g ^ 2u)) * S);
+      ld29<K, G>(other, lds_all + (wrow + (g ^ 2u)) * ROW);
       __builtin_amdgcn_wave_barrier();
       uint32_t t[K];
-      mont_mul<K, G>(t, acc, other, M, lds);
+      mm29<K, G>(t, acc, other, M, lds);
       select(acc, n_hi != 0u, t, acc);
     }
+    // out of Montgomery form (a product with 1), exact, back to 32-bit limbs
     set_small<K, G>(b, 1u);
-    mont_mul<K, G>(acc, acc, b, M, lds);  // out of Montgomery form
-    if (half == 0 && valid) st<K, G>(J.hist + (fb * 2 + slot) * S, acc);
+    mm29<K, G>(acc, acc, b, M, lds);
+    canon29<K, G>(acc, M);
+    uint32_t y[K32];
+    to32<K, K32, G>(y, acc, lds);
+    if (half == 0 && valid) st<K32, G>(J.hist + (fb * 2 + slot) * S, y);
     if (ws.mm_count && glane<G>() == 0 && valid) {
       const uint64_t real = (my_n ? my_n - 1 : 0) + ((half == 0 && n_hi) ? 1 : 0);
       const uint64_t done = (lo_max ? lo_max - 1 : 0) + (hi_any ? 1 : 0) + 1;
@@ -1228,11 +1233,13 @@ uint32_t pack_slots(int n_bits, uint64_t count) {
 hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64_t count,
                                uint32_t *out, bool to_mont, hipStream_t s) {
   if (!count) return hipSuccess;
-  const dim3 grid(blocks_for(count, 16));
+  const dim3 grid(blocks_for(count, kBlockThreads / kHistGroup));
   if (KP == 1)
-    hipLaunchKernelGGL(k_mont_convert<1>, grid, dim3(kBlockThreads), 0, s, k, in, count, out, (int)to_mont);
+    hipLaunchKernelGGL((k_mont_convert<1, kHistGroup>), grid, dim3(kBlockThreads), 0, s, k, in, count, out,
+                       (int)to_mont);
   else
-    hipLaunchKernelGGL(k_mont_convert<2>, grid, dim3(kBlockThreads), 0, s, k, in, count, out, (int)to_mont);
+    hipLaunchKernelGGL((k_mont_convert<2, kHistGroup>), grid, dim3(kBlockThreads), 0, s, k, in, count, out,
+                       (int)to_mont);
   return hipGetLastError();
 }
 

@@ -22,7 +22,7 @@
  *  - Ciphertexts crossing the ABI are canonical residues in [0, n^2) unless a
  *    parameter says HE_FORM_MONT: the Montgomery form x * R' mod n^2 of the
  *    histogram kernels, a canonical residue in the same 2L-limb layout, with
- *    R' = 2^(29 s) for their s limbs of 29 bits (s = 144 at 2048 bits, 72 at
+ *    R' = 2^(29 s) for their s limbs of 29 bits (s = 144 at 2048 bits, 80 at
  *    1024 bits).
  *  - Pointers documented as "device" are HIP device pointers owned by the
  *    caller; the library never frees or retains them after the call returns.

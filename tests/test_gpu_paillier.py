@@ -287,6 +287,27 @@ def test_c1_full_path_bit_exact(he):
     assert torch.equal(he.from_mont(k, ctm), ct)
 
 
+@pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
+def test_montgomery_form_definition(he, bits, seed):
+    """he_to_mont is x R' mod n^2 with R' = 2^(29 s), s the histogram
+    kernels' 29-bit limb count (144 at 2048 bits, 80 at 1024 bits with their
+    16-lane groups), canonical in the 2L-limb layout; he_from_mont inverts it
+    (checked with Python integers, including 0, 1 and n^2 - 1)."""
+    sk = oracle_key(bits, seed)
+    n2 = sk.public.n * sk.public.n
+    k = gpu_key(bits, seed)
+    s = {1024: 80, 2048: 144}[bits]
+    R = pow(2, 29 * s, n2)
+    rng = np.random.default_rng(3)
+    xs = [0, 1, n2 - 1] + [int.from_bytes(rng.bytes(bits // 4), "little") % n2 for _ in range(61)]
+    ct = dev(he.ints_to_limbs(xs, 2 * k.limbs))
+    say(f"montgomery form {bits}")
+    got = he.limbs_to_ints(host(he.to_mont(k, ct)))
+    assert got == [x * R % n2 for x in xs]
+    back = he.limbs_to_ints(host(he.from_mont(k, he.to_mont(k, ct))))
+    assert back == xs
+
+
 @pytest.mark.parametrize("chunk", [1, 2, 3, 7, 64, 5000])
 def test_hist_independent_of_chunking_order_and_batching(he, chunk):
     """Subsets (ragged sizes, empty bins, an empty node, a single sample) in

@@ -87,14 +87,16 @@ __device__ __forceinline__ uint32_t from_next(uint32_t v) {
 // first lane (G = 2: quad_perm [1,0,3,2]; G = 4: quad_perm [1,2,3,0]; G = 16:
 // row_ror:15).  Used for the one-limb shift of a Montgomery step, where the
 // first lane's value is the cleared lowest column and therefore 0, so this
-// equals from_next without the edge fix-up; G = 8 has no 8-lane rotation and
-// uses from_next.
+// equals from_next without the edge fix-up.  G = 8 has no 8-lane rotation; it
+// uses row_shl:1, whose group-edge lane reads the next group's first lane,
+// which in this use holds zero as well (every group clears its own lowest
+// column), and the row's last lane reads 0 (bound_ctrl).
 template <int G = 16>
 __device__ __forceinline__ uint32_t rotate_next(uint32_t v) {
   if constexpr (G == 2) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0xB1, 0xF, 0xF, false);
   else if constexpr (G == 4) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x39, 0xF, 0xF, false);
   else if constexpr (G == 16) return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x12F, 0xF, 0xF, false);
-  else return from_next<G>(v);
+  else return (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x101, 0xF, 0xF, true);
 }
 // Lane l reads lane l-1 of its group; the group's first lane reads 0 (row_shr:1).
 template <int G = 16>

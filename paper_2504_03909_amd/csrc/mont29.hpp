@@ -88,10 +88,11 @@ __device__ __forceinline__ Mod29<K> load_mod29(const DMod &D) {
 
 
 // x from the group's first lane (resp. the next lane, the last lane reading
-// the first), masked to 29 bits, in one v_and_b32_dpp.  The s_nop gives the
-// DPP read of x the two wait states it needs after the VALU write of x; it
-// costs this wave an issue cycle, not a VALU slot.  8-lane groups have no
-// single DPP control for either move and use the separate move and mask.
+// the first), masked to 29 bits, in one v_and_b32_dpp (two, each writing one
+// half of the row, for the 8-lane broadcast; the 8-lane hand-down uses
+// row_shl:1, see rotate_next).  The s_nop gives the DPP read of x the two
+// wait states it needs after the VALU write of x; it costs this wave an issue
+// cycle, not a VALU slot.
 template <int G>
 __device__ __forceinline__ uint32_t bcast_first_m29(uint32_t x, uint32_t mask) {
   uint32_t r;
@@ -105,7 +106,9 @@ __device__ __forceinline__ uint32_t bcast_first_m29(uint32_t x, uint32_t mask) {
     asm("s_nop 1\n\tv_and_b32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0xf"
         : "=v"(r) : "v"(x), "v"(mask));
   else
-    r = bcast_first<G>(x) & mask;
+    asm("s_nop 1\n\tv_and_b32_dpp %0, %1, %2 row_newbcast:0 row_mask:0xf bank_mask:0x3\n\t"
+        "v_and_b32_dpp %0, %1, %2 row_newbcast:8 row_mask:0xf bank_mask:0xc"
+        : "=&v"(r) : "v"(x), "v"(mask));
   return r;
 }
 template <int G>
@@ -121,7 +124,8 @@ __device__ __forceinline__ uint32_t rotate_next_m29(uint32_t x, uint32_t mask) {
     asm("s_nop 1\n\tv_and_b32_dpp %0, %1, %2 row_ror:15 row_mask:0xf bank_mask:0xf"
         : "=v"(r) : "v"(x), "v"(mask));
   else
-    r = rotate_next<G>(x) & mask;
+    asm("s_nop 1\n\tv_and_b32_dpp %0, %1, %2 row_shl:1 row_mask:0xf bank_mask:0xf bound_ctrl:1"
+        : "=v"(r) : "v"(x), "v"(mask));
   return r;
 }
 

@@ -1009,7 +1009,7 @@ __global__ __launch_bounds__(kBlockThreads, kHistWaves) void k_hist_chunk(DKey k
 // per wave, each taken by four groups (slot g/h x first/second half of its
 // chunks) like k_hist_chunk.
 template <int KP, int G>
-__global__ __launch_bounds__(kBlockThreads) void k_hist_final(DKey key, HistWs ws) {
+__global__ __launch_bounds__(kBlockThreads, 4) void k_hist_final(DKey key, HistWs ws) {
   constexpr int S = 64 * KP, K32 = S / G, GW = 64 / G, EPW = GW / 4;
   constexpr int S29 = he29::limbs_for_group(S, G), K = S29 / G, ROW = S29 > S ? S29 : S;
   __shared__ __align__(16) uint32_t lds_all[(kBlockThreads / 64) * GW * ROW];

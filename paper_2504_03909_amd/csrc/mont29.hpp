@@ -1,5 +1,6 @@
-// Radix-2^29 Montgomery exponentiation for gfx950 (group layout as in
-// mont.hpp: G lanes per integer, lane l holding limbs l*K .. l*K+K-1).
+// Radix-2^29 Montgomery arithmetic for gfx950: the modular exponentiations
+// and the histogram products (group layout as in mont.hpp: G lanes per
+// integer, lane l holding limbs l*K .. l*K+K-1).
 //
 // With 29-bit limbs every partial product is below 2^58, and a 64-bit column
 // accumulator can absorb every product a column receives while it lives in

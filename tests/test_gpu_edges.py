@@ -1,7 +1,9 @@
 """Degenerate inputs across the GPU library: zero-length calls return
 success and touch nothing, a single-bin histogram holds the product of
-every sample, 256 bins (the maximum) and a one-sample node are exact, and
-counts that leave a ragged tail in every kernel's grid are exact."""
+every sample, 256 bins (the maximum) and a one-sample node are exact,
+counts that leave a ragged tail in every kernel's grid are exact, and
+explicit randomness at the ends of its range or off the unit group gives the
+formula's ciphertext."""
 import functools
 import sys
 
@@ -143,3 +145,22 @@ def test_ragged_counts_encrypt_decrypt(he, count):
     got = he.limbs_to_ints(host(ct))
     for i in sorted({0, count // 2, count - 1}):
         assert got[i] == P.encrypt(pk, int(m[i]), P.seeded_r(pk.n, 1024, count, i))
+
+
+@pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
+@pytest.mark.parametrize("public", [False, True])
+def test_encrypt_degenerate_r(he, bits, seed, public):
+    """Explicit r at the ends of its range and off the unit group: 1, 2,
+    n - 1, n + 1 and 2^(32 L) - 1 (only r mod n matters), and r = p, q, 2p,
+    n - p (0 mod p or mod q: the exponentiation bases are 0, the ciphertext
+    is not a unit).  Both the CRT and the public-key path give the formula's
+    value (1 + m n) r^n mod n^2, bit for bit."""
+    sk, k = keys(bits, seed)
+    n, p, q = sk.public.n, sk.p, sk.q
+    rs = [1, 2, n - 1, n + 1, (1 << (32 * k.limbs)) - 1, p, q, 2 * p, n - p]
+    ms = [0, 5, -3, 1 << 40, -(1 << 62), 7, -7, 0, 123456789]
+    say(f"degenerate r {bits} public={public}")
+    ct = he.encrypt(k, dev(np.array(ms, dtype=np.int64)), r=dev(he.ints_to_limbs(rs, k.limbs)), public=public)
+    got = he.limbs_to_ints(host(ct))
+    want = [P.encrypt(sk.public, m, r) for m, r in zip(ms, rs)]
+    assert got == want

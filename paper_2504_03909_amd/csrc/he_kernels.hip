@@ -530,49 +530,63 @@ template <int KP>
 __global__ __launch_bounds__(kBlockThreads) void k_pack(DKey key, const uint32_t *__restrict__ ct, uint64_t count,
                                                        uint32_t slots, uint32_t *__restrict__ packed) {
   constexpr int KN2 = 4 * KP, SN2 = 64 * KP;
-  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  constexpr int S29 = he29::limbs_for_group(SN2, 16), K = S29 / 16, ROW = S29 > SN2 ? S29 : SN2;
+  constexpr int v = he29::variant(16);
+  __shared__ __align__(16) uint32_t lds_all[16 * ROW];
   const uint32_t gi = wave_in_block() * 4 + group_in_wave();
-  uint32_t *lds = lds_all + gi * SN2;
+  uint32_t *lds = lds_all + gi * ROW;
   const uint64_t n_packed = (count + slots - 1) / slots;
   uint64_t p = (uint64_t)blockIdx.x * 16 + gi;
   const bool valid = p < n_packed;
   if (!valid) p = n_packed - 1;
   const uint64_t first = p * slots;
   const uint32_t my_slots = (uint32_t)min((uint64_t)slots, count - first);
-  const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
-  uint32_t r2[KN2], acc[KN2], x[KN2];
-  set_zero(x);
-  ld<KN2>(r2, key.n2.R2);
-  // top slot into Montgomery form; a shorter (last) packed ciphertext starts
-  // from the Montgomery one instead
-  const bool full = my_slots == slots;
-  ld<KN2>(acc, key.n2.R1);
-  if (full) ld<KN2>(x, ct + (first + slots - 1) * SN2);
-  mont_mul<KN2>(x, x, r2, M, lds);
-  select(acc, full, x, acc);
+  const Mod29<K> M = load_mod29<K, 16>(key.n2);
+  const uint32_t *one29 = key.n2.R1_29[v], *r2_29 = key.n2.R2_29[v];
+  // radix-2^29 Montgomery form of slot ciphertext j: x R'^2 R'^-1 = x R'; a
+  // slot this packed ciphertext does not have gets R' R' R'^-1 = R', the
+  // Montgomery one (its row read is the packed ciphertext's first, in bounds)
+  auto slot_mont = [&](uint32_t (&y)[K], uint32_t j, bool have) {
+    uint32_t x[KN2], c[K];
+    ld<KN2>(x, ct + (first + (have ? j : 0u)) * SN2);
+    to29<KN2, K, 16>(y, x, lds);
+    if (!have) ld29<K, 16>(y, one29);
+    ld29<K, 16>(c, have ? r2_29 : one29);
+    mm29<K, 16>(y, y, c, M, lds);
+  };
+  uint32_t acc[K];
+  // top slot; a shorter (last) packed ciphertext starts from the one
+  slot_mont(acc, slots - 1, my_slots == slots);
 #pragma unroll 1
   for (uint32_t j = slots - 1; j-- > 0;) {
 #pragma unroll 1
-    for (int t = 0; t < 64; ++t) mont_mul<KN2>(acc, acc, acc, M, lds);
-    const bool have = j < my_slots;
-    if (have) ld<KN2>(x, ct + (first + j) * SN2);
-    else ld<KN2>(x, key.n2.R1);
-    mont_mul<KN2>(x, x, r2, M, lds);
-    uint32_t t[KN2];
-    mont_mul<KN2>(t, acc, x, M, lds);
-    select(acc, have, t, acc);
+    for (int t = 0; t < 64; ++t) mm29<K, 16>(acc, acc, acc, M, lds);
+    uint32_t y[K];
+    slot_mont(y, j, j < my_slots);
+    mm29<K, 16>(acc, y, acc, M, lds);
   }
   // f = 1 + K n: K has bit 31 of every odd limb below 2 my_slots
+  uint32_t f[KN2];
+  {
+    const Mod<KN2> M32 = load_mod<KN2>(key.n2.N, key.n2.ninv);
+    uint32_t c[KN2];
 #pragma unroll
-  for (int i = 0; i < KN2; ++i) {
-    const uint32_t idx = glane() * KN2 + i;
-    x[i] = ((idx & 1u) && (idx >> 1) < my_slots) ? 0x80000000u : 0u;
+    for (int i = 0; i < KN2; ++i) {
+      const uint32_t idx = glane() * KN2 + i;
+      f[i] = ((idx & 1u) && (idx >> 1) < my_slots) ? 0x80000000u : 0u;
+    }
+    ld<KN2>(c, key.nR_n2);
+    mont_mul<KN2>(f, f, c, M32, lds);  // K n mod n^2
+    add_one<KN2>(f);
   }
-  ld<KN2>(r2, key.nR_n2);
-  mont_mul<KN2>(x, x, r2, M, lds);  // K n mod n^2
-  add_one<KN2>(x);
-  mont_mul<KN2>(acc, acc, x, M, lds);  // leaves Montgomery form
-  if (valid) st<KN2>(packed + p * SN2, acc);
+  // acc f R'^-1 leaves the Montgomery form
+  uint32_t f29[K];
+  to29<KN2, K, 16>(f29, f, lds);
+  mm29<K, 16>(acc, f29, acc, M, lds);
+  canon29<K, 16>(acc, M);
+  uint32_t out[KN2];
+  to32<K, KN2, 16>(out, acc, lds);
+  if (valid) st<KN2>(packed + p * SN2, out);
 }
 
 // Slot values of decrypted packed plaintexts raw[n_packed][L]: value i is

@@ -966,8 +966,8 @@ __global__ __launch_bounds__(kBlockThreads, kHistWaves) void k_hist_chunk(DKey k
       start = item.start;
     }
     const uint32_t *pp = ws.perm + start;
-    // rows of groups with nothing to do read row 0 (in bounds); their
-    // products are discarded by the selects
+    // a group with nothing (more) to do reads row 0 (in bounds) and takes
+    // the Montgomery one in its place
     const uint32_t last = my_len ? my_len - 1 : 0u;
     const uint32_t *base = ctm + (uint64_t)slot * S;
     uint32_t acc[K];

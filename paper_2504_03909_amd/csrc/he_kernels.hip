@@ -276,29 +276,45 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
 
 // ------------------------------------------------ obfuscated encryption
 // ct = (1 + (m mod n) n) rho mod n^2 with a precomputed obfuscator
-// rho = r^n mod n^2 (canonical): three Montgomery products per ciphertext.
+// rho = r^n mod n^2 (canonical).  Since (1 + m n) rho = rho + n (m rho) and
+// n x mod n^2 = n (x mod n), ct = rho + n t mod n^2 with t = m rho mod n:
+// three products mod n (rho R mod n from rho's halves, then times m) and
+// one mod n^2 (n t), instead of three mod n^2.
 template <int KP>
 __global__ __launch_bounds__(kBlockThreads) void k_enc_obf(DKey key, const int64_t *__restrict__ m,
                                                           uint64_t count, const uint32_t *rho,
                                                           uint32_t *ct) {
-  constexpr int KN2 = 4 * KP, SN2 = 64 * KP, L = 32 * KP;
+  constexpr int KN = 2 * KP, KN2 = 4 * KP, SN2 = 64 * KP, L = 32 * KP;
   __shared__ __align__(16) uint32_t lds_all[16 * SN2];
   const uint32_t gi = wave_in_block() * 4 + group_in_wave();
   uint32_t *lds = lds_all + gi * SN2;
   uint64_t i = (uint64_t)blockIdx.x * 16 + gi;
   const bool valid = i < count;
   if (!valid) i = count - 1;
+  uint32_t t2[KN2];
+  {
+    // t = m rho mod n: s = rho0 R + rho1 R^2 = rho R (mod n) from the halves
+    // rho = rho0 + rho1 R (R = 2^(32 L)), then t = s (m mod n) R^-1
+    const Mod<KN> Mn = load_mod<KN>(key.n.N, key.n.ninv);
+    uint32_t a[KN], b[KN], c[KN];
+    ld<KN>(a, rho + i * SN2);
+    ld<KN>(c, key.n.R2);
+    mont_mul<KN>(a, a, c, Mn, lds);
+    ld<KN>(b, rho + i * SN2 + L);
+    ld<KN>(c, key.n.R3);
+    mont_mul<KN>(b, b, c, Mn, lds);
+    add_mod<KN>(a, a, b, Mn);
+    signed_mod<KN>(b, m[i], Mn.n);
+    mont_mul<KN>(a, a, b, Mn, lds);
+    relayout<KN, KN2>(t2, a, lds);
+  }
+  // ct = rho + n t mod n^2 (n t by one product with n R' mod n^2)
   const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
-  uint32_t x[KN2], c[KN2], f[KN2];
-  ld<KN2>(x, rho + i * SN2);
-  ld<KN2>(c, key.n2.R2);
-  mont_mul<KN2>(x, x, c, M, lds);  // Montgomery form of rho
-  ld_part<KN2>(c, key.n.N, L);
-  signed_mod<KN2>(f, m[i], c);
+  uint32_t x[KN2], c[KN2];
   ld<KN2>(c, key.nR_n2);
-  mont_mul<KN2>(f, f, c, M, lds);  // (m mod n) n, exact
-  add_one<KN2>(f);
-  mont_mul<KN2>(x, x, f, M, lds);
+  mont_mul<KN2>(t2, t2, c, M, lds);
+  ld<KN2>(x, rho + i * SN2);
+  add_mod<KN2>(x, x, t2, M);
   if (valid) st<KN2>(ct + i * SN2, x);
 }
 

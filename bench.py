@@ -44,7 +44,7 @@ MI355X_HBM_BPS = 8.0e12
 # by a 256 MiB copy (profiles/enc_crt_2048_100k_counters.md).  Valid for the
 # kernel build those passes ran on; set to None when the encryption kernels
 # change until the passes are repeated.
-ENC_LAUNCH_TRAFFIC_BYTES = 5.6176e10
+ENC_LAUNCH_TRAFFIC_BYTES = 5.6182e10
 
 
 def mm_products(s: int) -> int:

@@ -152,13 +152,21 @@ int he_from_mont(const he_key *key, const uint32_t *in, uint64_t count, uint32_t
 
 /* One tree-node histogram job (Sec. III-B: each passive party sums the
  * encrypted gradients into the bins of its own features).
- *  sample_idx: device uint32[n_samples], rows of `ct` in this node (any order,
- *              no duplicates);
+ *  sample_idx: device uint32[n_samples], rows of `ct` in this node (any order;
+ *              a row listed twice is multiplied in twice);
  *  bins:       device uint8[n_features][bins_ld]; bins[f][row] is the bin of
  *              sample `row` for feature f (bins_ld >= rows);
  *  n_bins:     1..256;
  *  hist:       device uint32[n_features][n_bins][2][2L] output, canonical;
- *              slot 0 accumulates g, slot 1 accumulates h. */
+ *              slot 0 accumulates g, slot 1 accumulates h;
+ *  n_bad:      device uint32, optional (NULL): receives (atomically, not
+ *              cleared) the number of skipped (sample, feature) pairs.
+ * Device data is checked, not trusted: a sample whose row is not below the
+ * call's `rows` is skipped for every feature, and a sample whose bin for a
+ * feature is not below n_bins is skipped for that feature; skipped pairs
+ * join no bin and are only counted.  (Reading a device value out of range
+ * never indexes memory.)  The call cannot detect ciphertexts made under a
+ * different key of the same size: they are multiplied like any others. */
 typedef struct he_hist_job {
   const uint32_t *sample_idx;
   uint64_t n_samples;
@@ -167,6 +175,7 @@ typedef struct he_hist_job {
   uint32_t n_features;
   uint32_t n_bins;
   uint32_t *hist;
+  uint32_t *n_bad;
 } he_hist_job;
 
 /* Encrypted histogram aggregation for n_jobs nodes in one batch:

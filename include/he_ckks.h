@@ -4,8 +4,12 @@
  * ciphertext carries a whole histogram vector).  Public-key encryption,
  * addition and decryption only.
  *
- * Ring Z_Q[X]/(X^N + 1), N = 2^log_n (log_n in [10, 14]), Q = q0 q1 q2 with
+ * Ring Z_Q[X]/(X^N + 1), N = 2^log_n (log_n in [12, 14]), Q = q0 q1 q2 with
  * the three largest primes below 2^30 that are 1 mod 2N, kept in RNS form.
+ * Q is about 2^90, inside the 128-bit classical security bounds of the
+ * homomorphic encryption standard for a ternary secret at these N (log Q up
+ * to 109, 218, 438 for N = 2^12, 2^13, 2^14); smaller N would not be, and
+ * he_ckks_create refuses them (HE_ERR_ARG).
  * Encoding of n <= N/2 reals z: the integer polynomial m with
  * m(zeta^(5^k)) ~ 2^scale_bits z_k (zeta = e^(i pi / N)); |2^scale_bits z| summed
  * over the ciphertexts that are added must stay below Q/2 (about 2^89).

@@ -401,7 +401,11 @@ extern "C" {
 
 int he_ckks_create(uint32_t log_n, uint32_t scale_bits, uint64_t seed, he_ckks **out) {
   if (!out) return fail(HE_ERR_ARG, "null out");
-  if (log_n < 10 || log_n > 14) return fail(HE_ERR_ARG, "log_n must be in [10, 14]");
+  // Q is about 2^90: within the 128-bit classical security bounds of the
+  // homomorphic encryption standard for a ternary secret (log Q at most 109
+  // at N = 2^12, 218 at 2^13, 438 at 2^14), far outside them at N = 2^10 or
+  // 2^11 (27 and 54), so smaller rings are refused.
+  if (log_n < 12 || log_n > 14) return fail(HE_ERR_ARG, "log_n must be in [12, 14]");
   if (scale_bits < 10 || scale_bits > 60) return fail(HE_ERR_ARG, "scale_bits must be in [10, 60]");
   auto *c = new he_ckks();
   c->log_n = log_n;

@@ -451,7 +451,7 @@ size_t align_up(size_t x, size_t a = 256) { return (x + a - 1) / a * a; }
 struct HistLayout {
   std::vector<he::DJob> dj;
   uint64_t total_fb = 0, total_f = 0, total_blocks = 0, total_perm = 0, items_cap = 0;
-  uint64_t contributions = 0;
+  uint64_t contributions = 0, rows = 0;
   size_t o_jobs = 0, o_counts = 0, o_offs = 0, o_cursor = 0, o_fch = 0, o_fitem = 0, o_ftot = 0,
          o_fbase = 0, o_nitems = 0, o_items = 0, o_perm = 0, o_part = 0, o_ctm = 0, bytes = 0;
   uint32_t chunk = 64, split = 2;
@@ -468,6 +468,7 @@ int plan_layout(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_for
   if (split != 1 && split != 2) return fail(HE_ERR_ARG, "split must be 1 or 2");
   const size_t S = 2 * (key->n_bits / 32);
   lay.dj.assign(n_jobs, he::DJob{});
+  lay.rows = rows;
   lay.chunk = chunk;
   lay.split = split;
   for (uint32_t j = 0; j < n_jobs; ++j) {
@@ -492,6 +493,7 @@ int plan_layout(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_for
     d.blk_off = lay.total_blocks;
     d.f_off = (uint32_t)lay.total_f;
     d.nblk = (uint32_t)((J.n_samples + he::kSampleBlock - 1) / he::kSampleBlock);
+    d.n_bad = J.n_bad;
     lay.total_fb += (uint64_t)d.F * d.B;
     lay.total_f += d.F;
     lay.total_blocks += (uint64_t)d.F * d.nblk;
@@ -545,6 +547,7 @@ he::HistWs bind_layout(const HistLayout &lay, char *base) {
   ws.total_f = lay.total_f;
   ws.total_blocks = lay.total_blocks;
   ws.items_cap = lay.items_cap;
+  ws.rows = lay.rows;
   ws.chunk = lay.chunk;
   ws.split = lay.split;
   return ws;

@@ -65,6 +65,7 @@ struct DJob {
   uint64_t blk_off;    // first sample block of this job (F * nblk blocks)
   uint32_t f_off;      // first (job, feature) entry
   uint32_t nblk;       // sample blocks per feature
+  uint32_t *n_bad;     // optional: skipped (sample, feature) pairs, device counter
 };
 
 struct HistItem {      // one chunk of one (feature, bin): perm[start .. start+len)
@@ -84,6 +85,7 @@ struct HistWs {
   uint32_t *perm;                                  // [total_perm]
   uint32_t *partials;                              // [items_cap][2][S29], 29-bit limbs
   uint64_t total_fb, total_f, total_blocks, items_cap;
+  uint64_t rows;                                   // resident ciphertext rows
   uint32_t chunk;                                  // samples per item
   uint32_t split;                                  // groups per (item, slot): 1 or 2
   unsigned long long *mm_count;                    // optional debug counters [3], else null

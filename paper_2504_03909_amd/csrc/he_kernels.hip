@@ -10,6 +10,7 @@
 #include <stdint.h>
 
 #include "he_internal.hpp"
+#include "hist_bucket.hpp"
 #include "mont.hpp"
 #include "mont29.hpp"
 
@@ -798,23 +799,33 @@ __device__ __forceinline__ uint32_t find_job_by_fb(const DJob *jobs, uint32_t n_
   return j;
 }
 
-// Bin counts of one (job, feature, sample block) into counts[fb].
+// Bin counts of one (job, feature, sample block) into counts[fb].  Samples
+// whose row is not resident or whose bin is out of range are skipped and
+// counted into the job's n_bad (bucket_sample).
 __global__ __launch_bounds__(256) void k_hist_count(HistWs ws) {
   __shared__ uint32_t h[256];
+  __shared__ uint32_t nbad;
   const uint64_t blk = blockIdx.x;
   const uint32_t jn = find_job_by_blk(ws.jobs, ws.n_jobs, blk);
   const DJob J = ws.jobs[jn];
-  const uint64_t local = blk - J.blk_off;
-  const uint32_t f = (uint32_t)(local / J.nblk);
-  const uint64_t s0 = (local % J.nblk) * kSampleBlock;
-  const uint64_t s1 = min(J.n, s0 + kSampleBlock);
+  uint32_t f;
+  uint64_t s0, s1;
+  bucket_block(blk - J.blk_off, J.nblk, J.n, kSampleBlock, f, s0, s1);
   h[threadIdx.x] = 0;
+  if (threadIdx.x == 0) nbad = 0;
   __syncthreads();
   const uint8_t *bf = J.bins + (uint64_t)f * J.ld;
-  for (uint64_t s = s0 + threadIdx.x; s < s1; s += 256) atomicAdd(&h[bf[J.idx[s]]], 1u);
+  for (uint64_t s = s0 + threadIdx.x; s < s1; s += 256) {
+    uint32_t row, bin;
+    if (bucket_sample(J.idx, bf, ws.rows, J.B, s, row, bin))
+      atomicAdd(&h[bin], 1u);
+    else
+      atomicAdd(&nbad, 1u);
+  }
   __syncthreads();
   if (threadIdx.x < J.B && h[threadIdx.x])
     atomicAdd(&ws.counts[J.fb_off + (uint64_t)f * J.B + threadIdx.x], h[threadIdx.x]);
+  if (threadIdx.x == 0 && nbad && J.n_bad) atomicAdd(J.n_bad, nbad);
 }
 
 // Per (job, feature): exclusive scan of the bin counts, chunk counts per bin
@@ -895,29 +906,28 @@ __global__ __launch_bounds__(256) void k_hist_items(HistWs ws) {
   }
 }
 
-// Scatter of sample rows into per-(feature, bin) runs of perm.
+// Scatter of sample rows into per-(feature, bin) runs of perm, skipping the
+// samples k_hist_count skipped (bucket_sample), so each run receives exactly
+// the samples counted for its bin.
 __global__ __launch_bounds__(256) void k_hist_scatter(HistWs ws) {
   __shared__ uint32_t h[256], base[256];
   const uint64_t blk = blockIdx.x;
   const uint32_t jn = find_job_by_blk(ws.jobs, ws.n_jobs, blk);
   const DJob J = ws.jobs[jn];
-  const uint64_t local = blk - J.blk_off;
-  const uint32_t f = (uint32_t)(local / J.nblk);
-  const uint64_t s0 = (local % J.nblk) * kSampleBlock;
-  const uint64_t s1 = min(J.n, s0 + kSampleBlock);
+  uint32_t f;
+  uint64_t s0, s1;
+  bucket_block(blk - J.blk_off, J.nblk, J.n, kSampleBlock, f, s0, s1);
   h[threadIdx.x] = 0;
   __syncthreads();
   const uint8_t *bf = J.bins + (uint64_t)f * J.ld;
   constexpr int kPer = kSampleBlock / 256;
   uint32_t rows[kPer], bn[kPer], rk[kPer];
+  bool ok[kPer];
 #pragma unroll
   for (int k = 0; k < kPer; ++k) {
     const uint64_t s = s0 + threadIdx.x + (uint64_t)k * 256;
-    if (s < s1) {
-      rows[k] = J.idx[s];
-      bn[k] = bf[rows[k]];
-      rk[k] = atomicAdd(&h[bn[k]], 1u);
-    }
+    ok[k] = s < s1 && bucket_sample(J.idx, bf, ws.rows, J.B, s, rows[k], bn[k]);
+    if (ok[k]) rk[k] = atomicAdd(&h[bn[k]], 1u);
   }
   __syncthreads();
   const uint64_t e0 = J.fb_off + (uint64_t)f * J.B;
@@ -925,10 +935,8 @@ __global__ __launch_bounds__(256) void k_hist_scatter(HistWs ws) {
   __syncthreads();
   uint32_t *pf = ws.perm + J.perm_off + (uint64_t)f * J.n;
 #pragma unroll
-  for (int k = 0; k < kPer; ++k) {
-    const uint64_t s = s0 + threadIdx.x + (uint64_t)k * 256;
-    if (s < s1) pf[base[bn[k]] + rk[k]] = rows[k];
-  }
+  for (int k = 0; k < kPer; ++k)
+    if (ok[k]) pf[bucket_slot(base[bn[k]], rk[k])] = rows[k];
 }
 
 // Product of the ciphertexts of one item (chunk) per (item, slot), in

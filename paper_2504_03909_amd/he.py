@@ -52,7 +52,7 @@ _vp, _u32, _u64, _i32 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctype
 
 class HistJob(ctypes.Structure):
     _fields_ = [("sample_idx", _vp), ("n_samples", _u64), ("bins", _vp), ("bins_ld", _u64),
-                ("n_features", _u32), ("n_bins", _u32), ("hist", _vp)]
+                ("n_features", _u32), ("n_bins", _u32), ("hist", _vp), ("n_bad", _vp)]
 
 
 def _sig(name, res, args):
@@ -333,6 +333,7 @@ class Job:
     bins: torch.Tensor         # uint8 [F, ld]
     n_bins: int
     hist: Optional[torch.Tensor] = None  # int32 [F, B, 2, 2L], allocated if None
+    n_bad: Optional[torch.Tensor] = None  # int32 [1]: skipped (sample, feature) pairs are added here
 
     def as_c(self, key: Key) -> HistJob:
         F, ld = self.bins.shape
@@ -340,7 +341,8 @@ class Job:
             self.hist = torch.empty((F, self.n_bins, 2, 2 * key.limbs), dtype=torch.int32,
                                     device=self.bins.device)
         return HistJob(_ptr(self.sample_idx) if self.sample_idx.numel() else None,
-                       self.sample_idx.numel(), _ptr(self.bins), ld, F, self.n_bins, _ptr(self.hist))
+                       self.sample_idx.numel(), _ptr(self.bins), ld, F, self.n_bins, _ptr(self.hist),
+                       _ptr(self.n_bad))
 
 
 def hist_aggregate(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = HE_FORM_CANONICAL,

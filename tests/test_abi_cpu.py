@@ -67,6 +67,9 @@ def test_host_side_argument_errors(lib):
     h2 = ctypes.c_void_p()
     assert lib.he_ckks_create(9, 40, 1, ctypes.byref(h2)) == -1
     assert b"log_n" in lib.he_ckks_last_error()
+    for small in (10, 11):  # below the security bounds for Q of about 2^90
+        assert lib.he_ckks_create(small, 40, 1, ctypes.byref(h2)) == -1
+    assert lib.he_ckks_create(15, 40, 1, ctypes.byref(h2)) == -1
     assert lib.he_ckks_create(14, 70, 1, ctypes.byref(h2)) == -1
     lib.he_ckks_encrypt.argtypes = [ctypes.c_void_p] * 2 + [ctypes.c_uint64] * 3 + [ctypes.c_void_p] * 2
     assert lib.he_ckks_encrypt(None, None, 1, 0, 0, None, None) == -1
@@ -261,3 +264,146 @@ def test_key_constants_against_definitions(tmp_path, bits, seed):
     assert c["q2R_n2"] == q * q * (1 << (64 * L)) % n2
     assert c["qinv_p"] == pow(q, -1, p)
     assert c["qR_n"] == q * (1 << (32 * L)) % n
+
+
+# ------------------------------------------------- bucketing index logic
+# The count and scatter kernels' per-sample decisions (hist_bucket.hpp) run
+# here on the CPU, block by block as the kernels run them (blocks in a
+# shuffled order, ranks inside a block in a shuffled order, as the atomics
+# may hand them out), on buffers of exactly the sizes the library allocates
+# (every access to the node list, the bin table and the permutation goes
+# through new[]-allocated arrays under AddressSanitizer).  Rows past the
+# resident count and bins past the job's count appear in the input; the
+# harness checks that each run of the permutation holds exactly the valid
+# samples of its bin, that no block reads the base of a bin it did not
+# reserve, and reports the skipped count.
+BUCKET_HARNESS = r"""
+#include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <random>
+#include <vector>
+#include "hist_bucket.hpp"
+using namespace he;
+int main(int argc, char **argv) {
+  const uint64_t seed = std::strtoull(argv[1], nullptr, 10), n = std::strtoull(argv[2], nullptr, 10);
+  const uint64_t rows = std::strtoull(argv[3], nullptr, 10);
+  const uint32_t F = std::strtoul(argv[4], nullptr, 10), B = std::strtoul(argv[5], nullptr, 10);
+  const uint32_t block = std::strtoul(argv[6], nullptr, 10);
+  setvbuf(stdout, nullptr, _IONBF, 0);
+  std::mt19937_64 rng(seed);
+  uint32_t *idx = new uint32_t[n ? n : 1];
+  const uint64_t ld = rows;
+  uint8_t *bins = new uint8_t[F * ld ? F * ld : 1];
+  for (uint64_t s = 0; s < n; ++s)  // about 1 in 16 rows out of range
+    idx[s] = (uint32_t)(rng() % 16 == 0 ? rows + rng() % 1000 : (rows ? rng() % rows : rng() % 1000));
+  for (uint64_t i = 0; i < F * ld; ++i)  // about 1 in 8 bins out of range
+    bins[i] = (uint8_t)(rng() % 8 == 0 ? B + rng() % (256 - B + (B == 256)) : rng() % B);
+  const uint32_t nblk = (uint32_t)((n + block - 1) / block);
+  std::vector<uint32_t> counts(F * B, 0), offs(F * B), cursor(F * B);
+  uint64_t nbad = 0;
+  std::vector<uint64_t> order(F * (uint64_t)nblk);
+  for (uint64_t i = 0; i < order.size(); ++i) order[i] = i;
+  // count kernel
+  std::shuffle(order.begin(), order.end(), rng);
+  for (uint64_t local : order) {
+    uint32_t f; uint64_t s0, s1;
+    bucket_block(local, nblk, n, block, f, s0, s1);
+    if (f >= F || s1 > n || s0 > s1) { printf("block out of range\n"); return 2; }
+    std::vector<uint32_t> h(256, 0);
+    for (uint64_t s = s0; s < s1; ++s) {
+      uint32_t row, bin;
+      if (bucket_sample(idx, bins + f * ld, rows, B, s, row, bin)) h.at(bin)++; else ++nbad;
+    }
+    for (uint32_t b = 0; b < B; ++b) counts[f * B + b] += h[b];
+  }
+  // scan kernel
+  for (uint32_t f = 0; f < F; ++f) {
+    uint32_t acc = 0;
+    for (uint32_t b = 0; b < B; ++b) { offs[f * B + b] = cursor[f * B + b] = acc; acc += counts[f * B + b]; }
+  }
+  // scatter kernel
+  uint32_t *perm = new uint32_t[F * n ? F * n : 1];
+  std::vector<uint8_t> written(F * n, 0);
+  std::shuffle(order.begin(), order.end(), rng);
+  const uint32_t kPoison = 0xFFFFFFFFu;
+  for (uint64_t local : order) {
+    uint32_t f; uint64_t s0, s1;
+    bucket_block(local, nblk, n, block, f, s0, s1);
+    std::vector<uint64_t> ss;
+    for (uint64_t s = s0; s < s1; ++s) ss.push_back(s);
+    std::shuffle(ss.begin(), ss.end(), rng);  // atomics hand out ranks in any order
+    std::vector<uint32_t> h(256, 0), base(256, kPoison);
+    struct Item { uint32_t row, bin, rank; };
+    std::vector<Item> items;
+    for (uint64_t s : ss) {
+      uint32_t row, bin;
+      if (bucket_sample(idx, bins + f * ld, rows, B, s, row, bin)) items.push_back({row, bin, h.at(bin)++});
+    }
+    for (uint32_t b = 0; b < B; ++b)
+      if (h[b]) { base[b] = cursor[f * B + b]; cursor[f * B + b] += h[b]; }
+    uint32_t *pf = perm + (uint64_t)f * n;
+    for (const Item &it : items) {
+      if (base[it.bin] == kPoison) { printf("unreserved base read\n"); return 3; }
+      const uint64_t slot = bucket_slot(base[it.bin], it.rank);
+      if (slot >= offs[f * B + it.bin] + counts[f * B + it.bin]) { printf("slot past its run\n"); return 4; }
+      pf[slot] = it.row;
+      written[f * n + slot]++;
+    }
+  }
+  // every run holds exactly its bin's valid samples (as a multiset)
+  uint64_t valid = 0;
+  for (uint32_t f = 0; f < F; ++f) {
+    std::vector<std::vector<uint32_t>> want(B);
+    for (uint64_t s = 0; s < n; ++s) {
+      const uint32_t row = idx[s];
+      if (row < rows && bins[f * ld + row] < B) want[bins[f * ld + row]].push_back(row);
+    }
+    for (uint32_t b = 0; b < B; ++b) {
+      const uint32_t o = offs[f * B + b], c = counts[f * B + b];
+      if (c != want[b].size()) { printf("count mismatch\n"); return 5; }
+      std::vector<uint32_t> got(perm + (uint64_t)f * n + o, perm + (uint64_t)f * n + o + c);
+      for (uint32_t k = 0; k < c; ++k) if (written[f * n + o + k] != 1) { printf("slot not written once\n"); return 6; }
+      std::sort(got.begin(), got.end());
+      std::sort(want[b].begin(), want[b].end());
+      if (got != want[b]) { printf("run content mismatch\n"); return 7; }
+      valid += c;
+    }
+  }
+  printf("bad %llu valid %llu\n", (unsigned long long)nbad, (unsigned long long)valid);
+  delete[] idx; delete[] bins; delete[] perm;
+  return 0;
+}
+"""
+
+
+@pytest.fixture(scope="module")
+def bucket_harness(tmp_path_factory):
+    d = tmp_path_factory.mktemp("bucket")
+    src = d / "b.cpp"
+    src.write_text(BUCKET_HARNESS)
+    exe = d / "b"
+    r = subprocess.run(["g++", "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined",
+                        "-fno-sanitize-recover=all",
+                        f"-I{os.path.join(ROOT, 'paper_2504_03909_amd', 'csrc')}", str(src), "-o", str(exe)],
+                       capture_output=True, text=True)
+    assert r.returncode == 0, r.stderr
+    return str(exe)
+
+
+@pytest.mark.parametrize("seed,n,rows,F,B,block", [
+    (1, 10000, 3000, 3, 17, 4096),     # ragged last block, bins past 17 in the table
+    (2, 4096, 5000, 2, 256, 4096),     # exactly one block, every bin value valid except rows
+    (3, 1, 1, 1, 1, 4096),             # one sample, one row, one bin
+    (4, 0, 10, 2, 8, 4096),            # empty node
+    (5, 20000, 50, 4, 64, 256),        # many blocks, heavy duplicates
+    (6, 777, 0, 1, 16, 128),           # no resident rows: every sample skipped
+])
+def test_bucketing_index_logic_under_asan(bucket_harness, seed, n, rows, F, B, block):
+    r = subprocess.run([bucket_harness, str(seed), str(n), str(rows), str(F), str(B), str(block)],
+                       capture_output=True, text=True, env={**os.environ, "ASAN_OPTIONS": "detect_leaks=0"})
+    assert r.returncode == 0, r.stdout + r.stderr
+    bad, valid = (int(x) for x in r.stdout.split()[1::2])
+    assert bad + valid == F * n
+    if n and rows == 0:
+        assert valid == 0

@@ -71,7 +71,7 @@ def test_zero_length_calls(he):
     (h,) = he.hist_aggregate(k, ct8, [he.Job(torch.empty(0, dtype=torch.int32, device="cuda"),
                                              torch.zeros((2, 8), dtype=torch.uint8, device="cuda"), 5)])
     assert he.limbs_to_ints(host(h)) == [1] * (2 * 5 * 2)   # empty node: every bin is the ciphertext 1
-    ctx = ckks.Context(10, 40, 1)
+    ctx = ckks.Context(12, 40, 1)
     z = ctx.encode(torch.empty((0, 8), dtype=torch.float64, device="cuda"))
     assert z.shape[0] == 0
     torch.cuda.synchronize()
@@ -164,3 +164,53 @@ def test_encrypt_degenerate_r(he, bits, seed, public):
     got = he.limbs_to_ints(host(ct))
     want = [P.encrypt(sk.public, m, r) for m, r in zip(ms, rs)]
     assert got == want
+
+
+@pytest.mark.parametrize("form", [0, 1])
+def test_out_of_range_rows_and_bins_are_skipped_and_counted(he, form):
+    """Device data the library cannot trust: node rows at or past the resident
+    row count and bin values at or past n_bins.  Such (sample, feature) pairs
+    join no bin and are counted into the job's n_bad; every other bin equals
+    the oracle's aggregation of the valid pairs, bit for bit."""
+    import torch
+    say(f"out-of-range rows and bins form={form}")
+    sk, k = keys(1024, 1)
+    pk = sk.public
+    R, J, B, r_seed = 300, 3, 12, 77
+    s = W.streams(61)
+    g = W.gradients(R, s[1])
+    m = np.array([[P.encode(float(x)) for x in row] for row in g], dtype=np.int64)
+    bins = W.bins_uniform(J, R, B, s[2])
+    rng = np.random.default_rng(61)
+    bins[0, rng.choice(R, 20, replace=False)] = B          # first value past the range
+    bins[1, rng.choice(R, 9, replace=False)] = 255         # the largest byte
+    # rows: every resident row once, plus rows past the end (R, R + 1, a large
+    # value, the largest uint32)
+    bad_rows = np.array([R, R + 1, 1 << 30, (1 << 32) - 1], dtype=np.uint64)
+    idx = np.concatenate([np.arange(R, dtype=np.uint64), bad_rows])
+    rng.shuffle(idx)
+    idx32 = idx.astype(np.uint32).view(np.int32)
+    ct = he.encrypt(k, dev(m.reshape(-1)), seed=r_seed).view(R, 2, -1)
+    ctin = he.to_mont(k, ct) if form == 1 else ct
+    n_bad = torch.zeros(1, dtype=torch.int32, device="cuda")
+    job = he.Job(dev(idx32), dev(bins), B, n_bad=n_bad)
+    (hist,) = he.hist_aggregate(k, ctin, [job], form=form, chunk=16)
+    got = he.limbs_to_ints(host(hist))
+    want_bad = J * len(bad_rows) + 20 + 9
+    assert int(host(n_bad)[0]) == want_bad
+    cts = he.limbs_to_ints(host(ct))
+    rows_ct = [[cts[2 * i], cts[2 * i + 1]] for i in range(R)]
+    for f in range(J):
+        # the oracle's histogram of feature f over the pairs the library keeps
+        valid = [i for i in range(R) if bins[f][i] < B]
+        want = P.aggregate(pk, rows_ct, valid, bins[f:f + 1], 1, B)
+        assert [got[(f * B + b) * 2 + t] for b in range(B) for t in range(2)] == \
+            [want[0][b][t] for b in range(B) for t in range(2)], f
+    # and the decrypted histogram equals the plaintext sums of the valid pairs
+    dm = host(he.decrypt(k, hist)[0])
+    for f in range(J):
+        ok = bins[f] < B
+        for t in range(2):
+            ref = np.zeros(B, dtype=np.int64)
+            np.add.at(ref, bins[f][ok].astype(np.int64), m[ok, t])
+            assert np.array_equal(dm[f, :, t], ref)

@@ -50,6 +50,22 @@ def test_seeded_r_assembles_published_words():
     assert r1 == (low + (P.splitmix64_word(1234567, 5) << 128)) % n
 
 
+
+def test_prime_candidate_assembles_published_words():
+    # Candidate 0 of p (stream counter 0) at 128 bits takes two words, low
+    # word first: published outputs 0 and 1 of seed 1234567,
+    #   0x599ed017fb08fc85 (6457827717110365317) and
+    #   0x2c73f08458540fa5 (3203168211198807973);
+    # forcing bits 127, 126 and 0 turns the high word into 0xec73f08458540fa5
+    # (the low word is already odd).
+    assert P.prime_candidate(1234567, 0, 0, 128) == 0xEC73F08458540FA5_599ED017FB08FC85
+    # Candidate 1 starts two words later: outputs 2 and 3,
+    #   0x883ebce5a3f27c77 and 0x3fbef740e9177b3f -> high word 0xffbef740e9177b3f.
+    assert P.prime_candidate(1234567, 0, 1, 128) == 0xFFBEF740E9177B3F_883EBCE5A3F27C77
+    # A 64-bit candidate is one word: output 4, 0xe3b8346708cb5ecd, with
+    # bits 63, 62 and 0 forced -> 0xe3b8346708cb5ecd (all three already set).
+    assert P.prime_candidate(1234567, 0, 4, 64) == 0xE3B8346708CB5ECD
+
 # ---------------------------------------------------------- toy-key brute force
 TOY = P.PrivateKey(11, 13)
 

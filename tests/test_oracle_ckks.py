@@ -89,6 +89,43 @@ def test_samplers_moments():
     assert abs(e.mean()) < 0.05 and abs(e.var() - 10.5) < 0.3
 
 
+
+# Published SplitMix64 outputs 0..4 of seed 1234567 (tests/golden/splitmix64.txt).
+W1234567 = (0x599ED017FB08FC85, 0x2C73F08458540FA5, 0x883EBCE5A3F27C77, 0x3FBEF740E9177B3F,
+            0xE3B8346708CB5ECD)
+
+
+def test_samplers_assemble_published_words():
+    # ternary = word mod 3 - 1: the words are 0, 1, 0, 1, 2 mod 3.
+    assert C.ternary(1234567, 0, 5) == [-1, 0, -1, 0, 1]
+    assert C.ternary(1234567, 2, 3) == [-1, 0, 1]          # the counter base shifts the words
+    # centered binomial = popcount(bits 0..20) - popcount(bits 21..41):
+    #   word 0: 0x08fc85 (10 ones) - 0x00bfd8 (11) = -1
+    #   word 1: 0x140fa5 (10)      - 0x0422c2 (6)  =  4
+    #   word 2: 0x127c77 (13)      - 0x072d1f (12) =  1
+    #   word 3: 0x177b3f (16)      - 0x1a0748 (8)  =  8
+    #   word 4: 0x0b5ecd (13)      - 0x033846 (8)  =  5
+    assert C.cbd(1234567, 0, 5) == [-1, 4, 1, 8, 5]
+    assert C.cbd(1234567, 3, 2) == [8, 5]
+    # uniform mod q = word mod q, here q = 1073479681 (a 30-bit prime that is
+    # 1 mod 2^15)
+    assert C.uniform(1234567, 0, 5, 1073479681) == [977752849, 627650537, 407729945, 553364867, 106535843]
+    assert C.uniform(1234567, 1, 1, 1000003) == [W1234567[1] % 1000003]
+
+
+def test_encryption_randomness_counter_layout():
+    # Ciphertext t of a call takes u, e0, e1 from counters (offset + t) 3N +
+    # [0, N), [N, 2N), [2N, 3N).  With N = 1 the three come from single words:
+    # t = 0 -> words 0, 1, 2; t = 1 -> words 3, 4, 5.
+    p1 = C.Params(0, 30)
+    u, e0, e1 = C.enc_randomness(p1, 1234567, 0)
+    assert (u, e0, e1) == ([-1], [4], [1])
+    u, e0, _ = C.enc_randomness(p1, 1234567, 1)
+    assert (u, e0) == ([0], [5])
+    # N = 2, t = 0: u from words 0, 1; e0 from words 2, 3; e1 from word 4 onwards.
+    u, e0, e1 = C.enc_randomness(C.Params(1, 30), 1234567, 0)
+    assert u == [-1, 0] and e0 == [1, 8] and e1[0] == 5
+
 def test_decrypt_is_message_plus_exact_noise():
     p = C.Params(7, 20)
     keys = C.keygen(p, 5)

@@ -5,9 +5,15 @@ workload: fixed-point encoding of the 200,000 gradient values, encryption of
 all of them (seeded r, CRT path), the root node's encrypted histogram over
 32 features x 256 Zipf(1.1) bins, and CRT decryption of the 16,384 histogram
 ciphertexts.  Inputs (gradients, bins, sample list, key) are resident in HBM
-before timing starts.  Prints one JSON line.
+before timing starts.  Prints one JSON line, which also carries (after the
+timed steps) the 64-job batched comparison ("batched": one job per launch
+against graph replay of one persistent launch), the served request loop
+("served": a 2,000-request Poisson trace at 200 requests/s and a
+1,000-request trace at 0.8x the measured capacity, continuous batching
+against FIFO, p50/p99 latency) and the CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+                    [--no-batched] [--no-served]
 
 Other workloads (each prints its own JSON line; not the default):
     --workload tree      2048-bit, 1,000,000 samples, 64 x 256 Zipf bins, depth-6
@@ -40,11 +46,26 @@ KEY_SEED, R_SEED, DATA_SEED = 2, 2024, 1
 PEAK_MUL32_PER_S = 256 * 64 * 2.4e9
 MI355X_HBM_BPS = 8.0e12
 # HBM-side bytes of one encryption launch (k_enc_p1 + k_enc_p2 + k_enc_crt_b
-# over 200,000 ciphertexts), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes scaled
-# by a 256 MiB copy (profiles/enc_crt_2048_100k_counters.md).  Valid for the
-# kernel build those passes ran on; set to None when the encryption kernels
-# change until the passes are repeated.
-ENC_LAUNCH_TRAFFIC_BYTES = 5.6182e10
+# over 200,000 ciphertexts), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes
+# scaled by a 256 MiB copy (profiles/enc_crt_2048_100k_counters.md), and the
+# digest of the kernel sources those passes ran on (kernel_sources_digest()).
+# The figure is reported only while the sources still have that digest.
+ENC_LAUNCH_TRAFFIC = {"bytes": 5.6182e10, "sources_sha256_16": "none"}
+KERNEL_SOURCES = ("he_kernels.hip", "he_internal.hpp", "hist_bucket.hpp", "mont.hpp", "mont29.hpp",
+                  "radix29.hpp")
+
+
+def kernel_sources_digest() -> str:
+    """First 16 hex digits of the SHA-256 of the kernel sources and the build
+    flags they compile with."""
+    import hashlib
+    from paper_2504_03909_amd import build as B
+    h = hashlib.sha256()
+    for name in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2504_03909_amd", "csrc", name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
+    h.update(" ".join(B.COMMON).encode())
+    return h.hexdigest()[:16]
 
 
 def mm_products(s: int) -> int:
@@ -101,9 +122,26 @@ def percentile(xs, q):
     return xs[lo] + (xs[hi] - xs[lo]) * (k - lo)
 
 
-def cpu_baseline(p: int, q: int, grads, bins, budget_s: float = 15.0):
-    """The oracle (Python ints, textbook Paillier) on the host's cores, on a
-    bounded sample of the same workload, scaled to one full step."""
+def host_cpu():
+    """nproc and the CPU model of this host (Linux /proc/cpuinfo)."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return os.cpu_count(), model
+
+
+def cpu_baseline(p: int, q: int, grads, bins, n_enc: int = 2000, n_feat: int = 16, n_dec: int = 512):
+    """The oracle (Python ints, textbook Paillier: no CRT, no Montgomery) on
+    the host's cores, on a bounded sample of the same workload, scaled to one
+    full step: n_enc encryptions of seeded gradient values, the histograms
+    of n_feat of the 32 features over all 100,000 samples (every product of
+    those features), and n_dec decryptions of histogram ciphertexts."""
     import numpy as np
     import oracle.paillier as P
     from oracle import pool
@@ -111,40 +149,43 @@ def cpu_baseline(p: int, q: int, grads, bins, budget_s: float = 15.0):
     sk = P.PrivateKey(p, q)
     pk = sk.public
     cores = pool.workers()
+    nproc, model = host_cpu()
     flat = grads.reshape(-1)
     rng = np.random.default_rng(0)
-    # encryption sample: about budget/2 seconds of work on all cores
-    n_enc = cores * 24
     pick = rng.choice(flat.size, size=n_enc, replace=False)
     ms = [P.encode(float(flat[i])) for i in pick]
     rs = [P.seeded_r(pk.n, KEY_BITS, R_SEED, int(i)) for i in pick]
     t0 = time.perf_counter()
     cts = pool.encrypt_many(pk, ms, rs, processes=cores)
     t_enc = (time.perf_counter() - t0) / n_enc
-    # aggregation sample: `cores` features' histograms over 2,000 samples, in parallel
-    n_agg = 2000
-    ct_rows = [[cts[i % n_enc], cts[(i + 1) % n_enc]] for i in range(n_agg)]
+    # aggregation: n_feat whole features of the root node (M samples each,
+    # g and h), sample i carrying the sampled ciphertext pair i mod n_enc/2
+    rows = [(cts[2 * i], cts[2 * i + 1]) for i in range(n_enc // 2)]
     t0 = time.perf_counter()
-    pool.aggregate_many(pk, ct_rows, range(n_agg), [bins[f % J] for f in range(cores)], cores, K,
-                        processes=cores)
-    t_add = (time.perf_counter() - t0) / (n_agg * 2 * cores)
-    # decryption sample
-    n_dec = cores * 2
+    hists = pool.aggregate_features_cycled(pk, rows, M, [bins[f] for f in range(n_feat)], K, processes=cores)
+    t_agg = time.perf_counter() - t0
+    t_add = t_agg / (2 * M * n_feat)
+    # decryption of n_dec of the histogram ciphertexts just formed
+    hct = [c for h in hists for b in h for c in b][:n_dec]
     t0 = time.perf_counter()
-    pool.decrypt_many(sk, cts[:n_dec], processes=cores)
-    t_dec = (time.perf_counter() - t0) / n_dec
+    pool.decrypt_many(sk, hct, processes=cores)
+    t_dec = (time.perf_counter() - t0) / len(hct)
     step = t_enc * 2 * M + t_add * 2 * M * J + t_dec * J * K * 2
     return {
         "value": round(2 * M / step, 3),
         "unit": "encryptions/s (whole pass)",
         "cores": cores,
         "kind": "oracle",
-        "sample": (f"{n_enc} encryptions, {n_agg * 2 * cores} ciphertext products ({cores} features x "
-                   f"{n_agg} samples x g,h) and {n_dec} decryptions, each on {cores} processes; "
-                   f"extrapolated linearly to one pass of "
-                   f"{2 * M} encryptions + {2 * M * J} products + {J * K * 2} decryptions"),
+        "sample": (f"{n_enc} encryptions; the histograms of {n_feat} of the {J} features over all {M} samples "
+                   f"({2 * M * n_feat} ciphertext products); {len(hct)} decryptions; on {cores} processes, "
+                   f"extrapolated linearly to one pass of {2 * M} encryptions + {2 * M * J} products + "
+                   f"{J * K * 2} decryptions"),
+        "host": {"nproc": nproc, "cpu_model": model,
+                 "processes_note": f"pool capped at {pool.MAX_WORKERS} processes, the host CPU share of one GPU"},
         "step_s": round(step, 1),
         "per_op_s": {"encrypt": t_enc, "product": t_add, "decrypt": t_dec},
+        "stage_s": {"encrypt": round(t_enc * 2 * M, 1), "aggregate": round(t_add * 2 * M * J, 1),
+                    "decrypt": round(t_dec * J * K * 2, 1)},
     }
 
 
@@ -155,8 +196,12 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true", help="leave the 64-job batched comparison out of the line")
+    ap.add_argument("--no-served", action="store_true", help="leave the served request loop out of the line")
     ap.add_argument("--workload", default="pass", choices=("pass", "tree", "batched", "served", "horizontal"))
-    ap.add_argument("--requests", type=int, default=300)
+    ap.add_argument("--requests", type=int, default=2000, help="requests of the served trace at --rate")
+    ap.add_argument("--capacity-requests", type=int, default=1000,
+                    help="requests of the served trace at 0.8x the measured capacity")
     ap.add_argument("--rate", type=float, default=200.0)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
@@ -289,6 +334,8 @@ def main():
     torch.cuda.synchronize()
     probe_rate = n_probe / (pr_marks[0].elapsed_time(pr_marks[1]) / 1e3)
 
+    digest = kernel_sources_digest()
+    traffic_current = digest == ENC_LAUNCH_TRAFFIC["sources_sha256_16"]
     enc_products = crt_encrypt_products(p, q, L)
     achieved = 2 * M * enc_products / (avg["encrypt"] / 1e3)
     line = {
@@ -336,7 +383,9 @@ def main():
             "peak": round(PEAK_MUL32_PER_S / 1e12, 3),
             "unit": "T mul32/s",
             "frac": round(achieved / PEAK_MUL32_PER_S, 4),
-            "traffic": ENC_LAUNCH_TRAFFIC_BYTES,
+            "traffic": (ENC_LAUNCH_TRAFFIC["bytes"] if traffic_current else None),
+            "traffic_sources_sha256_16": {"measured_on": ENC_LAUNCH_TRAFFIC["sources_sha256_16"],
+                                          "this_build": digest},
             "probe_measured": round(probe_rate / 1e12, 3),
             "frac_of_probe": round(achieved / probe_rate, 4),
             "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
@@ -356,7 +405,16 @@ def main():
             "equals_encrypt": obf_same,
         },
     }
+    del ct, hist, job
+    torch.cuda.empty_cache()
+    if not args.no_batched:
+        print("[bench] batched: 64 uneven node jobs", file=sys.stderr, flush=True)
+        line["batched"] = bench_batched(args, compact=True)
+    if not args.no_served:
+        print(f"[bench] served: {args.requests} requests at {args.rate:g}/s", file=sys.stderr, flush=True)
+        line["served"] = bench_served(args, compact=True)
     if not args.no_cpu_baseline:
+        print("[bench] cpu baseline (oracle on the host cores)", file=sys.stderr, flush=True)
         line["cpu_baseline"] = cpu_baseline(p, q, grads_h, bins_h)
     print(json.dumps(line), flush=True)
 
@@ -463,9 +521,11 @@ def bench_tree(args):
     }
 
 
-def bench_batched(args):
+def bench_batched(args, compact=False):
     """64 uneven tree-node jobs (|S| log-uniform in [1e3, 2e5], F in [8, 128],
-    B in {16, 64, 256}) over 200,000 resident 2048-bit encrypted samples."""
+    B in {16, 64, 256}) over 200,000 resident 2048-bit encrypted samples:
+    one launch per job against one batched persistent launch (autotuned
+    shape) replayed from a captured graph."""
     import numpy as np
     import torch
     from paper_2504_03909_amd import he
@@ -497,10 +557,24 @@ def bench_batched(args):
     _, t_graph = _timed(lambda: plan.launch())
     same = all(torch.equal(a.hist, b.hist) and torch.equal(a.hist, c.hist) for a, b, c in zip(ja, jb, jc))
     # work counters at the tuned shape: products joining real partials vs executed
-    _, cnt = he.hist_aggregate_counted(key, ctm, jobs(), form=he.HE_FORM_MONT, chunk=chunk, split=split)
-    mm_real, mm_done, mm_conv = (int(x) for x in cnt.cpu().tolist())
     L = key.limbs
     prod = contrib * (2 * (2 * L) ** 2 + 2 * L)
+    if compact:
+        return {
+            "workload": "64 node jobs, |S| log-uniform [1e3, 2e5], F uniform [8, 128], B in {16, 64, 256}, "
+                        "200000 resident samples, 2048-bit key",
+            "contributions": contrib,
+            "one_job_per_launch_ms": round(t_single * 1e3, 3),
+            "graph_replay_ms": round(t_graph * 1e3, 3),
+            "speedup_over_one_job_per_launch": round(t_single / t_graph, 3),
+            "sample_adds_per_s": {"one_job_per_launch": round(contrib / t_single, 1),
+                                  "graph_replay": round(contrib / t_graph, 1)},
+            "alu_frac_graph_replay": round(prod / t_graph / PEAK_MUL32_PER_S, 4),
+            "autotuned": {"chunk": chunk, "split": split, "ms": round(tune_ms, 3)},
+            "results_identical": bool(same),
+        }
+    _, cnt = he.hist_aggregate_counted(key, ctm, jobs(), form=he.HE_FORM_MONT, chunk=chunk, split=split)
+    mm_real, mm_done, mm_conv = (int(x) for x in cnt.cpu().tolist())
     return {
         "metric": "encrypted hist sample-adds/s at 2048-bit key",
         "workload": "64 node jobs, |S| log-uniform [1e3, 2e5], F uniform [8, 128], B in {16, 64, 256}, "
@@ -586,7 +660,7 @@ def bench_horizontal(args):
     }
 
 
-def bench_served(args):
+def bench_served(args, compact=False):
     """Request loop: Poisson arrivals of encrypt (1k-100k samples),
     aggregate (one depth-6 tree node, F in [8, 128]) and decrypt (up to
     64 x 256 x 2 ciphertexts) requests from 4 passive parties; 90% under a
@@ -604,27 +678,40 @@ def bench_served(args):
     budget = 64 << 30
     share = {"k2048": 0.9, "k1024": 0.1}
 
+    # one backend per policy for every run (the library keeps one workspace
+    # per stream)
+    backends = {"continuous": serve.backend_for(setups, n_streams=4, enc_slice=16384),
+                "fifo": serve.backend_for(setups, n_streams=1)}
+
     def run(rate, n, policy, seed):
         tr = serve.build_trace(np.random.default_rng(seed), n, rate, setups, share)
-        be = (serve.backend_for(setups, n_streams=4, enc_slice=16384) if policy == "continuous"
-              else serve.backend_for(setups, n_streams=1))
-        st = serve.Server(be, budget, max_inflight=8, policy=policy).run(tr, time_limit=900)
+        st = serve.Server(backends[policy], budget, max_inflight=8, policy=policy).run(tr, time_limit=900)
         print(f"[bench] served rate={rate:g} n={n} {policy}: {st['makespan_s']} s, p99 {st['p99_ms']} ms",
               file=sys.stderr, flush=True)
         return st
 
-    run(1000.0, 16, "continuous", 99)  # warm-up: workspaces and kernels
+    def brief(st):
+        keep = ("requests", "completed", "makespan_s", "throughput_req_s", "p50_ms", "p99_ms", "launches")
+        out = {k: st[k] for k in keep if k in st}
+        out["by_kind_p99_ms"] = {k: v["p99_ms"] for k, v in st.get("by_kind", {}).items()}
+        return out
+
+    run(1000.0, 16, "continuous", 99)  # warm-up: kernels and first allocations
     out = {"metric": "p50/p99 request latency and throughput, 2048-bit (90%) + 1024-bit (10%) keys",
-           "workload": f"{args.requests} requests, Poisson arrivals, mix encrypt/aggregate/decrypt 10/45/45, "
-                       "4 passive parties, depth-6 trees over resident encrypted gradients, HBM budget 64 GiB"}
+           "workload": f"Poisson arrivals, mix encrypt/aggregate/decrypt 10/45/45, 4 passive parties, "
+                       "depth-6 trees over 200000 (2048-bit) and 50000 (1024-bit) resident encrypted "
+                       "gradients, F up to 128, HBM budget 64 GiB; continuous batching (4 streams) against "
+                       "FIFO one request per launch on the same trace"}
     cont = run(args.rate, args.requests, "continuous", 1)
     fifo = run(args.rate, args.requests, "fifo", 1)
-    out[f"rate_{args.rate:g}"] = {"continuous": cont, "fifo": fifo}
+    f = brief if compact else (lambda x: x)
+    out[f"rate_{args.rate:g}"] = {"requests": args.requests, "continuous": f(cont), "fifo": f(fifo)}
     cap = cont["throughput_req_s"]
     r2 = round(0.8 * cap, 2)
-    n2 = max(50, int(min(args.requests, r2 * 20)))
-    out[f"rate_{r2:g}_(0.8x_capacity)"] = {"continuous": run(r2, n2, "continuous", 2),
-                                            "fifo": run(r2, n2, "fifo", 2)}
+    n2 = args.capacity_requests
+    out["capacity_req_s"] = cap
+    out[f"rate_{r2:g}_(0.8x_capacity)"] = {"requests": n2, "continuous": f(run(r2, n2, "continuous", 2)),
+                                            "fifo": f(run(r2, n2, "fifo", 2))}
     return out
 
 

@@ -11,8 +11,11 @@ resident encrypted gradients of the current round:
 
 The loop runs on one host thread against wall-clock time.  Requests that have
 arrived wait in a FIFO queue; a request is admitted when its estimated device
-memory footprint fits in the free part of the HBM budget and an in-flight
-slot is free.  Every loop turn groups what was admitted into launches -- all
+memory footprint fits in the free part of the HBM budget (the configured
+budget, capped by the device memory that is free when the server starts) and
+an in-flight slot is free.  Before the clock starts, the backend runs the
+largest launch of each kind the trace can form on every stream, so the
+library's per-stream workspaces never grow (and never wait) mid-trace.  Every loop turn groups what was admitted into launches -- all
 admitted aggregate jobs of one key become one batched persistent launch, all
 admitted decryptions of one key one launch over their concatenated
 ciphertexts, each encryption its own launch -- and puts each launch on the
@@ -89,7 +92,10 @@ class Server:
         if policy not in ("continuous", "fifo"):
             raise ValueError(policy)
         self.backend = backend
-        self.budget = int(hbm_budget)
+        # the budget never exceeds what the device can still give (a backend
+        # that knows its device reports that)
+        dev = backend.device_budget() if hasattr(backend, "device_budget") else None
+        self.budget = int(hbm_budget) if dev is None else min(int(hbm_budget), int(dev))
         self.max_inflight = 1 if policy == "fifo" else max_inflight
         self.policy = policy
         self.clock = clock
@@ -180,6 +186,10 @@ class Server:
         for r in reqs:
             r.bytes = int(self.backend.footprint(r))
             r.status = "new"
+        if hasattr(self.backend, "prepare"):
+            # before the clock starts: size whatever per-stream state the
+            # largest launches of this trace need, so none grows mid-trace
+            self.backend.prepare(reqs, self.max_inflight)
         t0 = self.clock()
         nxt = 0
         remaining = len(reqs)
@@ -265,6 +275,55 @@ class GpuBackend(Backend):
         # other streams can run between them; 0 = one launch
         self.enc_slice = enc_slice
 
+    def device_budget(self, reserve: int = 2 << 30) -> int:
+        """Free device memory now, less a reserve for the allocator."""
+        free, _ = self.torch.cuda.mem_get_info()
+        return max(0, int(free) - reserve)
+
+    def prepare(self, reqs: Sequence[Request], max_group: int) -> None:
+        """Runs, on every stream, the largest launch of each kind and key the
+        trace can form (the largest encryption slice; the `max_group` largest
+        decryptions, resp. aggregations, of one key merged into one launch),
+        so the library's per-stream workspaces reach their final size before
+        serving starts and never grow (a growth waits for the stream)."""
+        torch, he = self.torch, self.he
+        plans = []
+        for kid in sorted({r.key_id for r in reqs}):
+            mine = [r for r in reqs if r.key_id == kid]
+            enc = [r for r in mine if r.kind == "encrypt"]
+            if enc:
+                n = max(r.payload["m"].numel() for r in enc)
+                plans.append(("encrypt", kid, min(n, self.enc_slice or n)))
+            dec = sorted((r.payload["ct"].numel() // (2 * self.keys[kid].limbs) for r in mine
+                          if r.kind == "decrypt"), reverse=True)[:max_group]
+            if dec:
+                plans.append(("decrypt", kid, sum(dec)))
+            agg = sorted((r for r in mine if r.kind == "aggregate"), key=lambda r: r.bytes,
+                         reverse=True)[:max_group]
+            if agg:
+                plans.append(("aggregate", kid, agg))
+        for st in self.streams:
+            with torch.cuda.stream(st):
+                for kind, kid, arg in plans:
+                    key = self.keys[kid]
+                    if kind == "encrypt":
+                        m = torch.zeros(arg, dtype=torch.int64, device="cuda")
+                        he.encrypt(key, m, seed=1, stream=st)
+                    elif kind == "decrypt":
+                        pool = self.pools[kid]
+                        flat = pool.ct.view(-1, 2 * key.limbs)
+                        reps = -(-arg // flat.shape[0])
+                        ct = flat if reps == 1 else flat.repeat(reps, 1)
+                        he.decrypt(key, ct[:arg].contiguous(), stream=st)
+                    else:
+                        jobs = []
+                        for r in arg:
+                            table, B = self.bins[(kid, r.party)]
+                            jobs += [he.Job(idx, table[:F], B) for (idx, F) in r.payload["jobs"]]
+                        he.hist_aggregate(key, self.pools[kid].ctm, jobs, form=he.HE_FORM_MONT,
+                                          chunk=self.chunk, stream=st)
+        torch.cuda.synchronize()
+
     # Footprint estimates mirror the buffers each launch allocates (outputs
     # plus library workspace).
     def footprint(self, req: Request) -> int:
@@ -346,7 +405,9 @@ def build_trace(rng, n_requests: int, rate: float, setups: Dict[str, Dict[str, A
     key: "m" (int64 [rows*2] encoded gradients), "ct" (int32 [rows, 2, 2L]),
     "nodes" (list of int32 device tensors: the tree's node sample lists),
     "parties" (number of passive parties with bins for this key), "f_max".
-    Request payloads are views of that state (nothing is copied)."""
+    Request payloads are views of that state (nothing is copied); encrypt
+    and decrypt payloads also name the flat index of their first value
+    ("first") in the setup's gradient / ciphertext arrays."""
     import numpy as np
     from synth.workloads import poisson_arrivals
     times = poisson_arrivals(n_requests, rate, rng)
@@ -365,7 +426,8 @@ def build_trace(rng, n_requests: int, rate: float, setups: Dict[str, Dict[str, A
             n = min(n, rows)
             off = int(rng.integers(0, rows - n + 1))
             req = Request(i, "encrypt", kid, float(t), payload={
-                "m": st["m"][2 * off:2 * (off + n)], "seed": int(rng.integers(1, 2 ** 62)), "offset": 0})
+                "m": st["m"][2 * off:2 * (off + n)], "seed": int(rng.integers(1, 2 ** 62)), "offset": 0,
+                "first": 2 * off})
         elif u < mix[0] + mix[1]:
             node = st["nodes"][int(rng.integers(len(st["nodes"])))]
             F = int(rng.integers(feature_range[0], min(feature_range[1], st["f_max"]) + 1))
@@ -375,7 +437,7 @@ def build_trace(rng, n_requests: int, rate: float, setups: Dict[str, Dict[str, A
             n = int(rng.integers(1, min(max_decrypt, 2 * rows) + 1))
             flat = st["ct"].view(-1, st["ct"].shape[-1])
             off = int(rng.integers(0, flat.shape[0] - n + 1))
-            req = Request(i, "decrypt", kid, float(t), payload={"ct": flat[off:off + n]})
+            req = Request(i, "decrypt", kid, float(t), payload={"ct": flat[off:off + n], "first": off})
         out.append(req)
     return out
 
@@ -402,18 +464,23 @@ def make_setup(key, rows: int, depth: int, n_parties: int, f_max: int, rng, r_se
     import torch
     from synth import workloads as W
     from . import pipeline
-    grads = torch.from_numpy(W.gradients(rows, rng)).cuda()
+    grads_h = W.gradients(rows, rng)
+    grads = torch.from_numpy(grads_h).cuda()
     res = pipeline.encrypt_gradients(key, grads, r_seed)
     m = pipeline.he.encode(grads.reshape(-1).contiguous())
     levels = W.tree_levels(rows, depth, rng)
     nodes = [torch.from_numpy(n.view("int32")).cuda() for lvl in levels for n in lvl]
-    bins = {}
+    bins, bins_h = {}, {}
     for p in range(n_parties):
         B = int(rng.choice(list(bin_choices)))
-        bins[p] = (torch.from_numpy(W.bins_zipf(f_max, rows, B, rng)).cuda(), B)
+        bins_h[p] = W.bins_zipf(f_max, rows, B, rng)
+        bins[p] = (torch.from_numpy(bins_h[p]).cuda(), B)
     torch.cuda.synchronize()
     return {"key": key, "pool": res, "m": m, "ct": res.ct, "nodes": nodes, "bins": bins,
-            "parties": n_parties, "f_max": f_max}
+            "parties": n_parties, "f_max": f_max,
+            # host copies of the inputs, for checking results
+            "grads_h": grads_h, "bins_h": bins_h, "r_seed": r_seed,
+            "nodes_h": [n for lvl in levels for n in lvl]}
 
 
 def backend_for(setups: Dict[str, Dict[str, Any]], n_streams: int = 4, chunk: int = 0,

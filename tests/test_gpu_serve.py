@@ -1,37 +1,131 @@
-"""GPU test of the serving loop: requests under two keys (2048 and 1024 bit)
+"""GPU tests of the serving loop: requests under two keys (2048 and 1024 bit)
 from several parties arrive faster than they are served, are admitted by
-memory footprint and batched into overlapping launches on several streams;
-every request's result is bit-identical to the result of the same request
-run alone."""
+memory footprint and batched into overlapping launches on several streams.
+
+Every served result is checked twice: against the same request run alone
+(bit for bit), and against the CPU oracle on the host copies of the inputs --
+each decryption against the oracle's encoding of the gradients it decrypts,
+sampled ciphertexts of each encryption against the oracle's encryption with
+the request's seeded r, and each aggregation's decrypted histogram against
+plaintext sums of the oracle's encoding plus two of its ciphertexts against
+the closed form E(sum m; prod r) computed by the oracle."""
+import functools
 import sys
 
 import numpy as np
 import pytest
 
 import oracle.paillier as P
+from oracle import pool
 
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_alone():
-    import torch
-    from paper_2504_03909_amd import he, serve
-    print("[gpu-case] serve mix vs alone", flush=True)
+def say(msg):
+    print(f"[gpu-case] {msg}", flush=True)
     sys.stdout.flush()
-    rng = np.random.default_rng(11)
-    k2 = he.Key.from_primes(2048, *P.keygen(2048, 2))
-    k1 = he.Key.from_primes(1024, *P.keygen(1024, 1))
-    setups = {"k2048": serve.make_setup(k2, 6000, 4, 4, 24, rng, 5),
-              "k1024": serve.make_setup(k1, 3000, 3, 4, 16, rng, 6)}
-    trace = serve.build_trace(rng, 48, 2000.0, setups, {"k2048": 0.9, "k1024": 0.1},
-                              enc_range=(100, 4000), max_decrypt=3000, feature_range=(4, 24))
-    backend = serve.backend_for(setups, n_streams=4, enc_slice=1000)
-    srv = serve.Server(backend, hbm_budget=2 << 30, max_inflight=6)
+
+
+@functools.lru_cache(maxsize=None)
+def oracle_primes(bits, seed):
+    return P.keygen(bits, seed)
+
+
+def encoded(grads_h):
+    """The oracle's encoding of every gradient value of a setup, flat [2 rows]."""
+    return np.array([P.encode(float(x)) for x in grads_h.reshape(-1)], dtype=np.int64)
+
+
+def check_against_oracle(setups, trace, keys_h, rng, enc_samples=2, slot_cap=1500):
+    """Checks every request of a served trace against the oracle (see the
+    module docstring).  Returns per-kind check counts."""
+    import torch
+    from paper_2504_03909_amd import he
+    n_checked = {"encrypt": 0, "aggregate": 0, "decrypt": 0, "closed_form": 0}
+    enc_jobs, enc_want_at = [], []
+    m_all = {kid: encoded(st["grads_h"]) for kid, st in setups.items()}
+    for r in trace:
+        st = setups[r.key_id]
+        bits = st["key"].bits
+        pk = P.PublicKey(keys_h[r.key_id][0] * keys_h[r.key_id][1])
+        m_or = m_all[r.key_id]
+        if r.kind == "decrypt":
+            first, n = r.payload["first"], r.result.numel()
+            got = r.result.cpu().numpy()
+            assert np.array_equal(got, m_or[first:first + n]), (r.rid, "decrypt")
+            n_checked["decrypt"] += 1
+        elif r.kind == "encrypt":
+            first, seed = r.payload["first"], r.payload["seed"]
+            n = r.result.shape[0]
+            picks = sorted({0, n - 1, *rng.integers(0, n, size=max(0, enc_samples - 2)).tolist()})
+            rows = he.limbs_to_ints(r.result[picks].cpu().numpy())
+            for i, c in zip(picks, rows):
+                enc_jobs.append((int(m_or[first + i]), P.seeded_r(pk.n, bits, seed, r.payload["offset"] + i)))
+                enc_want_at.append((r.rid, pk, c))
+            n_checked["encrypt"] += 1
+        else:
+            table, B = st["bins"][r.party]
+            bins_h = st["bins_h"][r.party]
+            (node, F), = r.payload["jobs"]
+            (hist,) = r.result
+            node_h = node.cpu().numpy().view(np.uint32).astype(np.int64)
+            # decrypted sums == plaintext sums of the oracle's encoding
+            dm, _, ovf = he.decrypt(st["key"], hist)
+            dm = dm.cpu().numpy().reshape(F, B, 2)
+            assert int(ovf.item()) == 0
+            for t in range(2):
+                w = m_or[2 * node_h + t].astype(np.float64)   # |sum| < 2^53: exact in binary64
+                keyidx = (np.arange(F)[:, None] * B + bins_h[:F][:, node_h].astype(np.int64)).reshape(-1)
+                ref = np.bincount(keyidx, weights=np.tile(w, F), minlength=F * B).astype(np.int64)
+                assert np.array_equal(dm[:, :, t].reshape(-1), ref), (r.rid, "aggregate sums", t)
+            # two ciphertexts in closed form: the smallest non-empty bin of a
+            # random feature and a random non-empty bin capped in size
+            hh = hist.cpu().numpy()
+            for pick in range(2):
+                f = int(rng.integers(F))
+                counts = np.bincount(bins_h[f][node_h], minlength=B)
+                nz = np.nonzero(counts)[0]
+                if pick == 0:
+                    b = int(nz[np.argmin(counts[nz])])
+                else:
+                    small = nz[counts[nz] <= slot_cap]
+                    if small.size == 0:
+                        continue
+                    b = int(rng.choice(small))
+                t = int(rng.integers(2))
+                members = node_h[bins_h[f][node_h] == b]
+                rp = 1
+                for i in members:
+                    rp = rp * P.seeded_r(pk.n, bits, st["r_seed"], 2 * int(i) + t) % pk.n
+                enc_jobs.append((int(m_or[2 * members + t].sum()), rp))
+                enc_want_at.append((r.rid, pk, he.limbs_to_ints(hh[f, b, t][None])[0]))
+                n_checked["closed_form"] += 1
+            n_checked["aggregate"] += 1
+    # the oracle's encryptions, grouped by key, on the host's cores
+    by_key = {}
+    for (m, rr), (rid, pk, got) in zip(enc_jobs, enc_want_at):
+        by_key.setdefault(pk.n, []).append((m, rr, rid, got))
+    for n, items in by_key.items():
+        want = pool.encrypt_many(P.PublicKey(n), [x[0] for x in items], [x[1] for x in items])
+        for (m, rr, rid, got), w in zip(items, want):
+            assert got == w, (rid, "ciphertext vs oracle")
+    torch.cuda.synchronize()
+    return n_checked
+
+
+def served(setups, trace, n_streams=4, enc_slice=0, max_inflight=6, budget=2 << 30):
+    import torch
+    from paper_2504_03909_amd import serve
+    backend = serve.backend_for(setups, n_streams=n_streams, enc_slice=enc_slice)
+    srv = serve.Server(backend, hbm_budget=budget, max_inflight=max_inflight)
     stats = srv.run(trace, time_limit=300)
     torch.cuda.synchronize()
-    assert stats["completed"] == len(trace)
-    assert stats["launches"] < len(trace)            # some launches carried several requests
-    assert {r.key_id for r in trace} == {"k2048", "k1024"}
+    return stats
+
+
+def check_alone(setups, trace):
+    import torch
+    from paper_2504_03909_amd import serve
     alone_backend = serve.backend_for(setups, n_streams=1)
     for r in trace:
         solo = serve.run_alone(alone_backend, serve.clone_request(r))
@@ -42,11 +136,53 @@ def test_served_results_equal_alone():
                 assert torch.equal(a, b), r.rid
         else:
             assert torch.equal(solo, r.result), (r.rid, r.kind)
-    # one decrypt result against the oracle: it decrypts resident ciphertexts
-    # of known plaintexts (the encoded gradients)
-    d = next(r for r in trace if r.kind == "decrypt")
-    st = setups[d.key_id]
-    flat_ct = st["ct"].view(-1, st["ct"].shape[-1])
-    start = (d.payload["ct"].data_ptr() - flat_ct.data_ptr()) // (4 * flat_ct.shape[-1])
-    mh = st["m"].cpu().numpy()
-    assert d.result.cpu().numpy().tolist() == mh[start:start + d.result.numel()].tolist()
+
+
+def test_served_results_equal_alone_and_oracle():
+    """Small setups: 48 requests, every result checked alone and against the oracle."""
+    from paper_2504_03909_amd import he, serve
+    say("serve mix: small setups, alone + oracle")
+    rng = np.random.default_rng(11)
+    keys_h = {"k2048": oracle_primes(2048, 2), "k1024": oracle_primes(1024, 1)}
+    k2 = he.Key.from_primes(2048, *keys_h["k2048"])
+    k1 = he.Key.from_primes(1024, *keys_h["k1024"])
+    setups = {"k2048": serve.make_setup(k2, 6000, 4, 4, 24, rng, 5),
+              "k1024": serve.make_setup(k1, 3000, 3, 4, 16, rng, 6)}
+    trace = serve.build_trace(rng, 48, 2000.0, setups, {"k2048": 0.9, "k1024": 0.1},
+                              enc_range=(100, 4000), max_decrypt=3000, feature_range=(4, 24))
+    stats = served(setups, trace, enc_slice=1000)
+    assert stats["completed"] == len(trace)
+    assert stats["launches"] < len(trace)            # some launches carried several requests
+    assert {r.key_id for r in trace} == {"k2048", "k1024"}
+    check_alone(setups, trace)
+    n = check_against_oracle(setups, trace, keys_h, np.random.default_rng(1))
+    assert n["decrypt"] + n["encrypt"] + n["aggregate"] == len(trace)
+    assert min(n["decrypt"], n["encrypt"], n["aggregate"]) > 0
+
+
+def test_served_c5_scale_oracle():
+    """Setups at the served workload's scale: 200,000 resident rows under the
+    2048-bit key and 50,000 under the 1024-bit key, depth-6 trees, 4 passive
+    parties with up to 128 features and 16/64/256 Zipf bins, encryptions of
+    1k-100k samples, decryptions of up to 64 x 256 x 2 ciphertexts; Poisson
+    arrivals at 200 requests/s.  Every result is checked against the oracle."""
+    from paper_2504_03909_amd import he, serve
+    say("serve mix: C5-scale setups, oracle")
+    rng = np.random.default_rng(5)
+    keys_h = {"k2048": oracle_primes(2048, 2), "k1024": oracle_primes(1024, 1)}
+    k2 = he.Key.from_primes(2048, *keys_h["k2048"])
+    k1 = he.Key.from_primes(1024, *keys_h["k1024"])
+    setups = {"k2048": serve.make_setup(k2, 200_000, 6, 4, 128, rng, 11),
+              "k1024": serve.make_setup(k1, 50_000, 6, 4, 64, rng, 12)}
+    say("setups ready")
+    trace = serve.build_trace(np.random.default_rng(1), 64, 200.0, setups, {"k2048": 0.9, "k1024": 0.1})
+    stats = served(setups, trace, enc_slice=16384, max_inflight=8, budget=64 << 30)
+    say(f"served: {stats['makespan_s']} s, p99 {stats['p99_ms']} ms")
+    assert stats["completed"] == len(trace)
+    assert max(r.payload["ct"].shape[0] for r in trace if r.kind == "decrypt") > 4096
+    assert max(r.payload["jobs"][0][1] for r in trace if r.kind == "aggregate") > 64
+    n = check_against_oracle(setups, trace, keys_h, np.random.default_rng(2))
+    say(f"oracle checks: {n}")
+    assert n["decrypt"] + n["encrypt"] + n["aggregate"] == len(trace)
+    assert min(n["decrypt"], n["encrypt"], n["aggregate"]) > 0
+    assert n["closed_form"] >= n["aggregate"]

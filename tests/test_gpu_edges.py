@@ -184,10 +184,13 @@ def test_out_of_range_rows_and_bins_are_skipped_and_counted(he, form):
     rng = np.random.default_rng(61)
     bins[0, rng.choice(R, 20, replace=False)] = B          # first value past the range
     bins[1, rng.choice(R, 9, replace=False)] = 255         # the largest byte
-    # rows: every resident row once, plus rows past the end (R, R + 1, a large
-    # value, the largest uint32)
+    # rows: every resident row but four, and in their place rows past the end
+    # (R, R + 1, a large value, the largest uint32); the node keeps n_samples
+    # <= rows, which the host checks
     bad_rows = np.array([R, R + 1, 1 << 30, (1 << 32) - 1], dtype=np.uint64)
-    idx = np.concatenate([np.arange(R, dtype=np.uint64), bad_rows])
+    dropped = rng.choice(R, len(bad_rows), replace=False)
+    kept = np.setdiff1d(np.arange(R, dtype=np.uint64), dropped.astype(np.uint64))
+    idx = np.concatenate([kept, bad_rows])
     rng.shuffle(idx)
     idx32 = idx.astype(np.uint32).view(np.int32)
     ct = he.encrypt(k, dev(m.reshape(-1)), seed=r_seed).view(R, 2, -1)
@@ -196,20 +199,22 @@ def test_out_of_range_rows_and_bins_are_skipped_and_counted(he, form):
     job = he.Job(dev(idx32), dev(bins), B, n_bad=n_bad)
     (hist,) = he.hist_aggregate(k, ctin, [job], form=form, chunk=16)
     got = he.limbs_to_ints(host(hist))
-    want_bad = J * len(bad_rows) + 20 + 9
+    keep = np.zeros(R, dtype=bool)
+    keep[kept.astype(np.int64)] = True
+    want_bad = J * len(bad_rows) + int(np.sum(keep & (bins[0] >= B))) + int(np.sum(keep & (bins[1] >= B)))
     assert int(host(n_bad)[0]) == want_bad
     cts = he.limbs_to_ints(host(ct))
     rows_ct = [[cts[2 * i], cts[2 * i + 1]] for i in range(R)]
     for f in range(J):
         # the oracle's histogram of feature f over the pairs the library keeps
-        valid = [i for i in range(R) if bins[f][i] < B]
+        valid = [int(i) for i in kept if bins[f][i] < B]
         want = P.aggregate(pk, rows_ct, valid, bins[f:f + 1], 1, B)
         assert [got[(f * B + b) * 2 + t] for b in range(B) for t in range(2)] == \
             [want[0][b][t] for b in range(B) for t in range(2)], f
     # and the decrypted histogram equals the plaintext sums of the valid pairs
     dm = host(he.decrypt(k, hist)[0])
     for f in range(J):
-        ok = bins[f] < B
+        ok = (bins[f] < B) & keep
         for t in range(2):
             ref = np.zeros(B, dtype=np.int64)
             np.add.at(ref, bins[f][ok].astype(np.int64), m[ok, t])

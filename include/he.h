@@ -301,6 +301,22 @@ int he_split_find(const int64_t *hist, const int64_t *minus, uint32_t nodes, uin
 int he_decrypt(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m,
                uint32_t *raw, uint32_t *n_overflow, hipStream_t stream);
 
+/* Decryption that allocates nothing, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc).  Same arguments, results and errors as he_decrypt,
+ * bit for bit; the kernels are he_decrypt's.  Its working memory is one
+ * 64 MiB array in the library's device image, one copy per device, held
+ * until the process ends: count must not exceed 2^23 / L ciphertexts
+ * (131,072 at 2048-bit keys, 262,144 at 1024-bit), else HE_ERR_ARG before
+ * any device work; the exponentiation launch is cut to the blocks whose
+ * window tables fit beside the count's m_p, m_q, so large calls run on
+ * part of the device.  Nothing in the array needs to start at zero.  Every
+ * call on a device shares that device's array: calls that overlap on one
+ * device (other streams, other threads) race and must be serialised by the
+ * caller. */
+int he_decrypt_noalloc(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m,
+                       uint32_t *raw, uint32_t *n_overflow, hipStream_t stream);
+
 /* Ciphertext packing for cheaper decryption.  The holder of encrypted
  * histograms (public key only) folds `slots` consecutive ciphertexts into
  * one: packed = prod_j c_j^(2^(64 j)) (1 + K n) mod n^2 with

@@ -400,6 +400,73 @@ int he_decrypt(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m
   return HE_OK;
 }
 
+}  // extern "C"
+
+// ------------------------------------------------- allocation-free decryption
+// Scratch of he_decrypt_noalloc: the per-ciphertext half-plaintexts m_p, m_q
+// (L words per ciphertext, at most half of the array) followed by the
+// exponentiation window tables of the persistent launch, whose grid is cut
+// to what the rest of the array holds.  One copy per device, held until the
+// process ends; in host code `scratch` only names the symbol, its device
+// address comes from hipGetSymbolAddress.
+namespace {
+constexpr size_t kNoAllocBytes = size_t(64) << 20;
+constexpr int kNoAllocDevices = 64;
+}  // namespace
+static __device__ __align__(256) uint8_t scratch[kNoAllocBytes];
+namespace {
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kNoAllocDevices] = {};
+
+// Device address of this device's copy of `scratch` (looked up once per device).
+int scratch_address(void **out) {
+  int dev = 0;
+  HE_TRY_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= kNoAllocDevices)
+    return fail(HE_ERR_DEVICE, "device index " + std::to_string(dev) + " beyond the allocation-free path's table");
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void *p = nullptr;
+    HE_TRY_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(HE_ERR_DEVICE, "hipGetSymbolAddress returned a null address for the scratch array");
+    g_scratch_ptr[dev] = p;
+  }
+  *out = g_scratch_ptr[dev];
+  return HE_OK;
+}
+}  // namespace
+
+extern "C" {
+
+int he_decrypt_noalloc(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m, uint32_t *raw,
+                       uint32_t *n_overflow, hipStream_t stream) {
+  if (!key) return fail(HE_ERR_ARG, "null key");
+  if (!key->priv) return fail(HE_ERR_NOPRIV, "decryption needs p and q");
+  if (count == 0) return HE_OK;
+  if (!ct || !m) return fail(HE_ERR_ARG, "null ct or m");
+  const int KP = kp_of(key);
+  const size_t L = key->n_bits / 32;
+  const uint64_t max_count = (kNoAllocBytes / 2) / (L * sizeof(uint32_t));
+  if (count > max_count)
+    return fail(HE_ERR_ARG, "he_decrypt_noalloc: count " + std::to_string(count) + " exceeds the maximum of " +
+                                std::to_string(max_count) + " ciphertexts at " + std::to_string(key->n_bits) +
+                                "-bit keys (fixed scratch of " + std::to_string(kNoAllocBytes >> 20) + " MiB)");
+  void *base = nullptr;
+  int rc = scratch_address(&base);
+  if (rc) return rc;
+  const size_t mpq_bytes = (count * L * sizeof(uint32_t) + 255) / 256 * 256;
+  const int G = he::pick_group(KP, 2, count);
+  const uint64_t per_wave = 64 / G;
+  const uint64_t fit = (kNoAllocBytes - mpq_bytes) / he::table_bytes_per_block(KP, 2, G);
+  if (fit == 0) return fail(HE_ERR_ARG, "he_decrypt_noalloc: no room for one block's window tables");
+  const uint32_t grid = (uint32_t)std::min<uint64_t>(
+      fit, persistent_grid(KP, 2, (2 * ((count + per_wave - 1) / per_wave) + 3) / 4, G));
+  uint32_t *mpq = (uint32_t *)base;
+  uint32_t *tab = (uint32_t *)((char *)base + mpq_bytes);
+  HE_TRY_HIP(he::launch_dec(KP, key->dk, ct, count, mpq, m, raw, n_overflow, tab, grid, G, stream));
+  return HE_OK;
+}
+
 uint32_t he_pack_slots(const he_key *key, uint64_t count) {
   if (!key) return 0;
   return he::pack_slots((int)key->n_bits, count);

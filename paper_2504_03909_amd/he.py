@@ -29,6 +29,7 @@ EXPORTED = (
     "he_hist_autotune", "he_hist_plan_create", "he_hist_plan_launch", "he_hist_plan_free",
     "he_obfuscators", "he_encrypt_obfuscated", "he_hist_subtract", "he_split_find",
     "he_hist_aggregate_counted", "he_ct_mul", "he_pack_slots", "he_pack", "he_decrypt_packed",
+    "he_decrypt_noalloc",
 )
 
 
@@ -86,6 +87,7 @@ _hist_counted = _sig("he_hist_aggregate_counted", _i32, [_vp, _vp, _u64, _i32, c
                                                          _u32, _u32, _vp, _vp])
 _hist = _sig("he_hist_aggregate_ex", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32, _u32, _vp])
 _decrypt = _sig("he_decrypt", _i32, [_vp, _vp, _u64, _vp, _vp, _vp, _vp])
+_decrypt_noalloc = _sig("he_decrypt_noalloc", _i32, [_vp, _vp, _u64, _vp, _vp, _vp, _vp])
 _probe = _sig("he_probe_int_mul", _i32, [_u64, _u32, ctypes.POINTER(_u64), _vp])
 _last_error = _sig("he_last_error", ctypes.c_char_p, [])
 _autotune = _sig("he_hist_autotune", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32,
@@ -422,6 +424,20 @@ def decrypt(key: Key, ct: torch.Tensor, raw: bool = False, out: Optional[torch.T
     ovf = torch.zeros(1, dtype=torch.int32, device=ct.device)
     _check(_decrypt(key.handle, _ptr(ct.contiguous()), count, _ptr(m), _ptr(rw), _ptr(ovf), _stream(stream)))
     return m, rw, ovf
+
+
+def decrypt_noalloc(key: Key, ct: torch.Tensor, m: torch.Tensor, raw: Optional[torch.Tensor] = None,
+                    n_overflow: Optional[torch.Tensor] = None, stream=None) -> None:
+    """he_decrypt into caller-provided outputs through the library's fixed
+    device scratch (no device allocation by the library): m int64 [count],
+    raw int32 [count, L] or None, n_overflow int32 [1] or None (not cleared)."""
+    count = ct.numel() // (2 * key.limbs)
+    assert ct.is_contiguous() and m.dtype == torch.int64 and m.is_contiguous() and m.numel() == count
+    if raw is not None:
+        assert raw.dtype == torch.int32 and raw.is_contiguous() and raw.numel() == count * key.limbs
+    if n_overflow is not None:
+        assert n_overflow.dtype == torch.int32 and n_overflow.numel() >= 1
+    _check(_decrypt_noalloc(key.handle, _ptr(ct), count, _ptr(m), _ptr(raw), _ptr(n_overflow), _stream(stream)))
 
 
 def pack_slots(key: Key, count: int) -> int:

@@ -73,14 +73,22 @@ def mm_products(s: int) -> int:
     return 2 * s * s + s
 
 
+def sq_products(s: int) -> int:
+    """32x32->64 products of one s-limb Montgomery squaring: the s (s + 1) / 2
+    distinct products a_i a_j of the square plus the s^2 + s of the reduction."""
+    return s * (s + 1) // 2 + s * s + s
+
+
 def nwin(e: int) -> int:
     return max(1, -(-e.bit_length() // 5))
 
 
-def modexp_mm(e: int) -> int:
-    """Montgomery products of one 5-bit fixed-window exponentiation:
-    30 for the table, 6 per window after the first."""
-    return 30 + 6 * (nwin(e) - 1)
+def modexp_products(e: int, s: int) -> int:
+    """Products of one 5-bit fixed-window exponentiation mod an s-limb
+    modulus: 30 general products for the table, then per window after the
+    first 5 squarings and one general product."""
+    w = nwin(e) - 1
+    return (30 + w) * mm_products(s) + 5 * w * sq_products(s)
 
 
 def crt_encrypt_products(p: int, q: int, L: int) -> int:
@@ -88,9 +96,10 @@ def crt_encrypt_products(p: int, q: int, L: int) -> int:
     sp = L // 2
     tot = 0
     for P, Q in ((p, q), (q, p)):
-        mm_p = 3 + modexp_mm(Q % (P - 1)) + 2      # r reduction, exponentiation, from_mont, m Q
-        mm_p2 = 1 + modexp_mm(P) + 2                # to_mont, lift, (1 + m n), product
-        tot += mm_p * mm_products(sp) + mm_p2 * mm_products(2 * sp)
+        # mod P: r reduction (3), exponentiation, from_mont, m Q (2)
+        tot += (3 + 2) * mm_products(sp) + modexp_products(Q % (P - 1), sp)
+        # mod P^2: to_mont, lift, (1 + m n), product
+        tot += (1 + 2) * mm_products(2 * sp) + modexp_products(P, 2 * sp)
     return tot
 
 
@@ -101,7 +110,7 @@ def crt_decrypt_products(p: int, q: int, L: int) -> int:
     for P in (p, q):
         # c mod P^2 (2 MM + add), exponentiation, from_mont, exact division
         # (low-half product), m_P = k h_P
-        tot += (2 + modexp_mm(P - 1) + 1) * mm_products(2 * sp) + sp * sp + mm_products(sp)
+        tot += (2 + 1) * mm_products(2 * sp) + modexp_products(P - 1, 2 * sp) + sp * sp + mm_products(sp)
     return tot + 4 * mm_products(sp) + mm_products(L)
 
 

@@ -105,9 +105,11 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p1(DKey key, uint64_t 
                                                            uint32_t *__restrict__ tabs) {
   constexpr int SP = 16 * KP, L = 32 * KP;
   constexpr int K1 = SP / G;  // limbs per lane mod P
-  constexpr int S29 = he29::limbs_for_group(SP, G), ROW = S29 > SP ? S29 : SP;
+  constexpr int S29 = he29::limbs_for_group(SP, G), ROW = 2 * S29 > SP ? 2 * S29 : SP;
   constexpr int NG = 64 / G, GB = kBlockThreads / G;
-  __shared__ __align__(16) uint32_t lds_all[GB * ROW];
+  __shared__ __align__(16) uint32_t lds_all[GB * ROW + S29];
+  uint32_t *const zeros = lds_all + GB * ROW;
+  zero_lds(zeros, S29);
   const uint32_t g = (threadIdx.x & 63u) / G;
   uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
@@ -141,7 +143,7 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p1(DKey key, uint64_t 
       add_mod<K1, G>(x, x, t, Mp);
     }
     // t = r^(Q mod (P-1)) mod P, canonical
-    pow29<K1, G>(x, P.e_enc.e, P.e_enc.nwin, tab, P.P, lds);
+    pow29<K1, G>(x, P.e_enc.e, P.e_enc.nwin, tab, P.P, lds, zeros);
     if (valid) st<K1, G>(tq + (i * 2 + which) * SP, x);
   }
 }
@@ -153,9 +155,11 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p2(DKey key, const int
                                                            uint32_t *__restrict__ cpq, uint32_t *__restrict__ tabs) {
   constexpr int SP = 16 * KP, SP2 = 32 * KP;
   constexpr int K1 = SP / G, K2 = SP2 / G;  // limbs per lane mod P and mod P^2
-  constexpr int S29 = he29::limbs_for_group(SP2, G), ROW = S29 > SP2 ? S29 : SP2;
+  constexpr int S29 = he29::limbs_for_group(SP2, G), ROW = 2 * S29 > SP2 ? 2 * S29 : SP2;
   constexpr int NG = 64 / G, GB = kBlockThreads / G;
-  __shared__ __align__(16) uint32_t lds_all[GB * ROW];
+  __shared__ __align__(16) uint32_t lds_all[GB * ROW + S29];
+  uint32_t *const zeros = lds_all + GB * ROW;
+  zero_lds(zeros, S29);
   const uint32_t g = (threadIdx.x & 63u) / G;
   uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
@@ -172,7 +176,7 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p2(DKey key, const int
     // omega = t^P mod P^2, canonical
     uint32_t w[K2];
     ld_part<K2, G>(w, tq + (i * 2 + which) * SP, SP);
-    pow29<K2, G>(w, P.e_lift.e, P.e_lift.nwin, tab, P.P2, lds);
+    pow29<K2, G>(w, P.e_lift.e, P.e_lift.nwin, tab, P.P2, lds, zeros);
     const Mod<K2> M2 = load_mod<K2, G>(P.P2.N, P.P2.ninv);
     uint32_t f[K2];
     {
@@ -236,8 +240,10 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
     DKey key, const int64_t *__restrict__ m, uint64_t count, const uint32_t *__restrict__ r,
     uint64_t seed, uint64_t roff, uint32_t *__restrict__ ct, uint32_t *__restrict__ tabs) {
   constexpr int KN2 = 4 * KP, SN2 = 64 * KP, L = 32 * KP;
-  constexpr int S29 = he29::limbs_for_group(SN2, 16), ROW = S29 > SN2 ? S29 : SN2;
-  __shared__ __align__(16) uint32_t lds_all[16 * ROW];
+  constexpr int S29 = he29::limbs_for_group(SN2, 16), ROW = 2 * S29 > SN2 ? 2 * S29 : SN2;
+  __shared__ __align__(16) uint32_t lds_all[16 * ROW + S29];
+  uint32_t *const zeros = lds_all + 16 * ROW;
+  zero_lds(zeros, S29);
   const uint32_t g = group_in_wave();
   uint32_t *lds = lds_all + (wave_in_block() * 4 + g) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
@@ -261,7 +267,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
     mont_mul<KN2>(x, x, c, M, lds);
     set_small(c, 1u);
     mont_mul<KN2>(x, x, c, M, lds);
-    pow29<KN2, 16>(x, key.e_n.e, key.e_n.nwin, tab, key.n2, lds);
+    pow29<KN2, 16>(x, key.e_n.e, key.e_n.nwin, tab, key.n2, lds, zeros);
     // f = 1 + (m mod n) n, exact (< n^2), in Montgomery form
     ld_part<KN2>(c, key.n.N, L);
     signed_mod<KN2>(f, m ? m[i] : 0, c);
@@ -547,9 +553,11 @@ template <int KP>
 __global__ __launch_bounds__(kBlockThreads) void k_pack(DKey key, const uint32_t *__restrict__ ct, uint64_t count,
                                                        uint32_t slots, uint32_t *__restrict__ packed) {
   constexpr int KN2 = 4 * KP, SN2 = 64 * KP;
-  constexpr int S29 = he29::limbs_for_group(SN2, 16), K = S29 / 16, ROW = S29 > SN2 ? S29 : SN2;
+  constexpr int S29 = he29::limbs_for_group(SN2, 16), K = S29 / 16, ROW = 2 * S29 > SN2 ? 2 * S29 : SN2;
   constexpr int v = he29::variant(16);
-  __shared__ __align__(16) uint32_t lds_all[16 * ROW];
+  __shared__ __align__(16) uint32_t lds_all[16 * ROW + S29];
+  uint32_t *const zeros = lds_all + 16 * ROW;
+  zero_lds(zeros, S29);
   const uint32_t gi = wave_in_block() * 4 + group_in_wave();
   uint32_t *lds = lds_all + gi * ROW;
   const uint64_t n_packed = (count + slots - 1) / slots;
@@ -577,7 +585,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_pack(DKey key, const uint32_t
 #pragma unroll 1
   for (uint32_t j = slots - 1; j-- > 0;) {
 #pragma unroll 1
-    for (int t = 0; t < 64; ++t) mm29<K, 16>(acc, acc, acc, M, lds);
+    for (int t = 0; t < 64; ++t) sq29<K, 16>(acc, acc, M, lds, zeros);
     uint32_t y[K];
     slot_mont(y, j, j < my_slots);
     mm29<K, 16>(acc, y, acc, M, lds);
@@ -664,8 +672,10 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_dec_a(DKey key, const uint
                                                         uint32_t *__restrict__ tabs) {
   constexpr int SP = 16 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
   constexpr int K1 = SP / G, K2 = SP2 / G, NG = 64 / G, GB = kBlockThreads / G;
-  constexpr int S29 = he29::limbs_for_group(SP2, G), ROW = S29 > SP2 ? S29 : SP2;
-  __shared__ __align__(16) uint32_t lds_all[GB * ROW];
+  constexpr int S29 = he29::limbs_for_group(SP2, G), ROW = 2 * S29 > SP2 ? 2 * S29 : SP2;
+  __shared__ __align__(16) uint32_t lds_all[GB * ROW + S29];
+  uint32_t *const zeros = lds_all + GB * ROW;
+  zero_lds(zeros, S29);
   const uint32_t g = (threadIdx.x & 63u) / G;
   uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
@@ -691,7 +701,7 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_dec_a(DKey key, const uint
       ld<K2, G>(c, P.P2.R2);
       mont_mul<K2, G>(y, y, c, M2, lds);
       add_mod<K2, G>(x, x, y, M2);
-      pow29<K2, G>(x, P.e_dec.e, P.e_dec.nwin, tab, P.P2, lds);  // canonical, = 1 mod P
+      pow29<K2, G>(x, P.e_dec.e, P.e_dec.nwin, tab, P.P2, lds, zeros);  // canonical, = 1 mod P
       set_small<K2, G>(c, 1u);
       sub_plain<K2, G>(x, x, c);          // x - 1 = k P
       relayout<K2, K1, G>(lo, x, lds);

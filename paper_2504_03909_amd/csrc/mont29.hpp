@@ -30,6 +30,8 @@
 #include "mont.hpp"
 #include "radix29.hpp"
 
+#include <type_traits>
+
 namespace he {
 
 constexpr uint32_t kMask29 = (1u << he29::kBits) - 1u;
@@ -195,6 +197,143 @@ __device__ __forceinline__ void mm29_lds(uint32_t (&t)[K], const uint32_t *a_lds
   t[1] += (uint32_t)(s0 >> he29::kBits);
 }
 
+// Squaring.  The products a_i a_j of a square pair up (a_i a_j = a_j a_i),
+// and the pair's doubled product 2 a_i a_j can join its column (i + j) in
+// either of its two steps: at step i it is the multiply-add of position j,
+// at step j that of position i, and both positions hold column i + j then.
+// Each step keeps about half of its positions, the same local indices in
+// every lane so that the kept multiply-adds are ordinary lane-uniform
+// instructions: for local indices x = i mod K and y = j mod K with x != y,
+// step i keeps position j when y - x mod K lies in [1, K/2) (for even K
+// also when it equals K/2 and x < K/2); this is a tournament on the K local
+// indices, so exactly one of the pair's two steps keeps it.  Positions with
+// y = x (the square a_i^2 and the pairs of limbs at the same local index of
+// different lanes) are kept at every step with a per-lane multiplier: 2 a_i
+// in the lanes above the step's own lane (j > i), a_i in its own lane
+// (j = i) and 0 below (those pairs were taken at step j < i).  A column is
+// complete when its reduction step comes, since both steps of each of its
+// pairs are at most its index.  A kept doubled product is below 2^59 (1 +
+// 2^-20), so a column still stays below 2^64 for K <= 21.
+//
+// The multipliers come from LDS: the group's row holds a (S29 words) and
+// right after it 2a; the per-lane multiplier of the diagonal position is
+// read from the 2a row, the a row or a block-shared row of zeros, chosen
+// per lane once for every K steps, so a step costs no extra VALU work.
+template <int K>
+__host__ __device__ constexpr bool sq_keeps(int x, int y) {
+  const int d = ((y - x) % K + K) % K;
+  return K % 2 ? (d >= 1 && d <= (K - 1) / 2) : ((d >= 1 && d < K / 2) || (d == K / 2 && x < K / 2));
+}
+
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
+// One squaring step for multiplier limb a_i (i mod K = X): a2 = 2 a_i for the
+// kept pair positions, ad = this lane's multiplier at local index X.
+template <int K, int G, int X>
+__device__ __forceinline__ void sqstep29(uint64_t (&C)[K], uint32_t &top, uint32_t a2, uint32_t ad,
+                                         const uint32_t (&b)[K], const Mod29<K> &M) {
+  static_assert(K >= 2 && K <= 21, "column bound of the squaring needs 2 <= K <= 21");
+  static_for<0, K>([&](auto jc) {
+    constexpr int j = decltype(jc)::value;
+    const uint64_t base = j == K - 1 ? (uint64_t)top : C[j];
+    if constexpr (j == X)
+      C[j] = base + (uint64_t)ad * b[j];
+    else if constexpr (sq_keeps<K>(X, j))
+      C[j] = base + (uint64_t)a2 * b[j];
+    else
+      C[j] = base;
+  });
+  const uint32_t q = bcast_first_m29<G>(mul_lo32((uint32_t)C[0], M.ninv), M.mask);
+#pragma unroll
+  for (int j = 0; j < K; ++j) C[j] += (uint64_t)q * M.n[j];
+  top = rotate_next_m29<G>((uint32_t)C[0], M.mask);
+  C[1] += C[0] >> he29::kBits;
+#pragma unroll
+  for (int j = 0; j + 1 < K; ++j) C[j] = C[j + 1];
+#pragma unroll
+  for (int j = 0; j + 1 < K; ++j) asm("" : "+v"(C[j]));
+  asm("" : "+v"(top));
+}
+
+// t = a^2 R'^-1 mod N (settled, below 2N) with a (settled, below 2N) in
+// registers (b), in this group's LDS row (lds[0, S29)) and doubled right
+// after it (lds[S29, 2 S29)); `zeros`: S29 zero words in the same LDS array
+// as the row.  t may alias b.
+template <int K, int G>
+__device__ __forceinline__ void sq29_lds(uint32_t (&t)[K], const uint32_t *lds, const uint32_t (&b)[K],
+                                         const uint32_t *zeros, const Mod29<K> &M) {
+  constexpr int S = G * K;
+  constexpr int U = K % 2 == 0 ? K : 2 * K;  // steps per loop iteration, a multiple of K
+  static_assert(S % U == 0, "unroll must divide the limb count");
+  const int gl = (int)glane<G>();
+  const uint32_t *row2 = lds + S;
+  const int zoff = (int)(zeros - lds);  // same LDS array: an integer offset keeps the loads in LDS
+  uint64_t C[K];
+  uint32_t top = 0;
+#pragma unroll
+  for (int j = 0; j + 1 < K; ++j) C[j] = 0;
+#pragma unroll 1
+  for (int i0 = 0; i0 < S; i0 += U) {
+    uint2 v2, vd;
+    const uint32_t *dsel = nullptr;
+    static_for<0, U>([&](auto sc) {
+      constexpr int s = decltype(sc)::value;
+      if constexpr (s % K == 0) {
+        const int ls = i0 / K + s / K;  // lane holding limbs i0 + s .. i0 + s + K - 1
+        dsel = lds + (gl > ls ? S : (gl == ls ? 0 : zoff));
+      }
+      if constexpr (s % 2 == 0) v2 = *reinterpret_cast<const uint2 *>(row2 + i0 + s);
+      // the diagonal multipliers two at a time while both steps share a lane
+      // block (even K), else one at a time
+      if constexpr (K % 2 == 0 && s % 2 == 0) vd = *reinterpret_cast<const uint2 *>(dsel + i0 + s);
+      if constexpr (K % 2 != 0) vd.x = dsel[i0 + s];
+      const uint32_t ad = K % 2 != 0 || s % 2 == 0 ? vd.x : vd.y;
+      sqstep29<K, G, s % K>(C, top, s % 2 == 0 ? v2.x : v2.y, ad, b, M);
+    });
+  }
+  C[K - 1] = top;
+  uint64_t c = 0;
+#pragma unroll
+  for (int j = 0; j < K; ++j) {
+    const uint64_t s = C[j] + c;
+    t[j] = (uint32_t)s & kMask29;
+    c = s >> he29::kBits;
+  }
+  const uint32_t cl = from_prev<G>((uint32_t)c), ch = from_prev<G>((uint32_t)(c >> 32));
+  const uint64_t s0 = (uint64_t)t[0] + (((uint64_t)ch << 32) | cl);
+  t[0] = (uint32_t)s0 & kMask29;
+  t[1] += (uint32_t)(s0 >> he29::kBits);
+}
+
+// Fills the block-shared zero words the squaring reads (n words); every
+// thread of the block must call it before any leaves.
+__device__ __forceinline__ void zero_lds(uint32_t *z, int n) {
+  for (int t = threadIdx.x; t < n; t += blockDim.x) z[t] = 0u;
+  __syncthreads();
+}
+
+// t = a^2 R'^-1 mod N, a in registers; `lds`: this group's row of at least
+// 2 S29 words; `zeros`: S29 zero words in the row's LDS array.  t may alias a.
+template <int K, int G>
+__device__ __forceinline__ void sq29(uint32_t (&t)[K], const uint32_t (&a)[K], const Mod29<K> &M, uint32_t *lds,
+                                     const uint32_t *zeros) {
+  constexpr int S = G * K;
+  uint32_t d[K];
+#pragma unroll
+  for (int j = 0; j < K; ++j) d[j] = a[j] << 1;
+  st29<K, G>(lds, a);
+  st29<K, G>(lds + S, d);
+  __builtin_amdgcn_wave_barrier();
+  sq29_lds<K, G>(t, lds, a, zeros, M);
+  __builtin_amdgcn_wave_barrier();
+}
+
 // t = a b R'^-1 mod N, both operands in registers; `lds` is this group's row
 // (at least S29 words).  t may alias a or b.
 template <int K, int G>
@@ -305,10 +444,11 @@ __device__ __forceinline__ void to32(uint32_t (&x)[K32], const uint32_t (&t)[K],
 // for every window, zero digits included, so the sequence of operations does
 // not depend on the exponent.  `tab`: this group's table, kTable entries of
 // S29 words in global memory; `lds`: this group's row of at least
-// max(G K32, S29) words.
+// max(G K32, 2 S29) words; `zeros`: S29 zero words in the row's LDS array
+// (see sq29).
 template <int K32, int G>
 __device__ __forceinline__ void pow29(uint32_t (&x)[K32], const uint32_t *e, int nwin, uint32_t *tab,
-                                      const DMod &D, uint32_t *lds) {
+                                      const DMod &D, uint32_t *lds, const uint32_t *zeros) {
   constexpr int S29 = he29::limbs_for_group(G * K32, G);
   constexpr int K = S29 / G;
   constexpr int v = he29::variant(G);
@@ -335,7 +475,7 @@ __device__ __forceinline__ void pow29(uint32_t (&x)[K32], const uint32_t *e, int
 #pragma unroll 1
   for (int w = nwin - 2; w >= 0; --w) {
 #pragma unroll 1
-    for (int s = 0; s < kWindow; ++s) mm29<K, G>(cur, cur, cur, M, lds);
+    for (int s = 0; s < kWindow; ++s) sq29<K, G>(cur, cur, M, lds, zeros);
     mm29_mem<K, G>(cur, tab + exp_digit(e, w) * S29, cur, M, lds);
   }
   // leave the Montgomery domain: cur R'^-1 (a product with 1, at most N)

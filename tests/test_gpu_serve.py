@@ -148,7 +148,9 @@ def test_served_results_equal_alone_and_oracle():
     k1 = he.Key.from_primes(1024, *keys_h["k1024"])
     setups = {"k2048": serve.make_setup(k2, 6000, 4, 4, 24, rng, 5),
               "k1024": serve.make_setup(k1, 3000, 3, 4, 16, rng, 6)}
-    trace = serve.build_trace(rng, 48, 2000.0, setups, {"k2048": 0.9, "k1024": 0.1},
+    # arrivals far faster than the device serves them, so that requests wait
+    # together and launches carry several of them whatever the kernels' speed
+    trace = serve.build_trace(rng, 48, 100000.0, setups, {"k2048": 0.9, "k1024": 0.1},
                               enc_range=(100, 4000), max_decrypt=3000, feature_range=(4, 24))
     stats = served(setups, trace, enc_slice=1000)
     assert stats["completed"] == len(trace)

@@ -83,6 +83,18 @@ int he_key_import(uint32_t n_bits, const uint32_t *p, const uint32_t *q, he_key 
  * requested from a public key. */
 int he_key_export(const he_key *key, uint32_t *n, uint32_t *p, uint32_t *q);
 
+/* Side-channel hardening of the private-key exponentiations (the CRT
+ * encryption's r^(q mod (p-1)) mod p and x^p mod p^2, and decryption's
+ * c^(p-1) mod p^2, whose exponents are secret; Sec. III-B: only the active
+ * party holds p and q).  Their sequence of operations never depends on the
+ * exponent.  With on != 0 the window-table reads do not either: every window
+ * reads all 32 table entries and keeps the one its digit names by a mask, so
+ * the device addresses touched are a function of the sizes only.  Off (the
+ * default) each window reads the one entry it needs.  Results are identical
+ * bit for bit.  Applies to calls enqueued after it returns; must not run
+ * concurrently with other calls on the same key.  HE_ERR_ARG for a null key. */
+int he_key_set_constant_time(he_key *key, int on);
+
 /* Number of bits of n, and whether the key holds p and q (1) or not (0). */
 uint32_t he_key_bits(const he_key *key);
 int he_key_has_private(const he_key *key);

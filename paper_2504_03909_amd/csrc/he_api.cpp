@@ -277,6 +277,12 @@ int he_key_export(const he_key *key, uint32_t *n, uint32_t *p, uint32_t *q) {
   return HE_OK;
 }
 
+int he_key_set_constant_time(he_key *key, int on) {
+  if (!key) return fail(HE_ERR_ARG, "null key");
+  key->dk.ct = on ? 1 : 0;
+  return HE_OK;
+}
+
 uint32_t he_key_bits(const he_key *key) { return key ? key->n_bits : 0; }
 int he_key_has_private(const he_key *key) { return key && key->priv ? 1 : 0; }
 

@@ -50,6 +50,7 @@ struct DKey {
   const uint32_t *q2R_n2;  // q^2 R'' mod n^2
   const uint32_t *qinv_p;  // q^-1 mod p (canonical)
   const uint32_t *qR_n;    // q R_n mod n
+  int ct;                  // private-key exponentiations read their window tables in full (secret digits)
 };
 
 // Histogram job as the kernels see it (host fills offsets).

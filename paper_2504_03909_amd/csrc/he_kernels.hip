@@ -97,8 +97,8 @@ __global__ void k_encode(const double *__restrict__ x, uint64_t count, uint32_t 
 // unit = (prime, 64/G consecutive ciphertexts) so that the exponent is the
 // same for the whole wave.
 
-// A1: t[i][P] (S_P limbs, canonical).
-template <int KP, int G>
+// A1: t[i][P] (S_P limbs, canonical).  CT: constant-time window tables.
+template <int KP, int G, bool CT = false>
 __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p1(DKey key, uint64_t count,
                                                            const uint32_t *__restrict__ r, uint64_t seed,
                                                            uint64_t roff, uint32_t *__restrict__ tq,
@@ -143,13 +143,13 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p1(DKey key, uint64_t 
       add_mod<K1, G>(x, x, t, Mp);
     }
     // t = r^(Q mod (P-1)) mod P, canonical
-    pow29<K1, G>(x, P.e_enc.e, P.e_enc.nwin, tab, P.P, lds, zeros);
+    pow29<K1, G>(x, P.e_enc.e, P.e_enc.nwin, tab, P.P, lds, zeros, CT);
     if (valid) st<K1, G>(tq + (i * 2 + which) * SP, x);
   }
 }
 
 // A2: cpq[i][P] (S_P2 limbs, canonical) from t.
-template <int KP, int G>
+template <int KP, int G, bool CT = false>
 __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p2(DKey key, const int64_t *__restrict__ m,
                                                            uint64_t count, const uint32_t *__restrict__ tq,
                                                            uint32_t *__restrict__ cpq, uint32_t *__restrict__ tabs) {
@@ -176,7 +176,7 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p2(DKey key, const int
     // omega = t^P mod P^2, canonical
     uint32_t w[K2];
     ld_part<K2, G>(w, tq + (i * 2 + which) * SP, SP);
-    pow29<K2, G>(w, P.e_lift.e, P.e_lift.nwin, tab, P.P2, lds, zeros);
+    pow29<K2, G>(w, P.e_lift.e, P.e_lift.nwin, tab, P.P2, lds, zeros, CT);
     const Mod<K2> M2 = load_mod<K2, G>(P.P2.N, P.P2.ninv);
     uint32_t f[K2];
     {
@@ -267,7 +267,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
     mont_mul<KN2>(x, x, c, M, lds);
     set_small(c, 1u);
     mont_mul<KN2>(x, x, c, M, lds);
-    pow29<KN2, 16>(x, key.e_n.e, key.e_n.nwin, tab, key.n2, lds, zeros);
+    pow29<KN2, 16>(x, key.e_n.e, key.e_n.nwin, tab, key.n2, lds, zeros, false);  // public exponent
     // f = 1 + (m mod n) n, exact (< n^2), in Montgomery form
     ld_part<KN2>(c, key.n.N, L);
     signed_mod<KN2>(f, m ? m[i] : 0, c);
@@ -666,7 +666,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_mont_convert(DKey key, const 
 // Phase A: for (ciphertext i, prime P):
 //   x = c^(P-1) mod P^2,  m_P = ((x - 1) / P) h_P mod P.
 // Work unit = (prime, 64/G consecutive ciphertexts); G = lanes per integer.
-template <int KP, int G>
+template <int KP, int G, bool CT = false>
 __global__ __launch_bounds__(kBlockThreads, 4) void k_dec_a(DKey key, const uint32_t *__restrict__ ct,
                                                         uint64_t count, uint32_t *__restrict__ mpq,
                                                         uint32_t *__restrict__ tabs) {
@@ -701,7 +701,7 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_dec_a(DKey key, const uint
       ld<K2, G>(c, P.P2.R2);
       mont_mul<K2, G>(y, y, c, M2, lds);
       add_mod<K2, G>(x, x, y, M2);
-      pow29<K2, G>(x, P.e_dec.e, P.e_dec.nwin, tab, P.P2, lds, zeros);  // canonical, = 1 mod P
+      pow29<K2, G>(x, P.e_dec.e, P.e_dec.nwin, tab, P.P2, lds, zeros, CT);  // canonical, = 1 mod P
       set_small<K2, G>(c, 1u);
       sub_plain<K2, G>(x, x, c);          // x - 1 = k P
       relayout<K2, K1, G>(lo, x, lds);
@@ -1157,12 +1157,18 @@ hipError_t launch_encode(const double *x, uint64_t count, uint32_t frac_bits, in
 template <int KP, int G>
 static void launch_p1(const DKey &k, uint64_t count, const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *tq,
                       uint32_t *tab, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_enc_p1<KP, G>), dim3(grid), dim3(kBlockThreads), 0, s, k, count, r, seed, roff, tq, tab);
+  if (k.ct)
+    hipLaunchKernelGGL((k_enc_p1<KP, G, true>), dim3(grid), dim3(kBlockThreads), 0, s, k, count, r, seed, roff, tq, tab);
+  else
+    hipLaunchKernelGGL((k_enc_p1<KP, G>), dim3(grid), dim3(kBlockThreads), 0, s, k, count, r, seed, roff, tq, tab);
 }
 template <int KP, int G>
 static void launch_p2(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *tq, uint32_t *cpq,
                       uint32_t *tab, uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((k_enc_p2<KP, G>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, tq, cpq, tab);
+  if (k.ct)
+    hipLaunchKernelGGL((k_enc_p2<KP, G, true>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, tq, cpq, tab);
+  else
+    hipLaunchKernelGGL((k_enc_p2<KP, G>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, tq, cpq, tab);
 }
 template <int KP>
 static hipError_t enc_crt(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
@@ -1291,15 +1297,23 @@ hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64
   return hipGetLastError();
 }
 
+template <int KP, int G>
+static void launch_dec_a(const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *mpq, uint32_t *tab,
+                         uint32_t grid, hipStream_t s) {
+  if (k.ct)
+    hipLaunchKernelGGL((k_dec_a<KP, G, true>), dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
+  else
+    hipLaunchKernelGGL((k_dec_a<KP, G>), dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
+}
 template <int KP>
 static hipError_t dec(const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *mpq, int64_t *m,
                       uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, uint32_t grid, int G, hipStream_t s) {
   if (G == 4)
-    hipLaunchKernelGGL((k_dec_a<KP, 4>), dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
+    launch_dec_a<KP, 4>(k, ct, count, mpq, tab, grid, s);
   else if (G == 8)
-    hipLaunchKernelGGL((k_dec_a<KP, 8>), dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
+    launch_dec_a<KP, 8>(k, ct, count, mpq, tab, grid, s);
   else
-    hipLaunchKernelGGL((k_dec_a<KP, 16>), dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
+    launch_dec_a<KP, 16>(k, ct, count, mpq, tab, grid, s);
   hipLaunchKernelGGL(k_dec_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k,
                      (const uint32_t *)mpq, count, m, raw, n_overflow);
   return hipGetLastError();

@@ -438,17 +438,43 @@ __device__ __forceinline__ void to32(uint32_t (&x)[K32], const uint32_t (&t)[K],
   __builtin_amdgcn_wave_barrier();
 }
 
+// This group's window-table entry `digit` into registers.  With ct (the
+// exponent is secret) every entry is read and the wanted one kept by a mask,
+// so the addresses the table reads touch do not depend on the digit; the
+// digit goes through a VGPR so that the selection is data, never control.
+template <int K, int G>
+__device__ __forceinline__ void tab_entry(uint32_t (&v)[K], const uint32_t *tab, uint32_t digit, bool ct) {
+  constexpr int S29 = G * K;
+  if (!ct) {
+    ld29<K, G>(v, tab + digit * S29);
+    return;
+  }
+  uint32_t dv = digit;
+  asm volatile("" : "+v"(dv));
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = 0u;
+#pragma unroll 1
+  for (uint32_t j = 0; j < (uint32_t)kTable; ++j) {
+    uint32_t t[K];
+    ld29<K, G>(t, tab + j * S29);
+    const uint32_t m = dv == j ? 0xFFFFFFFFu : 0u;
+#pragma unroll
+    for (int k = 0; k < K; ++k) v[k] |= t[k] & m;
+  }
+}
+
 // x <- x^e mod N for canonical x < N in 32-bit limbs (K32 per lane), result
 // canonical.  Left-to-right fixed 5-bit windows over `nwin` windows in the
 // radix-2^29 Montgomery domain; a multiplication by the table entry is done
 // for every window, zero digits included, so the sequence of operations does
-// not depend on the exponent.  `tab`: this group's table, kTable entries of
-// S29 words in global memory; `lds`: this group's row of at least
-// max(G K32, 2 S29) words; `zeros`: S29 zero words in the row's LDS array
-// (see sq29).
+// not depend on the exponent; with ct the table reads do not either (see
+// tab_entry), otherwise each window reads the entry its digit names.  `tab`:
+// this group's table, kTable entries of S29 words in global memory; `lds`:
+// this group's row of at least max(G K32, 2 S29) words; `zeros`: S29 zero
+// words in the row's LDS array (see sq29).
 template <int K32, int G>
 __device__ __forceinline__ void pow29(uint32_t (&x)[K32], const uint32_t *e, int nwin, uint32_t *tab,
-                                      const DMod &D, uint32_t *lds, const uint32_t *zeros) {
+                                      const DMod &D, uint32_t *lds, const uint32_t *zeros, bool ct) {
   constexpr int S29 = he29::limbs_for_group(G * K32, G);
   constexpr int K = S29 / G;
   constexpr int v = he29::variant(G);
@@ -471,12 +497,18 @@ __device__ __forceinline__ void pow29(uint32_t (&x)[K32], const uint32_t *e, int
     st29<K, G>(tab + d * S29, cur);
   }
   __threadfence_block();
-  ld29<K, G>(cur, tab + exp_digit(e, nwin - 1) * S29);
+  tab_entry<K, G>(cur, tab, exp_digit(e, nwin - 1), ct);
 #pragma unroll 1
   for (int w = nwin - 2; w >= 0; --w) {
 #pragma unroll 1
     for (int s = 0; s < kWindow; ++s) sq29<K, G>(cur, cur, M, lds, zeros);
-    mm29_mem<K, G>(cur, tab + exp_digit(e, w) * S29, cur, M, lds);
+    if (ct) {
+      uint32_t v[K];
+      tab_entry<K, G>(v, tab, exp_digit(e, w), true);
+      mm29<K, G>(cur, v, cur, M, lds);
+    } else {
+      mm29_mem<K, G>(cur, tab + exp_digit(e, w) * S29, cur, M, lds);
+    }
   }
   // leave the Montgomery domain: cur R'^-1 (a product with 1, at most N)
   {

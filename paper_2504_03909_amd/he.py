@@ -29,7 +29,7 @@ EXPORTED = (
     "he_hist_autotune", "he_hist_plan_create", "he_hist_plan_launch", "he_hist_plan_free",
     "he_obfuscators", "he_encrypt_obfuscated", "he_hist_subtract", "he_split_find",
     "he_hist_aggregate_counted", "he_ct_mul", "he_pack_slots", "he_pack", "he_decrypt_packed",
-    "he_decrypt_noalloc",
+    "he_decrypt_noalloc", "he_key_set_constant_time",
 )
 
 
@@ -69,6 +69,7 @@ _key_export = _sig("he_key_export", _i32, [_vp, _vp, _vp, _vp])
 _key_bits = _sig("he_key_bits", _u32, [_vp])
 _key_priv = _sig("he_key_has_private", _i32, [_vp])
 _key_free = _sig("he_key_free", None, [_vp])
+_key_ct = _sig("he_key_set_constant_time", _i32, [_vp, _i32])
 _encode = _sig("he_encode", _i32, [_vp, _u64, _u32, _vp, _vp, _vp])
 _encrypt = _sig("he_encrypt", _i32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp])
 _encrypt_pub = _sig("he_encrypt_public", _i32, [_vp, _vp, _u64, _vp, _u64, _u64, _vp, _vp])
@@ -183,6 +184,11 @@ class Key:
     @property
     def has_private(self) -> bool:
         return bool(_key_priv(self._h))
+
+    def set_constant_time(self, on: bool = True) -> None:
+        """Private-key exponentiations read every window-table entry (addresses
+        independent of the secret exponent digits); results are unchanged."""
+        _check(_key_ct(self._h, 1 if on else 0))
 
     def export(self):
         L = self.limbs

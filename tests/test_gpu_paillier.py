@@ -202,6 +202,37 @@ def test_exponentiation_group_widths(he):
         assert got == want
 
 
+@pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
+def test_constant_time_exponentiations(he, bits, seed):
+    """With the key's constant-time table reads on, CRT encryption (every
+    group width) and decryption give the same ciphertexts and plaintexts as
+    the default path, and sampled ciphertexts equal the oracle's."""
+    import torch
+    say(f"constant-time exponentiations {bits}")
+    sk = oracle_key(bits, seed)
+    pk = sk.public
+    ref = gpu_key(bits, seed)
+    k = he.Key.from_primes(bits, sk.p, sk.q)
+    k.set_constant_time(True)
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    counts = _group_counts(cus) if bits == 2048 else [1000, 37]
+    rng = np.random.default_rng(bits + 7)
+    for count in counts:
+        say(f"constant-time {bits}: {count} encryptions")
+        m = rng.integers(-(1 << 62), 1 << 62, size=count, dtype=np.int64)
+        ct = he.encrypt(k, dev(m), seed=91)
+        assert torch.equal(ct, he.encrypt(ref, dev(m), seed=91))
+        dm, raw, _ = he.decrypt(k, ct, raw=True)
+        dm_ref, raw_ref, _ = he.decrypt(ref, ct, raw=True)
+        assert torch.equal(dm, dm_ref) and torch.equal(raw, raw_ref)
+        assert host(dm).tolist() == m.tolist()
+        pick = rng.choice(count, size=4, replace=False)
+        want = pool.encrypt_many(pk, [int(m[i]) % pk.n for i in pick],
+                                 [P.seeded_r(pk.n, bits, 91, int(i)) for i in pick])
+        assert he.limbs_to_ints(host(ct)[pick]) == want
+    k.close()
+
+
 # ---------------------------------------------------------- decryption
 @pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
 def test_decrypt_exact(he, bits, seed):

@@ -274,6 +274,9 @@ def main():
     he.encrypt(key, he.encode(grads), seed=R_SEED, out=ct.view(-1, 2 * L))
     tuned_chunk, tuned_split, tuned_ms = (he.hist_autotune(key, ct, [he.Job(idx, bins, K)])
                                           if args.chunk == 0 else (args.chunk, 2, None))
+    # launch shapes of the exponentiations (lanes per integer, waves per SIMD)
+    # for 200,000 encryptions and 16,384 decryptions, tuned before timing
+    exp_shapes = he.crt_autotune(key, 2 * M, J * K * 2)
     for _ in range(args.warmup):
         step([ev() for _ in range(5)])
     torch.cuda.synchronize()
@@ -383,6 +386,8 @@ def main():
             "key_bits": KEY_BITS, "samples": M, "features": J, "bins": K, "r": "seeded",
             "encrypt_path": "crt", "hist_chunk": tuned_chunk, "hist_split": tuned_split,
             "hist_shape": "autotuned before timing" if args.chunk == 0 else "given",
+            "exponentiation_shapes": {k: {"lanes": v[0], "waves_per_simd": v[1] or "own occupancy",
+                                          "tuning_ms": round(v[2], 3)} for k, v in exp_shapes.items()},
         },
         "stages": {
             "encode_ms": round(avg["encode"], 3),

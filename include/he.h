@@ -219,6 +219,24 @@ int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t rows, int c
                      const he_hist_job *jobs, uint32_t n_jobs, uint32_t *chunk, uint32_t *split,
                      float *ms, hipStream_t stream);
 
+/* Autotuner for the private-key exponentiations: the CRT encryption's
+ * exponentiation mod p and p-th-power lift mod p^2 (Sec. III-C: 2M
+ * encryptions for M samples) and decryption's exponentiation mod p^2.  Times
+ * every built launch shape of each -- lanes per integer (2, 4, 8 or 16) and
+ * waves per SIMD (the kernel's own occupancy, or 3 or 2 by reserving LDS) --
+ * on enc_count encryptions and dec_count decryptions of trial operands (the
+ * running time of the fixed-window exponentiations does not depend on the
+ * data), and remembers the fastest per kind for the count's size class (bit
+ * length) on this device and key size; later he_encrypt, he_obfuscators and
+ * he_decrypt calls of that class use it.  Results never depend on the shape.
+ * Allocates trial buffers and synchronises `stream`.
+ * choice: optional host uint32[6]: lanes and waves (0 = own occupancy) of
+ *         the mod-p exponentiation, the lift and decryption.
+ * ms: optional host float[3]: their launch times.
+ * HE_ERR_NOPRIV for a public key, HE_ERR_ARG for a zero count. */
+int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t dec_count, uint32_t *choice, float *ms,
+                    hipStream_t stream);
+
 /* Work-count check of the aggregation: he_hist_aggregate_ex with an explicit
  * work-item length (chunk, 0 = default) and groups per item (split, 1 or 2),
  * that also adds, into the device counters mm_count[3] (not cleared):
@@ -318,11 +336,11 @@ int he_decrypt(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m
  * that forbid hipMalloc).  Same arguments, results and errors as he_decrypt,
  * bit for bit; the kernels are he_decrypt's.  Its working memory is one
  * 64 MiB array in the library's device image, one copy per device, held
- * until the process ends: count must not exceed 2^23 / L ciphertexts
- * (131,072 at 2048-bit keys, 262,144 at 1024-bit), else HE_ERR_ARG before
+ * until the process ends: count must not exceed 2^22 / L ciphertexts
+ * (65,536 at 2048-bit keys, 131,072 at 1024-bit), else HE_ERR_ARG before
  * any device work; the exponentiation launch is cut to the blocks whose
- * window tables fit beside the count's m_p, m_q, so large calls run on
- * part of the device.  Nothing in the array needs to start at zero.  Every
+ * window tables fit beside the count's residues mod p^2 and q^2, so large
+ * calls run on part of the device.  Nothing in the array needs to start at zero.  Every
  * call on a device shares that device's array: calls that overlap on one
  * device (other streams, other threads) race and must be serialised by the
  * caller. */

@@ -173,9 +173,56 @@ int ensure(Buf &b, size_t bytes, hipStream_t s) {
   return HE_OK;
 }
 
-uint32_t persistent_grid(int KP, int kind, uint64_t work_blocks, int G = 16) {
-  const uint32_t res = he::resident_blocks(KP, kind, G);
+uint32_t persistent_grid(int KP, int kind, uint64_t work_blocks) {
+  const uint32_t res = he::resident_blocks(KP, kind);
   return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(res, work_blocks));
+}
+
+// ------------------------------------------------- exponentiation launch shapes
+// Tuned shapes (lanes per integer, waves per SIMD) of the private-key
+// exponentiations per (device, key size, kind, count class), filled by
+// he_crt_autotune; count class = bit length of the count.
+struct PowShape {
+  int G = 0, waves = 0;  // waves 0: the kernel's own occupancy
+};
+std::mutex g_pow_mu;
+std::map<std::tuple<int, int, int, int>, PowShape> g_pow_tuned;
+
+int count_class(uint64_t count) {
+  int b = 0;
+  while (count) {
+    ++b;
+    count >>= 1;
+  }
+  return b;
+}
+
+int pow_s32(int KP, int kind) { return kind == 4 ? 16 * KP : 32 * KP; }
+
+he::PowLaunch pow_launch_at(int KP, int kind, uint64_t count, PowShape sh) {
+  const int S32 = pow_s32(KP, kind);
+  if (sh.G == 0 || !he::pow_shape_valid(S32, sh.G)) sh = PowShape{he::pick_group(KP, kind, count), 0};
+  const uint32_t dyn = he::pow_dyn_lds(S32, sh.G, sh.waves);
+  const uint64_t per_wave = 64 / sh.G;
+  const uint64_t work_blocks = (2 * ((count + per_wave - 1) / per_wave) + 3) / 4;
+  const uint32_t grid =
+      (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(he::pow_resident_blocks(S32, sh.G, dyn), work_blocks));
+  return he::PowLaunch{sh.G, grid, dyn};
+}
+
+// The launch shape of a private-key exponentiation over `count` ciphertexts:
+// the tuned one for its class if the autotuner ran, else the default
+// (pick_group's width, the kernel's maximum occupancy).
+he::PowLaunch pow_launch(int KP, int kind, uint64_t count) {
+  PowShape sh;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  {
+    std::lock_guard<std::mutex> lk(g_pow_mu);
+    auto it = g_pow_tuned.find({dev, KP, kind, count_class(count)});
+    if (it != g_pow_tuned.end()) sh = it->second;
+  }
+  return pow_launch_at(KP, kind, count, sh);
 }
 
 // m == nullptr encrypts zeros (the obfuscators r^n mod n^2).
@@ -188,19 +235,17 @@ int encrypt_impl(const he_key *key, const int64_t *m, uint64_t count, const uint
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
   if (key->priv && !force_pub) {
-    // kind 4: the mod-P exponentiation (A1); kind 0: the lift mod P^2 (A2)
-    const int G1 = he::pick_group(KP, 4, count), G2 = he::pick_group(KP, 0, count);
-    const uint32_t grid1 = persistent_grid(KP, 4, (2 * ((count + 64 / G1 - 1) / (64 / G1)) + 3) / 4, G1);
-    const uint32_t grid2 = persistent_grid(KP, 0, (2 * ((count + 64 / G2 - 1) / (64 / G2)) + 3) / 4, G2);
-    int rc = ensure(w->tab, std::max(grid1 * he::table_bytes_per_block(KP, 4, G1),
-                                     grid2 * he::table_bytes_per_block(KP, 0, G2)), stream);
+    const he::PowLaunch l1 = pow_launch(KP, 4, count), l2 = pow_launch(KP, 0, count);
+    int rc = ensure(w->tab, std::max(l1.grid * he::table_bytes_per_block(KP, 4, l1.G),
+                                     l2.grid * he::table_bytes_per_block(KP, 0, l2.G)), stream);
     if (rc) return rc;
-    // c_P per (ciphertext, prime) (2L limbs per ciphertext), then t per (ciphertext, prime) (L limbs)
+    // omega / c_P per (ciphertext, prime) (2L limbs per ciphertext), then
+    // r mod P / t per (ciphertext, prime) (L limbs)
     rc = ensure(w->tmp, count * 3 * L * sizeof(uint32_t), stream);
     if (rc) return rc;
     uint32_t *cpq = (uint32_t *)w->tmp.p, *tq = cpq + count * 2 * L;
     HE_TRY_HIP(he::launch_enc_crt(KP, key->dk, m, count, r, r_seed, r_offset, tq, cpq, ct, (uint32_t *)w->tab.p,
-                                  grid1, G1, grid2, G2, stream));
+                                  l1, l2, stream));
   } else {
     const uint32_t grid = persistent_grid(KP, 1, ((count + 3) / 4 + 3) / 4);
     int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 1), stream);
@@ -394,23 +439,22 @@ int he_decrypt(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m
   Workspace *w = workspace(stream);
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
-  const int G = he::pick_group(KP, 2, count);
-  const uint64_t per_wave = 64 / G;
-  const uint32_t grid = persistent_grid(KP, 2, (2 * ((count + per_wave - 1) / per_wave) + 3) / 4, G);
-  int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 2, G), stream);
+  const he::PowLaunch l = pow_launch(KP, 2, count);
+  int rc = ensure(w->tab, l.grid * he::table_bytes_per_block(KP, 2, l.G), stream);
   if (rc) return rc;
-  rc = ensure(w->tmp, count * L * sizeof(uint32_t), stream);
+  // c mod P^2, then c^(P-1) mod P^2, per (ciphertext, prime): 2L limbs per ciphertext
+  rc = ensure(w->tmp, count * 2 * L * sizeof(uint32_t), stream);
   if (rc) return rc;
   HE_TRY_HIP(he::launch_dec(KP, key->dk, ct, count, (uint32_t *)w->tmp.p, m, raw, n_overflow,
-                            (uint32_t *)w->tab.p, grid, G, stream));
+                            (uint32_t *)w->tab.p, l, stream));
   return HE_OK;
 }
 
 }  // extern "C"
 
 // ------------------------------------------------- allocation-free decryption
-// Scratch of he_decrypt_noalloc: the per-ciphertext half-plaintexts m_p, m_q
-// (L words per ciphertext, at most half of the array) followed by the
+// Scratch of he_decrypt_noalloc: c mod p^2 and c mod q^2, then their powers
+// (2L words per ciphertext, at most half of the array), followed by the
 // exponentiation window tables of the persistent launch, whose grid is cut
 // to what the rest of the array holds.  One copy per device, held until the
 // process ends; in host code `scratch` only names the symbol, its device
@@ -452,7 +496,7 @@ int he_decrypt_noalloc(const he_key *key, const uint32_t *ct, uint64_t count, in
   if (!ct || !m) return fail(HE_ERR_ARG, "null ct or m");
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
-  const uint64_t max_count = (kNoAllocBytes / 2) / (L * sizeof(uint32_t));
+  const uint64_t max_count = (kNoAllocBytes / 2) / (2 * L * sizeof(uint32_t));
   if (count > max_count)
     return fail(HE_ERR_ARG, "he_decrypt_noalloc: count " + std::to_string(count) + " exceeds the maximum of " +
                                 std::to_string(max_count) + " ciphertexts at " + std::to_string(key->n_bits) +
@@ -460,16 +504,14 @@ int he_decrypt_noalloc(const he_key *key, const uint32_t *ct, uint64_t count, in
   void *base = nullptr;
   int rc = scratch_address(&base);
   if (rc) return rc;
-  const size_t mpq_bytes = (count * L * sizeof(uint32_t) + 255) / 256 * 256;
-  const int G = he::pick_group(KP, 2, count);
-  const uint64_t per_wave = 64 / G;
-  const uint64_t fit = (kNoAllocBytes - mpq_bytes) / he::table_bytes_per_block(KP, 2, G);
+  const size_t xpq_bytes = (count * 2 * L * sizeof(uint32_t) + 255) / 256 * 256;
+  he::PowLaunch l = pow_launch(KP, 2, count);
+  const uint64_t fit = (kNoAllocBytes - xpq_bytes) / he::table_bytes_per_block(KP, 2, l.G);
   if (fit == 0) return fail(HE_ERR_ARG, "he_decrypt_noalloc: no room for one block's window tables");
-  const uint32_t grid = (uint32_t)std::min<uint64_t>(
-      fit, persistent_grid(KP, 2, (2 * ((count + per_wave - 1) / per_wave) + 3) / 4, G));
-  uint32_t *mpq = (uint32_t *)base;
-  uint32_t *tab = (uint32_t *)((char *)base + mpq_bytes);
-  HE_TRY_HIP(he::launch_dec(KP, key->dk, ct, count, mpq, m, raw, n_overflow, tab, grid, G, stream));
+  l.grid = (uint32_t)std::min<uint64_t>(fit, l.grid);
+  uint32_t *xpq = (uint32_t *)base;
+  uint32_t *tab = (uint32_t *)((char *)base + xpq_bytes);
+  HE_TRY_HIP(he::launch_dec(KP, key->dk, ct, count, xpq, m, raw, n_overflow, tab, l, stream));
   return HE_OK;
 }
 
@@ -749,6 +791,112 @@ extern "C" int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t 
   if (chunk_out) *chunk_out = best.chunk;
   if (split_out) *split_out = best.split;
   if (ms_out) *ms_out = best.ms;
+  return HE_OK;
+}
+
+// ------------------------------------------- exponentiation shape autotuner
+namespace {
+struct DevBuf {
+  void *p = nullptr;
+  ~DevBuf() {
+    if (p) hipFree(p);
+  }
+};
+
+// Times `launch` (two runs after one warm-up) on `stream`; ms per run.
+template <typename F>
+int time_ms(F launch, hipStream_t stream, hipEvent_t e0, hipEvent_t e1, float *ms) {
+  HE_TRY_HIP(launch());
+  HE_TRY_HIP(hipEventRecord(e0, stream));
+  for (int r = 0; r < 2; ++r) HE_TRY_HIP(launch());
+  HE_TRY_HIP(hipEventRecord(e1, stream));
+  HE_TRY_HIP(hipEventSynchronize(e1));
+  HE_TRY_HIP(hipEventElapsedTime(ms, e0, e1));
+  *ms /= 2;
+  return HE_OK;
+}
+}  // namespace
+
+extern "C" int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t dec_count, uint32_t *choice,
+                               float *ms_out, hipStream_t stream) {
+  if (!key) return fail(HE_ERR_ARG, "null key");
+  if (!key->priv) return fail(HE_ERR_NOPRIV, "the CRT exponentiations need p and q");
+  if (enc_count == 0 || dec_count == 0) return fail(HE_ERR_ARG, "need enc_count >= 1 and dec_count >= 1");
+  const int KP = kp_of(key);
+  const size_t L = key->n_bits / 32;
+  const uint64_t n_ct = std::max(enc_count, dec_count);
+  int dev = 0;
+  HE_TRY_HIP(hipGetDevice(&dev));
+  // trial buffers: r mod P / t, omega, ciphertexts, c mod P^2, window tables
+  DevBuf tq, cpq, ct, xpq, tab;
+  size_t tab_bytes = 0;
+  for (int kind : {4, 0, 2})
+    for (int G : {2, 4, 8, 16})
+      if (he::pow_shape_valid(pow_s32(KP, kind), G))
+        tab_bytes = std::max<size_t>(tab_bytes, (size_t)he::pow_resident_blocks(pow_s32(KP, kind), G, 0) *
+                                                   he::table_bytes_per_block(KP, kind, G));
+  const size_t sizes[5] = {n_ct * L * 4, n_ct * 2 * L * 4, n_ct * 2 * L * 4, n_ct * 2 * L * 4, tab_bytes};
+  DevBuf *bufs[5] = {&tq, &cpq, &ct, &xpq, &tab};
+  for (int b = 0; b < 5; ++b)
+    if (hipMalloc(&bufs[b]->p, sizes[b]) != hipSuccess) {
+      hipGetLastError();
+      return fail(HE_ERR_OOM, "autotuner trial buffers");
+    }
+  uint32_t *tq_p = (uint32_t *)tq.p, *cpq_p = (uint32_t *)cpq.p, *ct_p = (uint32_t *)ct.p,
+           *xpq_p = (uint32_t *)xpq.p, *tab_p = (uint32_t *)tab.p;
+  const uint32_t SP = 16 * KP, SP2 = 32 * KP;
+  // real operands: r mod P, one encryption (default shapes), c mod P^2
+  HE_TRY_HIP(he::launch_enc_r(KP, key->dk, enc_count, nullptr, 1, 0, tq_p, stream));
+  int rc = encrypt_impl(key, nullptr, n_ct, nullptr, 1, 0, ct_p, stream, false);
+  if (rc) return rc;
+  HE_TRY_HIP(he::launch_dec_pre(KP, key->dk, ct_p, dec_count, xpq_p, stream));
+  hipEvent_t e0, e1;
+  HE_TRY_HIP(hipEventCreate(&e0));
+  HE_TRY_HIP(hipEventCreate(&e1));
+  PowShape best[3];
+  float best_ms[3] = {1e30f, 1e30f, 1e30f};
+  const int kinds[3] = {4, 0, 2};
+  for (int t = 0; t < 3 && !rc; ++t) {
+    const int kind = kinds[t];
+    const uint64_t count = kind == 2 ? dec_count : enc_count;
+    for (int G : {2, 4, 8, 16}) {
+      if (!he::pow_shape_valid(pow_s32(KP, kind), G)) continue;
+      for (int waves : {0, 3, 2}) {
+        const PowShape sh{G, waves};
+        const he::PowLaunch l = pow_launch_at(KP, kind, count, sh);
+        if (waves && l.dyn == 0) continue;  // the kernel's own occupancy is already at most `waves`
+        auto run = [&]() -> hipError_t {
+          if (kind == 4) return he::launch_pow_kind(KP, key->dk, 4, tq_p, SP, SP, tq_p, SP, count, tab_p, l, stream);
+          if (kind == 0) return he::launch_pow_kind(KP, key->dk, 0, tq_p, SP, SP, cpq_p, SP2, count, tab_p, l, stream);
+          return he::launch_pow_kind(KP, key->dk, 2, xpq_p, SP2, SP2, xpq_p, SP2, count, tab_p, l, stream);
+        };
+        float ms = 0;
+        rc = time_ms(run, stream, e0, e1, &ms);
+        if (rc) break;
+        if (ms < best_ms[t]) {
+          best_ms[t] = ms;
+          best[t] = sh;
+        }
+      }
+      if (rc) break;
+    }
+  }
+  hipEventDestroy(e0);
+  hipEventDestroy(e1);
+  HE_TRY_HIP(hipStreamSynchronize(stream));
+  if (rc) return rc;
+  {
+    std::lock_guard<std::mutex> lk(g_pow_mu);
+    for (int t = 0; t < 3; ++t)
+      g_pow_tuned[{dev, KP, kinds[t], count_class(kinds[t] == 2 ? dec_count : enc_count)}] = best[t];
+  }
+  for (int t = 0; t < 3; ++t) {
+    if (choice) {
+      choice[2 * t] = (uint32_t)best[t].G;
+      choice[2 * t + 1] = (uint32_t)best[t].waves;
+    }
+    if (ms_out) ms_out[t] = best_ms[t];
+  }
   return HE_OK;
 }
 

@@ -102,9 +102,17 @@ constexpr int kHistWaves = 5;       // waves per SIMD asked of the histogram pro
 // KP = limbs per lane of a prime: 1 for 1024-bit keys, 2 for 2048-bit keys.
 hipError_t launch_encode(const double *x, uint64_t count, uint32_t frac_bits, int64_t *m,
                          uint32_t *n_bad, hipStream_t s);
+// Launch shape of a private-key exponentiation (k_pow): lanes per integer,
+// grid, and dynamic LDS reserved only to cap the blocks per compute unit.
+struct PowLaunch {
+  int G;
+  uint32_t grid;
+  uint32_t dyn;
+};
+// tq: [count][2][S_P] (r mod P, then t in place), cpq: [count][2][S_P2].
 hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
-                          uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab, uint32_t grid1,
-                          int G1, uint32_t grid2, int G2, hipStream_t s);
+                          uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab,
+                          const PowLaunch &l1, const PowLaunch &l2, hipStream_t s);
 hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
                           const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *ct,
                           uint32_t *tab, uint32_t grid, hipStream_t s);
@@ -125,9 +133,19 @@ hipError_t launch_unpack(const uint32_t *raw, uint64_t count, uint32_t slots, ui
 uint32_t pack_slots(int n_bits, uint64_t count);
 hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64_t count,
                                uint32_t *out, bool to_mont, hipStream_t s);
+// The pieces, for the autotuner: r mod P into tq; one private-key
+// exponentiation of `kind` (4 mod P, 0 lift, 2 decryption; in/out strides
+// and limbs per (ciphertext, prime) unit); c mod P^2 into xpq.
+hipError_t launch_enc_r(int KP, const DKey &k, uint64_t count, const uint32_t *r, uint64_t seed, uint64_t roff,
+                        uint32_t *tq, hipStream_t s);
+hipError_t launch_pow_kind(int KP, const DKey &k, int kind, const uint32_t *in, uint32_t in_stride,
+                           uint32_t in_limbs, uint32_t *out, uint32_t out_stride, uint64_t count, uint32_t *tab,
+                           const PowLaunch &l, hipStream_t s);
+hipError_t launch_dec_pre(int KP, const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *xpq, hipStream_t s);
+// xpq: [count][2][S_P2] (c mod P^2, then c^(P-1) mod P^2 in place).
 hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count,
-                      uint32_t *mpq, int64_t *m, uint32_t *raw, uint32_t *n_overflow,
-                      uint32_t *tab, uint32_t grid, int G, hipStream_t s);
+                      uint32_t *xpq, int64_t *m, uint32_t *raw, uint32_t *n_overflow,
+                      uint32_t *tab, const PowLaunch &l, hipStream_t s);
 hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *host_jobs,
                        const HistWs &ws, uint32_t chunk_grid, hipStream_t s);
 // Work items are chunks of `chunk` samples of one (feature, bin); with
@@ -136,13 +154,21 @@ hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *h
 hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_probe_mul(uint64_t iters, uint32_t grid, uint32_t *sink, hipStream_t s);
 
-// Resident blocks of 256 threads the device holds for each persistent kernel
-// (occupancy x compute units), by kind: 0 enc_crt, 1 enc_pub, 2 dec, 3 hist
-// chunk; G = lanes per integer of the kernel variant (kinds 0 and 2).
-uint32_t resident_blocks(int KP, int kind, int G = 16);
-// Window-table scratch bytes per resident block of the given kernel kind.
+// Resident blocks of 256 threads the device holds for the persistent
+// public-key encryption (kind 1) and histogram product (kind 3) kernels.
+uint32_t resident_blocks(int KP, int kind);
+// The private-key exponentiation k_pow over an S32-limb modulus (S_P or
+// S_P2 32-bit limbs) at G lanes per integer: whether that shape is built,
+// its resident blocks with `dyn` bytes of dynamic LDS, and the dynamic LDS
+// that caps it at `waves` blocks per compute unit (0: no cap).
+bool pow_shape_valid(int S32, int G);
+uint32_t pow_resident_blocks(int S32, int G, uint32_t dyn);
+uint32_t pow_dyn_lds(int S32, int G, int waves);
+// Window-table scratch bytes per resident block: kinds 4 (mod P), 0 (lift
+// mod P^2), 2 (decryption mod P^2) at G lanes, 1 (public key, 16 lanes).
 uint64_t table_bytes_per_block(int KP, int kind, int G = 16);
-// Lanes per integer for a CRT exponentiation kernel over `count` ciphertexts.
+// Default lanes per integer for a private-key exponentiation of `kind`
+// over `count` ciphertexts.
 int pick_group(int KP, int kind, uint64_t count);
 
 }  // namespace he

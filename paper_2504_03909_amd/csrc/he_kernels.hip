@@ -9,6 +9,10 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <map>
+#include <mutex>
+#include <tuple>
+
 #include "he_internal.hpp"
 #include "hist_bucket.hpp"
 #include "mont.hpp"
@@ -70,7 +74,10 @@ __device__ __forceinline__ void seeded_limbs(uint32_t (&x)[K], uint64_t seed, ui
   }
 }
 
-__device__ __forceinline__ uint32_t wave_in_block() { return threadIdx.x >> 6; }
+// The wave's index in its block, as a wave-uniform (scalar) value: what the
+// persistent loops derive from it (unit index, prime, modulus and exponent
+// pointers) then lives in SGPRs.
+__device__ __forceinline__ uint32_t wave_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
 __device__ __forceinline__ uint32_t group_in_wave() { return (threadIdx.x >> 4) & 3u; }
 
 // ------------------------------------------------------------------- encode
@@ -88,124 +95,104 @@ __global__ void k_encode(const double *__restrict__ x, uint64_t count, uint32_t 
   }
 }
 
+// ----------------------------------------------------- private-key exponentiation
+// k_pow: x_u <- x_u^(e_P) mod M_P for units u = (ciphertext i, prime P), the
+// radix-2^29 exponentiation alone (the products around it run in the 16-lane
+// kernels below, so this kernel holds nothing but the exponentiation's own
+// state).  Unit (i, w) reads in_limbs limbs at in + (2 i + w) in_stride
+// (zero-extended to S32) and writes S32 canonical limbs at
+// out + (2 i + w) out_stride.  Work unit = (prime, 64/G consecutive
+// ciphertexts), so the modulus and exponent are the same for the whole wave.
+// CT: constant-time window-table reads.  At most 3 waves per SIMD: the
+// 18-limb-per-lane shapes need about 168 VGPRs to run their step loops
+// without spills (at 128, for 4 waves, the loops spill and run 25% slower).
+struct PowArgs {
+  DMod mod[2];
+  DExp exp[2];
+  const uint32_t *in;
+  uint32_t *out;
+  uint32_t in_stride, in_limbs, out_stride;
+  uint64_t count;
+  uint32_t *tabs;
+};
+
+template <int S32, int G, bool CT>
+__global__ __launch_bounds__(kBlockThreads, 3) void k_pow(PowArgs a) {
+  constexpr int K32 = S32 / G, NG = 64 / G, GB = kBlockThreads / G;
+  constexpr int S29 = he29::limbs_for_group(S32, G), ROW = 2 * S29 > S32 ? 2 * S29 : S32;
+  __shared__ __align__(16) uint32_t lds_all[GB * ROW + S29];
+  uint32_t *const zeros = lds_all + GB * ROW;
+  zero_lds(zeros, S29);
+  const uint32_t g = (threadIdx.x & 63u) / G;
+  uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
+  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
+  const uint64_t nw = (uint64_t)gridDim.x * 4;
+  uint32_t *tab = a.tabs + (gw * NG + g) * (uint64_t)(kTable * S29);
+  const uint64_t nunits = 2 * ((a.count + NG - 1) / NG);
+  for (uint64_t qd = gw; qd < nunits; qd += nw) {
+    const int which = (int)(qd & 1);
+    uint64_t i = (qd >> 1) * NG + g;
+    const bool valid = i < a.count;
+    if (!valid) i = a.count - 1;
+    const uint64_t u = i * 2 + which;
+    uint32_t x[K32];
+    ld_part<K32, G>(x, a.in + u * a.in_stride, (int)a.in_limbs);
+    pow29<K32, G>(x, a.exp[which].e, a.exp[which].nwin, tab, a.mod[which], lds, zeros, CT);
+    if (valid) st<K32, G>(a.out + u * a.out_stride, x);
+  }
+}
+
 // ----------------------------------------------------------- CRT encryption
-// Phase A, for each (ciphertext i, prime P):
-//   c_P = (1 + m n) r^n mod P^2,  r^n mod P^2 = (r^(Q mod (P-1)) mod P)^P mod P^2,
-// in two kernels so that each runs at its own group width: A1 computes
-// t = r^(Q mod (P-1)) mod P (mod-P arithmetic, 2-lane groups for large
-// counts), A2 lifts omega = t^P mod P^2 and forms c_P (4-lane groups).  Work
-// unit = (prime, 64/G consecutive ciphertexts) so that the exponent is the
-// same for the whole wave.
+// For each (ciphertext i, prime P):
+//   c_P = (1 + m n) r^n mod P^2,  r^n mod P^2 = (r^(Q mod (P-1)) mod P)^P mod P^2
+// (x -> x^P mod P^2 depends only on x mod P), and 1 + m n = 1 + P (m Q mod P)
+// mod P^2.  k_enc_r reduces r mod P, k_pow computes t = r^(Q mod (P-1)) mod P
+// (mod-P arithmetic, 2-lane groups for large counts) and then omega = t^P mod
+// P^2 (4-lane groups), and k_enc_crt_b forms c_P = omega (1 + P (m Q mod P))
+// and combines c_p, c_q by the CRT.
 
-// A1: t[i][P] (S_P limbs, canonical).  CT: constant-time window tables.
-template <int KP, int G, bool CT = false>
-__global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p1(DKey key, uint64_t count,
-                                                           const uint32_t *__restrict__ r, uint64_t seed,
-                                                           uint64_t roff, uint32_t *__restrict__ tq,
-                                                           uint32_t *__restrict__ tabs) {
-  constexpr int SP = 16 * KP, L = 32 * KP;
-  constexpr int K1 = SP / G;  // limbs per lane mod P
-  constexpr int S29 = he29::limbs_for_group(SP, G), ROW = 2 * S29 > SP ? 2 * S29 : SP;
-  constexpr int NG = 64 / G, GB = kBlockThreads / G;
-  __shared__ __align__(16) uint32_t lds_all[GB * ROW + S29];
-  uint32_t *const zeros = lds_all + GB * ROW;
-  zero_lds(zeros, S29);
-  const uint32_t g = (threadIdx.x & 63u) / G;
-  uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
-  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
-  const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * S29);
-  const uint64_t nunits = 2 * ((count + NG - 1) / NG);
-  const uint64_t W = (uint64_t)SP + 1;  // stream words per r
-
-  for (uint64_t qd = gw; qd < nunits; qd += nw) {
-    const int which = (int)(qd & 1);
-    const DPrime &P = key.pr[which];
-    uint64_t i = (qd >> 1) * NG + g;
-    const bool valid = i < count;
-    if (!valid) i = count - 1;
-    const Mod<K1> Mp = load_mod<K1, G>(P.P.N, P.P.ninv);
-    // x = r mod P: r's S_P-limb words w_k (two for an explicit r, three for
-    // the seeded one), each times R^k mod P by a Montgomery product with
-    // R^(k+1) mod P, summed; one word in registers at a time
-    uint32_t x[K1], t[K1], c[K1];
-    const uint64_t base = (roff + i) * W;
-    const int words = r ? 2 : 3;
-    set_zero(x);
-#pragma unroll 1
-    for (int k = 0; k < words; ++k) {
-      if (r)
-        ld<K1, G>(t, r + i * L + k * SP);
-      else
-        seeded_limbs<K1, G>(t, seed, base, k * SP, 2 * SP + 2);
-      ld<K1, G>(c, k == 0 ? P.P.R1 : (k == 1 ? P.P.R2 : P.P.R3));
-      mont_mul<K1, G>(t, t, c, Mp, lds);
-      add_mod<K1, G>(x, x, t, Mp);
-    }
-    // t = r^(Q mod (P-1)) mod P, canonical
-    pow29<K1, G>(x, P.e_enc.e, P.e_enc.nwin, tab, P.P, lds, zeros, CT);
-    if (valid) st<K1, G>(tq + (i * 2 + which) * SP, x);
-  }
-}
-
-// A2: cpq[i][P] (S_P2 limbs, canonical) from t.
-template <int KP, int G, bool CT = false>
-__global__ __launch_bounds__(kBlockThreads, 4) void k_enc_p2(DKey key, const int64_t *__restrict__ m,
-                                                           uint64_t count, const uint32_t *__restrict__ tq,
-                                                           uint32_t *__restrict__ cpq, uint32_t *__restrict__ tabs) {
-  constexpr int SP = 16 * KP, SP2 = 32 * KP;
-  constexpr int K1 = SP / G, K2 = SP2 / G;  // limbs per lane mod P and mod P^2
-  constexpr int S29 = he29::limbs_for_group(SP2, G), ROW = 2 * S29 > SP2 ? 2 * S29 : SP2;
-  constexpr int NG = 64 / G, GB = kBlockThreads / G;
-  __shared__ __align__(16) uint32_t lds_all[GB * ROW + S29];
-  uint32_t *const zeros = lds_all + GB * ROW;
-  zero_lds(zeros, S29);
-  const uint32_t g = (threadIdx.x & 63u) / G;
-  uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
-  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
-  const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * S29);
-  const uint64_t nunits = 2 * ((count + NG - 1) / NG);
-
-  for (uint64_t qd = gw; qd < nunits; qd += nw) {
-    const int which = (int)(qd & 1);
-    const DPrime &P = key.pr[which];
-    uint64_t i = (qd >> 1) * NG + g;
-    const bool valid = i < count;
-    if (!valid) i = count - 1;
-    // omega = t^P mod P^2, canonical
-    uint32_t w[K2];
-    ld_part<K2, G>(w, tq + (i * 2 + which) * SP, SP);
-    pow29<K2, G>(w, P.e_lift.e, P.e_lift.nwin, tab, P.P2, lds, zeros, CT);
-    const Mod<K2> M2 = load_mod<K2, G>(P.P2.N, P.P2.ninv);
-    uint32_t f[K2];
-    {
-      // u = (m mod P) Q mod P, then f = 1 + m n mod P^2 = 1 + P u
-      const Mod<K1> Mp = load_mod<K1, G>(P.P.N, P.P.ninv);
-      uint32_t u[K1], c[K1];
-      signed_mod<K1, G>(u, m ? m[i] : 0, Mp.n);
-      ld<K1, G>(c, P.QR_P);
-      mont_mul<K1, G>(u, u, c, Mp, lds);
-      relayout<K1, K2, G>(f, u, lds);
-    }
-    {
-      uint32_t c2[K2];
-      ld<K2, G>(c2, P.PR_P2);
-      mont_mul<K2, G>(f, f, c2, M2, lds);
-      add_one<K2, G>(f);
-      ld<K2, G>(c2, P.P2.R2);
-      mont_mul<K2, G>(f, f, c2, M2, lds);  // Montgomery form of f
-    }
-    // c_P = omega f mod P^2 (the Montgomery factor of f cancels)
-    mont_mul<K2, G>(w, w, f, M2, lds);
-    if (valid) st<K2, G>(cpq + (i * 2 + which) * SP2, w);
-  }
-}
-
-// Phase B: c = c_q + q^2 ((c_p - c_q) (q^2)^-1 mod p^2), the CRT to mod n^2.
+// r mod P for each (ciphertext i, prime P) into tq[2 i + P] (S_P limbs): r's
+// S_P-limb words w_k (two for an explicit r, three for the seeded one), each
+// times R^k mod P by a Montgomery product with R^(k+1) mod P, summed.  One
+// 16-lane group per (i, P).
 template <int KP>
-__global__ __launch_bounds__(kBlockThreads) void k_enc_crt_b(DKey key, const uint32_t *__restrict__ cpq,
-                                                            uint64_t count, uint32_t *__restrict__ ct) {
+__global__ __launch_bounds__(kBlockThreads) void k_enc_r(DKey key, uint64_t count, const uint32_t *__restrict__ r,
+                                                        uint64_t seed, uint64_t roff, uint32_t *__restrict__ tq) {
+  constexpr int SP = 16 * KP, L = 32 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SP];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SP;
+  uint64_t u = (uint64_t)blockIdx.x * 16 + gi;
+  const bool valid = u < 2 * count;
+  if (!valid) u = 2 * count - 1;
+  const uint64_t i = u >> 1;
+  const DPrime &P = key.pr[u & 1];
+  const Mod<KP> Mp = load_mod<KP>(P.P.N, P.P.ninv);
+  const uint64_t W = (uint64_t)SP + 1;  // stream words per r
+  const uint64_t base = (roff + i) * W;
+  const int words = r ? 2 : 3;
+  uint32_t x[KP], t[KP], c[KP];
+  set_zero(x);
+#pragma unroll 1
+  for (int k = 0; k < words; ++k) {
+    if (r)
+      ld<KP>(t, r + i * L + k * SP);
+    else
+      seeded_limbs<KP>(t, seed, base, k * SP, 2 * SP + 2);
+    ld<KP>(c, k == 0 ? P.P.R1 : (k == 1 ? P.P.R2 : P.P.R3));
+    mont_mul<KP>(t, t, c, Mp, lds);
+    add_mod<KP>(x, x, t, Mp);
+  }
+  if (valid) st<KP>(tq + u * SP, x);
+}
+
+// c_P = omega_P (1 + P (m Q mod P)) mod P^2 for both primes, then
+// c = c_q + q^2 ((c_p - c_q) (q^2)^-1 mod p^2), the CRT to mod n^2.  One
+// 16-lane group per ciphertext.
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_enc_crt_b(DKey key, const int64_t *__restrict__ m,
+                                                            const uint32_t *__restrict__ cpq, uint64_t count,
+                                                            uint32_t *__restrict__ ct) {
   constexpr int KP2 = 2 * KP, KN2 = 4 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
   __shared__ __align__(16) uint32_t lds_all[16 * SN2];
   const uint32_t gi = wave_in_block() * 4 + group_in_wave();
@@ -213,19 +200,41 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_crt_b(DKey key, const uin
   uint64_t i = (uint64_t)blockIdx.x * 16 + gi;
   const bool valid = i < count;
   if (!valid) i = count - 1;
+  const int64_t mi = m ? m[i] : 0;
+  uint32_t cw[2][KP2];
+#pragma unroll 1
+  for (int which = 0; which < 2; ++which) {
+    const DPrime &P = key.pr[which];
+    uint32_t w[KP2], f[KP2], c2[KP2];
+    ld<KP2>(w, cpq + (i * 2 + which) * SP2);  // omega = t^P mod P^2
+    {
+      // u = (m mod P) Q mod P, then f = 1 + m n mod P^2 = 1 + P u
+      const Mod<KP> Mp = load_mod<KP>(P.P.N, P.P.ninv);
+      uint32_t uu[KP], c[KP];
+      signed_mod<KP>(uu, mi, Mp.n);
+      ld<KP>(c, P.QR_P);
+      mont_mul<KP>(uu, uu, c, Mp, lds);
+      relayout<KP, KP2>(f, uu, lds);
+    }
+    const Mod<KP2> M2 = load_mod<KP2>(P.P2.N, P.P2.ninv);
+    ld<KP2>(c2, P.PR_P2);
+    mont_mul<KP2>(f, f, c2, M2, lds);
+    add_one<KP2>(f);
+    ld<KP2>(c2, P.P2.R2);
+    mont_mul<KP2>(f, f, c2, M2, lds);  // Montgomery form of f
+    mont_mul<KP2>(cw[which], w, f, M2, lds);  // the Montgomery factor of f cancels
+  }
   const DPrime &Pp = key.pr[0];
   const Mod<KP2> M2 = load_mod<KP2>(Pp.P2.N, Pp.P2.ninv);
-  uint32_t cp[KP2], cq[KP2], c[KP2], a[KP2], b[KP2];
-  ld<KP2>(cp, cpq + (i * 2 + 0) * SP2);
-  ld<KP2>(cq, cpq + (i * 2 + 1) * SP2);
+  uint32_t c[KP2], a[KP2], b[KP2];
   ld<KP2>(c, key.Cq);
-  mont_mul<KP2>(a, cp, c, M2, lds);
-  mont_mul<KP2>(b, cq, c, M2, lds);
+  mont_mul<KP2>(a, cw[0], c, M2, lds);
+  mont_mul<KP2>(b, cw[1], c, M2, lds);
   sub_mod<KP2>(a, a, b, M2);
   const Mod<KN2> Mn2 = load_mod<KN2>(key.n2.N, key.n2.ninv);
   uint32_t u[KN2], cq4[KN2], k4[KN2];
   relayout<KP2, KN2>(u, a, lds);
-  relayout<KP2, KN2>(cq4, cq, lds);
+  relayout<KP2, KN2>(cq4, cw[1], lds);
   ld<KN2>(k4, key.q2R_n2);
   mont_mul<KN2>(u, u, k4, Mn2, lds);
   add_plain<KN2>(u, u, cq4);
@@ -663,81 +672,73 @@ __global__ __launch_bounds__(kBlockThreads) void k_mont_convert(DKey key, const 
 }
 
 // -------------------------------------------------------------- decryption
-// Phase A: for (ciphertext i, prime P):
-//   x = c^(P-1) mod P^2,  m_P = ((x - 1) / P) h_P mod P.
-// Work unit = (prime, 64/G consecutive ciphertexts); G = lanes per integer.
-template <int KP, int G, bool CT = false>
-__global__ __launch_bounds__(kBlockThreads, 4) void k_dec_a(DKey key, const uint32_t *__restrict__ ct,
-                                                        uint64_t count, uint32_t *__restrict__ mpq,
-                                                        uint32_t *__restrict__ tabs) {
-  constexpr int SP = 16 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
-  constexpr int K1 = SP / G, K2 = SP2 / G, NG = 64 / G, GB = kBlockThreads / G;
-  constexpr int S29 = he29::limbs_for_group(SP2, G), ROW = 2 * S29 > SP2 ? 2 * S29 : SP2;
-  __shared__ __align__(16) uint32_t lds_all[GB * ROW + S29];
-  uint32_t *const zeros = lds_all + GB * ROW;
-  zero_lds(zeros, S29);
-  const uint32_t g = (threadIdx.x & 63u) / G;
-  uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
-  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
-  const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * NG + g) * (uint64_t)(kTable * S29);
-  const uint64_t nunits = 2 * ((count + NG - 1) / NG);
-  for (uint64_t qd = gw; qd < nunits; qd += nw) {
-    const int which = (int)(qd & 1);
-    const DPrime &P = key.pr[which];
-    uint64_t i = (qd >> 1) * NG + g;
-    const bool valid = i < count;
-    if (!valid) i = count - 1;
-    uint32_t lo[K1];
-    {
-      const Mod<K2> M2 = load_mod<K2, G>(P.P2.N, P.P2.ninv);
-      uint32_t x[K2], y[K2], c[K2];
-      // c mod P^2 = c0 + c1 R' mod P^2 (halves c0, c1; R' = 2^(32 S_P2)),
-      // each half by a Montgomery product with R' resp. R'^2
-      ld<K2, G>(x, ct + i * SN2);
-      ld<K2, G>(y, ct + i * SN2 + SP2);
-      ld<K2, G>(c, P.P2.R1);
-      mont_mul<K2, G>(x, x, c, M2, lds);
-      ld<K2, G>(c, P.P2.R2);
-      mont_mul<K2, G>(y, y, c, M2, lds);
-      add_mod<K2, G>(x, x, y, M2);
-      pow29<K2, G>(x, P.e_dec.e, P.e_dec.nwin, tab, P.P2, lds, zeros, CT);  // canonical, = 1 mod P
-      set_small<K2, G>(c, 1u);
-      sub_plain<K2, G>(x, x, c);          // x - 1 = k P
-      relayout<K2, K1, G>(lo, x, lds);
-    }
-    // k = (x - 1) P^-1 mod 2^(32 S_P) (exact division), m_P = k h_P mod P
-    uint32_t k[K1], pinv[K1];
-    ld<K1, G>(pinv, P.Pinv);
-    st<K1, G>(lds, lo);
-    __builtin_amdgcn_wave_barrier();
-    mul_lo_lds<K1, G>(k, lds, pinv);
-    __builtin_amdgcn_wave_barrier();
-    const Mod<K1> Mp = load_mod<K1, G>(P.P.N, P.P.ninv);
-    ld<K1, G>(pinv, P.hR_P);
-    mont_mul<K1, G>(k, k, pinv, Mp, lds);
-    if (valid) st<K1, G>(mpq + (i * 2 + which) * SP, k);
-  }
+// For (ciphertext i, prime P): x = c^(P-1) mod P^2 (k_pow), then
+// m_P = ((x - 1) / P) h_P mod P, and Garner's combination of m_p, m_q.
+// k_dec_pre: c mod P^2 for both primes into xpq[2 i + P] (S_P2 limbs):
+// c mod P^2 = c0 + c1 R' mod P^2 (halves c0, c1; R' = 2^(32 S_P2)), each half
+// by a Montgomery product with R' resp. R'^2.  One 16-lane group per (i, P).
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_dec_pre(DKey key, const uint32_t *__restrict__ ct, uint64_t count,
+                                                          uint32_t *__restrict__ xpq) {
+  constexpr int KP2 = 2 * KP, SP2 = 32 * KP, SN2 = 64 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SP2];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SP2;
+  uint64_t u = (uint64_t)blockIdx.x * 16 + gi;
+  const bool valid = u < 2 * count;
+  if (!valid) u = 2 * count - 1;
+  const uint64_t i = u >> 1;
+  const DPrime &P = key.pr[u & 1];
+  const Mod<KP2> M2 = load_mod<KP2>(P.P2.N, P.P2.ninv);
+  uint32_t x[KP2], y[KP2], c[KP2];
+  ld<KP2>(x, ct + i * SN2);
+  ld<KP2>(y, ct + i * SN2 + SP2);
+  ld<KP2>(c, P.P2.R1);
+  mont_mul<KP2>(x, x, c, M2, lds);
+  ld<KP2>(c, P.P2.R2);
+  mont_mul<KP2>(y, y, c, M2, lds);
+  add_mod<KP2>(x, x, y, M2);
+  if (valid) st<KP2>(xpq + u * SP2, x);
 }
 
-// Phase B: m = m_q + q ((m_p - m_q) q^-1 mod p), then the signed decode.
+// m_P = ((x_P - 1) / P) h_P mod P from x_P = c^(P-1) mod P^2 (exact
+// division: (x - 1) P^-1 mod 2^(32 S_P), a low-half product), then
+// m = m_q + q ((m_p - m_q) q^-1 mod p) and the signed decode.
 template <int KP>
-__global__ __launch_bounds__(kBlockThreads) void k_dec_b(DKey key, const uint32_t *__restrict__ mpq,
+__global__ __launch_bounds__(kBlockThreads) void k_dec_b(DKey key, const uint32_t *__restrict__ xpq,
                                                         uint64_t count, int64_t *__restrict__ mout,
                                                         uint32_t *__restrict__ raw,
                                                         uint32_t *__restrict__ n_overflow) {
-  constexpr int KN = 2 * KP, SP = 16 * KP, SN = 32 * KP;
+  constexpr int KN = 2 * KP, KP2 = 2 * KP, SP2 = 32 * KP, SN = 32 * KP;
   __shared__ __align__(16) uint32_t lds_all[16 * SN];
   const uint32_t gi = wave_in_block() * 4 + group_in_wave();
   uint32_t *lds = lds_all + gi * SN;
   uint64_t i = (uint64_t)blockIdx.x * 16 + gi;
   const bool valid = i < count;
   if (!valid) i = count - 1;
+  uint32_t mpq[2][KP];
+#pragma unroll 1
+  for (int which = 0; which < 2; ++which) {
+    const DPrime &P = key.pr[which];
+    uint32_t x[KP2], one[KP2], lo[KP], k[KP], c[KP];
+    ld<KP2>(x, xpq + (i * 2 + which) * SP2);  // canonical, = 1 mod P
+    set_small<KP2>(one, 1u);
+    sub_plain<KP2>(x, x, one);                 // x - 1 = k P
+    relayout<KP2, KP>(lo, x, lds);
+    ld<KP>(c, P.Pinv);
+    st<KP>(lds, lo);
+    __builtin_amdgcn_wave_barrier();
+    mul_lo_lds<KP>(k, lds, c);
+    __builtin_amdgcn_wave_barrier();
+    const Mod<KP> Mp = load_mod<KP>(P.P.N, P.P.ninv);
+    ld<KP>(c, P.hR_P);
+    mont_mul<KP>(mpq[which], k, c, Mp, lds);
+  }
   const DPrime &Pp = key.pr[0];
   const Mod<KP> Mp = load_mod<KP>(Pp.P.N, Pp.P.ninv);
   uint32_t mp[KP], mq[KP], c[KP];
-  ld<KP>(mp, mpq + (i * 2 + 0) * SP);
-  ld<KP>(mq, mpq + (i * 2 + 1) * SP);
+  copy(mp, mpq[0]);
+  copy(mq, mpq[1]);
   ld<KP>(c, Pp.P.R2);
   mont_mul<KP>(mp, mp, c, Mp, lds);
   uint32_t mqr[KP];
@@ -1154,47 +1155,101 @@ hipError_t launch_encode(const double *x, uint64_t count, uint32_t frac_bits, in
   return hipGetLastError();
 }
 
-template <int KP, int G>
-static void launch_p1(const DKey &k, uint64_t count, const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *tq,
-                      uint32_t *tab, uint32_t grid, hipStream_t s) {
-  if (k.ct)
-    hipLaunchKernelGGL((k_enc_p1<KP, G, true>), dim3(grid), dim3(kBlockThreads), 0, s, k, count, r, seed, roff, tq, tab);
-  else
-    hipLaunchKernelGGL((k_enc_p1<KP, G>), dim3(grid), dim3(kBlockThreads), 0, s, k, count, r, seed, roff, tq, tab);
+// k_pow at (S32, G, CT), as a function pointer for the generic launch.
+template <int S32, int G>
+static const void *pow_fn(bool ct) {
+  return ct ? (const void *)k_pow<S32, G, true> : (const void *)k_pow<S32, G, false>;
 }
-template <int KP, int G>
-static void launch_p2(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *tq, uint32_t *cpq,
-                      uint32_t *tab, uint32_t grid, hipStream_t s) {
-  if (k.ct)
-    hipLaunchKernelGGL((k_enc_p2<KP, G, true>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, tq, cpq, tab);
-  else
-    hipLaunchKernelGGL((k_enc_p2<KP, G>), dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, tq, cpq, tab);
+static const void *pow_kernel(int S32, int G, bool ct) {
+  switch (S32) {
+    case 16:
+      return G == 2 ? pow_fn<16, 2>(ct) : G == 4 ? pow_fn<16, 4>(ct) : G == 8 ? pow_fn<16, 8>(ct) : pow_fn<16, 16>(ct);
+    case 32:
+      return G == 2 ? pow_fn<32, 2>(ct) : G == 4 ? pow_fn<32, 4>(ct) : G == 8 ? pow_fn<32, 8>(ct) : pow_fn<32, 16>(ct);
+    default:  // 64: 2-lane groups would exceed the column bound of the radix-2^29 products
+      return G == 4 ? pow_fn<64, 4>(ct) : G == 8 ? pow_fn<64, 8>(ct) : pow_fn<64, 16>(ct);
+  }
 }
+bool pow_shape_valid(int S32, int G) {
+  return (G == 2 || G == 4 || G == 8 || G == 16) && (S32 == 16 || S32 == 32 || (S32 == 64 && G != 2));
+}
+
+// Modulus and exponent of a private-key exponentiation per prime: kind 4
+// r^(Q mod (P-1)) mod P, kind 0 t^P mod P^2, kind 2 c^(P-1) mod P^2.
+static PowArgs pow_args(const DKey &k, int kind, const uint32_t *in, uint32_t in_stride, uint32_t in_limbs,
+                        uint32_t *out, uint32_t out_stride, uint64_t count, uint32_t *tabs) {
+  PowArgs a{};
+  for (int w = 0; w < 2; ++w) {
+    const DPrime &P = k.pr[w];
+    a.mod[w] = kind == 4 ? P.P : P.P2;
+    a.exp[w] = kind == 4 ? P.e_enc : (kind == 0 ? P.e_lift : P.e_dec);
+  }
+  a.in = in;
+  a.in_stride = in_stride;
+  a.in_limbs = in_limbs;
+  a.out = out;
+  a.out_stride = out_stride;
+  a.count = count;
+  a.tabs = tabs;
+  return a;
+}
+
+static hipError_t launch_pow(int S32, bool ct, PowArgs a, const PowLaunch &l, hipStream_t s) {
+  if (!pow_shape_valid(S32, l.G)) return hipErrorInvalidValue;
+  void *args[] = {&a};
+  return hipLaunchKernel(pow_kernel(S32, l.G, ct), dim3(l.grid), dim3(kBlockThreads), args, l.dyn, s);
+}
+
+hipError_t launch_pow_kind(int KP, const DKey &k, int kind, const uint32_t *in, uint32_t in_stride,
+                           uint32_t in_limbs, uint32_t *out, uint32_t out_stride, uint64_t count, uint32_t *tab,
+                           const PowLaunch &l, hipStream_t s) {
+  if (!count) return hipSuccess;
+  const int S32 = kind == 4 ? 16 * KP : 32 * KP;
+  return launch_pow(S32, k.ct != 0, pow_args(k, kind, in, in_stride, in_limbs, out, out_stride, count, tab), l, s);
+}
+
+hipError_t launch_enc_r(int KP, const DKey &k, uint64_t count, const uint32_t *r, uint64_t seed, uint64_t roff,
+                        uint32_t *tq, hipStream_t s) {
+  if (!count) return hipSuccess;
+  if (KP == 1)
+    hipLaunchKernelGGL(k_enc_r<1>, dim3(blocks_for(2 * count, 16)), dim3(kBlockThreads), 0, s, k, count, r, seed,
+                       roff, tq);
+  else
+    hipLaunchKernelGGL(k_enc_r<2>, dim3(blocks_for(2 * count, 16)), dim3(kBlockThreads), 0, s, k, count, r, seed,
+                       roff, tq);
+  return hipGetLastError();
+}
+
+hipError_t launch_dec_pre(int KP, const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *xpq, hipStream_t s) {
+  if (!count) return hipSuccess;
+  if (KP == 1)
+    hipLaunchKernelGGL(k_dec_pre<1>, dim3(blocks_for(2 * count, 16)), dim3(kBlockThreads), 0, s, k, ct, count, xpq);
+  else
+    hipLaunchKernelGGL(k_dec_pre<2>, dim3(blocks_for(2 * count, 16)), dim3(kBlockThreads), 0, s, k, ct, count, xpq);
+  return hipGetLastError();
+}
+
 template <int KP>
 static hipError_t enc_crt(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
-                          uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab, uint32_t grid1,
-                          int G1, uint32_t grid2, int G2, hipStream_t s) {
-  switch (G1) {
-    case 2: launch_p1<KP, 2>(k, count, r, seed, roff, tq, tab, grid1, s); break;
-    case 4: launch_p1<KP, 4>(k, count, r, seed, roff, tq, tab, grid1, s); break;
-    case 8: launch_p1<KP, 8>(k, count, r, seed, roff, tq, tab, grid1, s); break;
-    default: launch_p1<KP, 16>(k, count, r, seed, roff, tq, tab, grid1, s); break;
-  }
-  switch (G2) {
-    case 4: launch_p2<KP, 4>(k, m, count, tq, cpq, tab, grid2, s); break;
-    case 8: launch_p2<KP, 8>(k, m, count, tq, cpq, tab, grid2, s); break;
-    default: launch_p2<KP, 16>(k, m, count, tq, cpq, tab, grid2, s); break;
-  }
-  hipLaunchKernelGGL(k_enc_crt_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k,
+                          uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab,
+                          const PowLaunch &l1, const PowLaunch &l2, hipStream_t s) {
+  constexpr int SP = 16 * KP, SP2 = 32 * KP;
+  hipLaunchKernelGGL(k_enc_r<KP>, dim3(blocks_for(2 * count, 16)), dim3(kBlockThreads), 0, s, k, count, r, seed,
+                     roff, tq);
+  hipError_t e = launch_pow(SP, k.ct != 0, pow_args(k, 4, tq, SP, SP, tq, SP, count, tab), l1, s);
+  if (e != hipSuccess) return e;
+  e = launch_pow(SP2, k.ct != 0, pow_args(k, 0, tq, SP, SP, cpq, SP2, count, tab), l2, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_enc_crt_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k, m,
                      (const uint32_t *)cpq, count, ct);
   return hipGetLastError();
 }
 hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
-                          uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab, uint32_t grid1,
-                          int G1, uint32_t grid2, int G2, hipStream_t s) {
+                          uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab,
+                          const PowLaunch &l1, const PowLaunch &l2, hipStream_t s) {
   if (!count) return hipSuccess;
-  return KP == 1 ? enc_crt<1>(k, m, count, r, seed, roff, tq, cpq, ct, tab, grid1, G1, grid2, G2, s)
-                 : enc_crt<2>(k, m, count, r, seed, roff, tq, cpq, ct, tab, grid1, G1, grid2, G2, s);
+  return KP == 1 ? enc_crt<1>(k, m, count, r, seed, roff, tq, cpq, ct, tab, l1, l2, s)
+                 : enc_crt<2>(k, m, count, r, seed, roff, tq, cpq, ct, tab, l1, l2, s);
 }
 
 hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
@@ -1297,33 +1352,23 @@ hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64
   return hipGetLastError();
 }
 
-template <int KP, int G>
-static void launch_dec_a(const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *mpq, uint32_t *tab,
-                         uint32_t grid, hipStream_t s) {
-  if (k.ct)
-    hipLaunchKernelGGL((k_dec_a<KP, G, true>), dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
-  else
-    hipLaunchKernelGGL((k_dec_a<KP, G>), dim3(grid), dim3(kBlockThreads), 0, s, k, ct, count, mpq, tab);
-}
 template <int KP>
-static hipError_t dec(const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *mpq, int64_t *m,
-                      uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, uint32_t grid, int G, hipStream_t s) {
-  if (G == 4)
-    launch_dec_a<KP, 4>(k, ct, count, mpq, tab, grid, s);
-  else if (G == 8)
-    launch_dec_a<KP, 8>(k, ct, count, mpq, tab, grid, s);
-  else
-    launch_dec_a<KP, 16>(k, ct, count, mpq, tab, grid, s);
+static hipError_t dec(const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *xpq, int64_t *m,
+                      uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, const PowLaunch &l, hipStream_t s) {
+  constexpr int SP2 = 32 * KP;
+  hipLaunchKernelGGL(k_dec_pre<KP>, dim3(blocks_for(2 * count, 16)), dim3(kBlockThreads), 0, s, k, ct, count, xpq);
+  hipError_t e = launch_pow(SP2, k.ct != 0, pow_args(k, 2, xpq, SP2, SP2, xpq, SP2, count, tab), l, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dec_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k,
-                     (const uint32_t *)mpq, count, m, raw, n_overflow);
+                     (const uint32_t *)xpq, count, m, raw, n_overflow);
   return hipGetLastError();
 }
-hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *mpq,
-                      int64_t *m, uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, uint32_t grid,
-                      int G, hipStream_t s) {
+hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *xpq,
+                      int64_t *m, uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, const PowLaunch &l,
+                      hipStream_t s) {
   if (!count) return hipSuccess;
-  return KP == 1 ? dec<1>(k, ct, count, mpq, m, raw, n_overflow, tab, grid, G, s)
-                 : dec<2>(k, ct, count, mpq, m, raw, n_overflow, tab, grid, G, s);
+  return KP == 1 ? dec<1>(k, ct, count, xpq, m, raw, n_overflow, tab, l, s)
+                 : dec<2>(k, ct, count, xpq, m, raw, n_overflow, tab, l, s);
 }
 
 hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
@@ -1389,47 +1434,20 @@ uint32_t ct_div_batch(uint64_t count) {
   return (uint32_t)std::max<uint64_t>(1, (count + groups - 1) / groups);
 }
 
-static int gidx(int G) { return G == 2 ? 0 : (G == 4 ? 1 : (G == 8 ? 2 : 3)); }
-
 template <int KP>
-static const void *kernel_of(int kind, int G) {
-  switch (kind) {
-    case 0:
-      return G == 4 ? (const void *)k_enc_p2<KP, 4> : G == 8 ? (const void *)k_enc_p2<KP, 8>
-                                                             : (const void *)k_enc_p2<KP, 16>;
-    case 1: return (const void *)k_enc_pub<KP>;
-    case 2:
-      return G == 4 ? (const void *)k_dec_a<KP, 4> : G == 8 ? (const void *)k_dec_a<KP, 8>
-                                                            : (const void *)k_dec_a<KP, 16>;
-    case 4:
-      return G == 2 ? (const void *)k_enc_p1<KP, 2> : G == 4 ? (const void *)k_enc_p1<KP, 4>
-                      : G == 8 ? (const void *)k_enc_p1<KP, 8> : (const void *)k_enc_p1<KP, 16>;
-    default: return (const void *)k_hist_chunk<KP, kHistGroup>;
-  }
+static const void *kernel_of(int kind) {
+  return kind == 1 ? (const void *)k_enc_pub<KP> : (const void *)k_hist_chunk<KP, kHistGroup>;
 }
 
-uint32_t resident_blocks(int KP, int kind, int G) {
-  static uint32_t cache[2][5][4] = {};
-  uint32_t &c = cache[KP - 1][kind][gidx(G)];
+uint32_t resident_blocks(int KP, int kind) {
+  static uint32_t cache[2][5] = {};
+  uint32_t &c = cache[KP - 1][kind];
   if (c) return c;
-  c = occupancy_blocks(KP == 1 ? kernel_of<1>(kind, G) : kernel_of<2>(kind, G));
+  c = occupancy_blocks(KP == 1 ? kernel_of<1>(kind) : kernel_of<2>(kind));
   return c;
 }
 
-uint64_t table_bytes_per_block(int KP, int kind, int G) {
-  // limbs of the modulus the kernel's exponentiation tables work in (the
-  // CRT kernels' tables hold radix-2^29 limbs)
-  const uint64_t S = (uint64_t)he29::limbs_for_group(kind == 1 ? 64 * KP : (kind == 4 ? 16 * KP : 32 * KP),
-                                                    kind == 1 ? 16 : G);
-  return (uint64_t)(kBlockThreads / G) * kTable * S * sizeof(uint32_t);
-}
-
-// Group width for a CRT exponentiation kernel (kind 0 encryption, 2
-// decryption) over `count` ciphertexts: the narrowest group (more limbs per
-// lane, less cross-lane work per product) whose launch still gives every
-// SIMD at least two waves; below that, wider groups buy parallelism.
-int pick_group(int KP, int kind, uint64_t count) {
-  (void)KP;
+static int device_cus() {
   static int cus = 0;
   if (!cus) {
     int dev = 0;
@@ -1437,8 +1455,61 @@ int pick_group(int KP, int kind, uint64_t count) {
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
       cus = 1;
   }
-  const uint64_t need = 2ull * 4 * (uint64_t)cus;  // two waves on each of the 4 SIMDs per CU
-  // the mod-P kernel of encryption (kind 4) also has 2-lane groups
+  return cus;
+}
+
+// Resident blocks of k_pow<S32, G> on the device with `dyn` bytes of dynamic LDS.
+uint32_t pow_resident_blocks(int S32, int G, uint32_t dyn) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, uint32_t>, uint32_t> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({S32, G, dyn});
+  if (it != cache.end()) return it->second;
+  int nb = 0;
+  if (!pow_shape_valid(S32, G) ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, pow_kernel(S32, G, false), kBlockThreads, dyn) !=
+          hipSuccess ||
+      nb < 1)
+    nb = 1;
+  const uint32_t r = (uint32_t)(nb * device_cus());
+  cache[{S32, G, dyn}] = r;
+  return r;
+}
+
+// Dynamic LDS that caps k_pow<S32, G> at `waves` blocks (= waves per SIMD)
+// per compute unit: enough that waves + 1 blocks do not fit.  0 when waves
+// is 0 or the kernel's own occupancy is at most `waves`.
+uint32_t pow_dyn_lds(int S32, int G, int waves) {
+  if (waves <= 0 || !pow_shape_valid(S32, G)) return 0;
+  if ((int)(pow_resident_blocks(S32, G, 0) / (uint32_t)device_cus()) <= waves) return 0;
+  int dev = 0, lds_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess ||
+      hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
+      lds_cu <= 0)
+    return 0;
+  hipFuncAttributes fa{};
+  if (hipFuncGetAttributes(&fa, pow_kernel(S32, G, false)) != hipSuccess) return 0;
+  const int64_t per_block = lds_cu / (waves + 1) + 1;
+  const int64_t dyn = per_block - (int64_t)fa.sharedSizeBytes;
+  return dyn > 0 ? (uint32_t)((dyn + 255) / 256 * 256) : 0u;
+}
+
+uint64_t table_bytes_per_block(int KP, int kind, int G) {
+  // limbs of the modulus the kernel's exponentiation tables work in
+  // (radix-2^29 limbs); kind 1 the public-key kernel at 16-lane groups
+  const uint64_t S = (uint64_t)he29::limbs_for_group(kind == 1 ? 64 * KP : (kind == 4 ? 16 * KP : 32 * KP),
+                                                    kind == 1 ? 16 : G);
+  return (uint64_t)(kBlockThreads / G) * kTable * S * sizeof(uint32_t);
+}
+
+// Group width for a private-key exponentiation (kind 4 mod P, 0 lift, 2
+// decryption) over `count` ciphertexts: the narrowest group (more limbs per
+// lane, less cross-lane work per product) whose launch still gives every
+// SIMD at least two waves; below that, wider groups buy parallelism.
+int pick_group(int KP, int kind, uint64_t count) {
+  (void)KP;
+  const uint64_t need = 2ull * 4 * (uint64_t)device_cus();  // two waves on each of the 4 SIMDs per CU
+  // the mod-P exponentiation (kind 4) also has 2-lane groups
   for (int G : {2, 4, 8}) {
     if (G == 2 && kind != 4) continue;
     const uint64_t waves = 2 * ((count + 64 / G - 1) / (64 / G));

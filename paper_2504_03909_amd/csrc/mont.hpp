@@ -35,8 +35,16 @@ constexpr int kWindow = 5;                 // fixed-window exponentiation width
 constexpr int kTable = 1 << kWindow;       // entries per window table
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+// The lane's index in its group.  Opaque to the optimiser (an empty volatile
+// asm), so that addresses derived from it are recomputed where they are used
+// instead of being hoisted out of the persistent loops, where the kernels
+// have no registers to keep them and would spill them.
 template <int G = 16>
-__device__ __forceinline__ uint32_t glane() { return __lane_id() & (G - 1u); }
+__device__ __forceinline__ uint32_t glane() {
+  uint32_t l = __lane_id() & (G - 1u);
+  asm volatile("" : "+v"(l));
+  return l;
+}
 
 // ---- DPP group operations -------------------------------------------------
 // Every lane of the group reads the group's first / last lane.

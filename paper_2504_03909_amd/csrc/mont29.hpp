@@ -36,6 +36,16 @@ namespace he {
 
 constexpr uint32_t kMask29 = (1u << he29::kBits) - 1u;
 
+// f(integral_constant<I>), ..., f(integral_constant<N-1>): a loop whose index
+// is a compile-time constant in the body.
+template <int I, int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+  if constexpr (I < N) {
+    f(std::integral_constant<int, I>{});
+    static_for<I + 1, N>(f);
+  }
+}
+
 template <int K>
 struct Mod29 {
   uint32_t n[K];  // this lane's 29-bit limbs of N
@@ -172,14 +182,13 @@ __device__ __forceinline__ void mm29_lds(uint32_t (&t)[K], const uint32_t *a_lds
   for (int j = 0; j + 1 < K; ++j) C[j] = 0;
 #pragma unroll 1
   for (int i0 = 0; i0 < S; i0 += U) {
-    uint32_t av[U];
-#pragma unroll
-    for (int h = 0; h < U; h += 2) {
-      const uint2 v = *reinterpret_cast<const uint2 *>(a_lds + i0 + h);
-      av[h] = v.x; av[h + 1] = v.y;
-    }
-#pragma unroll
-    for (int s = 0; s < U; ++s) step29<K, G>(C, top, av[s], b, M);
+    // multiplier limbs two at a time, read right before their steps
+    uint2 v;
+    static_for<0, U>([&](auto sc) {
+      constexpr int s = decltype(sc)::value;
+      if constexpr (s % 2 == 0) v = *reinterpret_cast<const uint2 *>(a_lds + i0 + s);
+      step29<K, G>(C, top, s % 2 == 0 ? v.x : v.y, b, M);
+    });
   }
   C[K - 1] = top;
   // settle: one carry pass in the lane, the lane's carry (below 2^36) into
@@ -223,14 +232,6 @@ template <int K>
 __host__ __device__ constexpr bool sq_keeps(int x, int y) {
   const int d = ((y - x) % K + K) % K;
   return K % 2 ? (d >= 1 && d <= (K - 1) / 2) : ((d >= 1 && d < K / 2) || (d == K / 2 && x < K / 2));
-}
-
-template <int I, int N, typename F>
-__device__ __forceinline__ void static_for(F &&f) {
-  if constexpr (I < N) {
-    f(std::integral_constant<int, I>{});
-    static_for<I + 1, N>(f);
-  }
 }
 
 // One squaring step for multiplier limb a_i (i mod K = X): a2 = 2 a_i for the

@@ -29,7 +29,7 @@ EXPORTED = (
     "he_hist_autotune", "he_hist_plan_create", "he_hist_plan_launch", "he_hist_plan_free",
     "he_obfuscators", "he_encrypt_obfuscated", "he_hist_subtract", "he_split_find",
     "he_hist_aggregate_counted", "he_ct_mul", "he_pack_slots", "he_pack", "he_decrypt_packed",
-    "he_decrypt_noalloc", "he_key_set_constant_time",
+    "he_decrypt_noalloc", "he_key_set_constant_time", "he_crt_autotune",
 )
 
 
@@ -94,6 +94,8 @@ _last_error = _sig("he_last_error", ctypes.c_char_p, [])
 _autotune = _sig("he_hist_autotune", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32,
                                             ctypes.POINTER(_u32), ctypes.POINTER(_u32),
                                             ctypes.POINTER(ctypes.c_float), _vp])
+_crt_autotune = _sig("he_crt_autotune", _i32, [_vp, _u64, _u64, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float),
+                                               _vp])
 _plan_create = _sig("he_hist_plan_create", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32, _u32,
                                                   _u32, ctypes.POINTER(_vp)])
 _plan_launch = _sig("he_hist_plan_launch", _i32, [_vp, _vp])
@@ -383,6 +385,17 @@ def hist_autotune(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = H
     _check(_autotune(key.handle, _ptr(ct), ct.shape[0], form, arr, len(jobs), ctypes.byref(c),
                      ctypes.byref(sp), ctypes.byref(ms), _stream(stream)))
     return int(c.value), int(sp.value), float(ms.value)
+
+
+def crt_autotune(key: Key, enc_count: int, dec_count: int, stream=None):
+    """Tunes the launch shapes of the private-key exponentiations for these
+    counts (see he_crt_autotune); returns {kind: (lanes, waves, ms)} for
+    "mod_p", "lift" and "decrypt"."""
+    choice = (_u32 * 6)()
+    ms = (ctypes.c_float * 3)()
+    _check(_crt_autotune(key.handle, enc_count, dec_count, choice, ms, _stream(stream)))
+    return {name: (int(choice[2 * i]), int(choice[2 * i + 1]), float(ms[i]))
+            for i, name in enumerate(("mod_p", "lift", "decrypt"))}
 
 
 class HistPlan:

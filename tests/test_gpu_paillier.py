@@ -233,6 +233,31 @@ def test_constant_time_exponentiations(he, bits, seed):
     k.close()
 
 
+def test_crt_autotune_keeps_results(he):
+    """The exponentiation autotuner picks a built shape for each kind, and
+    encryption and decryption at the tuned shapes stay exact: sampled
+    ciphertexts equal the oracle's, every decryption equals its plaintext."""
+    bits = 2048
+    sk = oracle_key(bits, 2)
+    pk = sk.public
+    k = gpu_key(bits, 2)
+    enc_count, dec_count = 5003, 3001
+    say(f"crt autotune {enc_count}/{dec_count}")
+    tuned = he.crt_autotune(k, enc_count, dec_count)
+    for kind, (lanes, waves, ms) in tuned.items():
+        assert lanes in (2, 4, 8, 16) and waves in (0, 2, 3) and ms > 0, (kind, lanes, waves, ms)
+    assert tuned["lift"][0] != 2 and tuned["decrypt"][0] != 2
+    rng = np.random.default_rng(77)
+    m = rng.integers(-(1 << 62), 1 << 62, size=enc_count, dtype=np.int64)
+    ct = he.encrypt(k, dev(m), seed=5)
+    dm, _, ovf = he.decrypt(k, ct[:dec_count])
+    assert host(dm).tolist() == m[:dec_count].tolist() and int(host(ovf)[0]) == 0
+    pick = rng.choice(enc_count, size=5, replace=False)
+    want = pool.encrypt_many(pk, [int(m[i]) % pk.n for i in pick],
+                             [P.seeded_r(pk.n, bits, 5, int(i)) for i in pick])
+    assert he.limbs_to_ints(host(ct)[pick]) == want
+
+
 # ---------------------------------------------------------- decryption
 @pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
 def test_decrypt_exact(he, bits, seed):

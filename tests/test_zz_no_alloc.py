@@ -77,7 +77,7 @@ def test_noalloc_decrypt_refuses_counts_beyond_its_scratch(setup):
     import torch
     he, key, _ = setup
     say("he_decrypt_noalloc size limit (host-side refusal)")
-    limit = (1 << 23) // key.limbs
+    limit = (1 << 22) // key.limbs
     ct = torch.zeros((1, 2 * key.limbs), dtype=torch.int32, device="cuda")
     m = torch.zeros(1, dtype=torch.int64, device="cuda")
     rc = he._decrypt_noalloc(key.handle, he._ptr(ct), limit + 1, he._ptr(m), None, None, None)

@@ -272,8 +272,9 @@ def main():
     # Setup: one encryption of the gradients so the autotuner can pick the
     # histogram work shape for this shape class (used by every step below).
     he.encrypt(key, he.encode(grads), seed=R_SEED, out=ct.view(-1, 2 * L))
-    tuned_chunk, tuned_split, tuned_ms = (he.hist_autotune(key, ct, [he.Job(idx, bins, K)])
-                                          if args.chunk == 0 else (args.chunk, 2, None))
+    hist_tune = (he.hist_autotune(key, ct, [he.Job(idx, bins, K)]) if args.chunk == 0
+                 else he.HistTune(args.chunk, 2, 16, 0, None))
+    tuned_chunk, tuned_split = hist_tune.chunk, hist_tune.split
     # launch shapes of the exponentiations (lanes per integer, waves per SIMD)
     # for 200,000 encryptions and 16,384 decryptions, tuned before timing
     exp_shapes = he.crt_autotune(key, 2 * M, J * K * 2)
@@ -385,6 +386,7 @@ def main():
                         "encode + encrypt 200000 + encrypted histogram + CRT decrypt 16384",
             "key_bits": KEY_BITS, "samples": M, "features": J, "bins": K, "r": "seeded",
             "encrypt_path": "crt", "hist_chunk": tuned_chunk, "hist_split": tuned_split,
+            "hist_lanes": hist_tune.lanes, "hist_waves_per_simd": hist_tune.waves or "own occupancy",
             "hist_shape": "autotuned before timing" if args.chunk == 0 else "given",
             "exponentiation_shapes": {k: {"lanes": v[0], "waves_per_simd": v[1] or "own occupancy",
                                           "tuning_ms": round(v[2], 3)} for k, v in exp_shapes.items()},
@@ -587,7 +589,8 @@ def bench_batched(args, compact=False):
     jb = jobs()
     he.hist_aggregate(key, ctm, jb, form=he.HE_FORM_MONT, chunk=64)
     _, t_batch64 = _timed(lambda: he.hist_aggregate(key, ctm, jb, form=he.HE_FORM_MONT, chunk=64))
-    chunk, split, tune_ms = he.hist_autotune(key, ctm, jb, form=he.HE_FORM_MONT)
+    tune = he.hist_autotune(key, ctm, jb, form=he.HE_FORM_MONT)
+    chunk, split, tune_ms = tune.chunk, tune.split, tune.ms
     _, t_tuned = _timed(lambda: he.hist_aggregate(key, ctm, jb, form=he.HE_FORM_MONT))
     jc = jobs()
     plan = he.HistPlan(key, ctm, jc, form=he.HE_FORM_MONT)
@@ -608,10 +611,12 @@ def bench_batched(args, compact=False):
             "sample_adds_per_s": {"one_job_per_launch": round(contrib / t_single, 1),
                                   "graph_replay": round(contrib / t_graph, 1)},
             "alu_frac_graph_replay": round(prod / t_graph / PEAK_MUL32_PER_S, 4),
-            "autotuned": {"chunk": chunk, "split": split, "ms": round(tune_ms, 3)},
+            "autotuned": {"chunk": chunk, "split": split, "lanes": tune.lanes,
+                          "waves_per_simd": tune.waves or "own occupancy", "ms": round(tune_ms, 3)},
             "results_identical": bool(same),
         }
-    _, cnt = he.hist_aggregate_counted(key, ctm, jobs(), form=he.HE_FORM_MONT, chunk=chunk, split=split)
+    _, cnt = he.hist_aggregate_counted(key, ctm, jobs(), form=he.HE_FORM_MONT, chunk=chunk, split=split,
+                                       lanes=tune.lanes, waves=tune.waves)
     mm_real, mm_done, mm_conv = (int(x) for x in cnt.cpu().tolist())
     return {
         "metric": "encrypted hist sample-adds/s at 2048-bit key",
@@ -622,7 +627,8 @@ def bench_batched(args, compact=False):
         "batched_chunk64_ms": round(t_batch64 * 1e3, 3),
         "batched_autotuned_ms": round(t_tuned * 1e3, 3),
         "graph_replay_ms": round(t_graph * 1e3, 3),
-        "autotuned": {"chunk": chunk, "split": split, "ms": round(tune_ms, 3)},
+        "autotuned": {"chunk": chunk, "split": split, "lanes": tune.lanes,
+                      "waves_per_simd": tune.waves or "own occupancy", "ms": round(tune_ms, 3)},
         "sample_adds_per_s": {"one_job_per_launch": round(contrib / t_single, 1),
                               "graph_replay": round(contrib / t_graph, 1)},
         "alu_frac_graph_replay": round(prod / t_graph / PEAK_MUL32_PER_S, 4),

@@ -209,15 +209,18 @@ int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint64_t rows, i
                          hipStream_t stream);
 
 /* Autotuner for the batched aggregation: times he_hist_aggregate on these
- * jobs (synchronising `stream`) for work-item lengths of 16..512 samples and
- * for one or two groups per (item, slot), and remembers the fastest choice
- * for the shape class (key size, total contributions and job count rounded
- * to powers of two, largest bin count).  Later he_hist_aggregate calls and
- * plans with chunk 0 in the same class use it.  The histograms are written
- * (correctly) several times.  Outputs are host pointers, each optional. */
+ * jobs (synchronising `stream`), first for work-item lengths of 16..512
+ * samples and one or two groups per (item, slot), then, at the best of
+ * those, for the product kernel's lanes per ciphertext (16, or 8 at
+ * 2048-bit keys) and waves per SIMD (its own occupancy, or 4, 3 or 2 by
+ * reserving LDS), and remembers the fastest choice for the shape class (key
+ * size, total contributions and job count rounded to powers of two, largest
+ * bin count).  Later he_hist_aggregate calls and plans with chunk 0 in the
+ * same class use it.  The histograms are written (correctly) several times.
+ * Outputs are host pointers, each optional; waves 0 = own occupancy. */
 int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
                      const he_hist_job *jobs, uint32_t n_jobs, uint32_t *chunk, uint32_t *split,
-                     float *ms, hipStream_t stream);
+                     uint32_t *lanes, uint32_t *waves, float *ms, hipStream_t stream);
 
 /* Autotuner for the private-key exponentiations: the CRT encryption's
  * exponentiation mod p and p-th-power lift mod p^2 (Sec. III-C: 2M
@@ -237,9 +240,12 @@ int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t rows, int c
 int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t dec_count, uint32_t *choice, float *ms,
                     hipStream_t stream);
 
-/* Work-count check of the aggregation: he_hist_aggregate_ex with an explicit
- * work-item length (chunk, 0 = default) and groups per item (split, 1 or 2),
- * that also adds, into the device counters mm_count[3] (not cleared):
+/* Work-count check of the aggregation: he_hist_aggregate_ex at an explicit
+ * work shape -- work-item length (chunk, 0 = default), groups per item
+ * (split, 1 or 2), lanes per ciphertext of the product kernel (lanes, 0 =
+ * 16; 8 only at 2048-bit keys, else HE_ERR_ARG) and its waves per SIMD
+ * (waves, 0 = own occupancy, at most 8) -- that also adds, into the device
+ * counters mm_count[3] (not cleared):
  *   [0] the Montgomery products that join two partial products of real
  *       samples -- for every (job, feature, slot) the node's sample count
  *       minus its number of non-empty bins, the algorithm's count;
@@ -249,7 +255,7 @@ int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t dec_count, u
  * The conversion of canonical input rows into Montgomery form is not counted. */
 int he_hist_aggregate_counted(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
                               const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk, uint32_t split,
-                              uint64_t *mm_count, hipStream_t stream);
+                              uint32_t lanes, uint32_t waves, uint64_t *mm_count, hipStream_t stream);
 
 /* A batched aggregation captured once into a HIP graph (all of its kernels,
  * with a workspace the plan owns), to be replayed with one launch, e.g. once

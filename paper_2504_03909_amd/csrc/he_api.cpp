@@ -570,6 +570,7 @@ struct HistLayout {
   size_t o_jobs = 0, o_counts = 0, o_offs = 0, o_cursor = 0, o_fch = 0, o_fitem = 0, o_ftot = 0,
          o_fbase = 0, o_nitems = 0, o_items = 0, o_perm = 0, o_part = 0, o_ctm = 0, bytes = 0;
   uint32_t chunk = 64, split = 2;
+  int G = he::kHistGroup, waves = 0;  // product kernel: lanes per ciphertext, waves per SIMD cap (0: none)
   bool convert = false;
 };
 
@@ -681,16 +682,23 @@ int enqueue_hist(const he_key *key, const uint32_t *ct, uint64_t rows, const His
     HE_TRY_HIP(he::launch_mont_convert(KP, key->dk, ct, rows * 2, dst, true, stream));
     ctm = dst;
   }
-  HE_TRY_HIP(he::launch_hist(KP, key->dk, ctm, lay.dj.data(), ws, he::resident_blocks(KP, 3), stream));
+  he::HistLaunch hl{lay.G, 0, 0};
+  if (!he::hist_shape_valid(KP, hl.G)) hl.G = he::kHistGroup;
+  hl.dyn = he::hist_dyn_lds(KP, hl.G, lay.waves);
+  hl.grid = he::hist_resident_blocks(KP, hl.G, hl.dyn);
+  HE_TRY_HIP(he::launch_hist(KP, key->dk, ctm, lay.dj.data(), ws, hl, stream));
   return HE_OK;
 }
 
 int hist_run(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form, const he_hist_job *jobs,
-             uint32_t n_jobs, uint32_t chunk, uint32_t split, hipStream_t stream, uint64_t *mm_count = nullptr) {
+             uint32_t n_jobs, uint32_t chunk, uint32_t split, hipStream_t stream, uint64_t *mm_count = nullptr,
+             int G = he::kHistGroup, int waves = 0) {
   if (n_jobs == 0) return key ? HE_OK : fail(HE_ERR_ARG, "null key");
   HistLayout lay;
   int rc = plan_layout(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, lay);
   if (rc) return rc;
+  lay.G = G;
+  lay.waves = waves;
   Workspace *w = workspace(stream);
   rc = ensure(w->hist, lay.bytes, stream);
   if (rc) return rc;
@@ -707,6 +715,7 @@ struct TuneKey {
 struct TuneVal {
   uint32_t chunk, split;
   float ms;
+  int G = he::kHistGroup, waves = 0;
 };
 std::mutex g_tune_mu;
 std::map<TuneKey, TuneVal> g_tune;
@@ -736,28 +745,37 @@ extern "C" int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint6
                                     const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk,
                                     hipStream_t stream) {
   uint32_t split = 2;
+  int G = he::kHistGroup, waves = 0;
   if (chunk == 0 && key && jobs && n_jobs) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(key, jobs, n_jobs));
     if (it != g_tune.end()) {
       chunk = it->second.chunk;
       split = it->second.split;
+      G = it->second.G;
+      waves = it->second.waves;
     }
   }
-  return hist_run(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, stream);
+  return hist_run(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, stream, nullptr, G, waves);
 }
 
 extern "C" int he_hist_aggregate_counted(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
                                          const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk, uint32_t split,
-                                         uint64_t *mm_count, hipStream_t stream) {
+                                         uint32_t lanes, uint32_t waves, uint64_t *mm_count, hipStream_t stream) {
   if (!mm_count) return fail(HE_ERR_ARG, "null mm_count");
   if (split != 1 && split != 2) return fail(HE_ERR_ARG, "split must be 1 or 2");
-  return hist_run(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, stream, mm_count);
+  if (!key) return fail(HE_ERR_ARG, "null key");
+  if (lanes == 0) lanes = he::kHistGroup;
+  if (!he::hist_shape_valid(kp_of(key), (int)lanes))
+    return fail(HE_ERR_ARG, "lanes must be 16, or 8 at 2048-bit keys");
+  if (waves > 8) return fail(HE_ERR_ARG, "waves must be 0 (own occupancy) to 8");
+  return hist_run(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, stream, mm_count, (int)lanes, (int)waves);
 }
 
 extern "C" int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
                                 const he_hist_job *jobs, uint32_t n_jobs, uint32_t *chunk_out,
-                                uint32_t *split_out, float *ms_out, hipStream_t stream) {
+                                uint32_t *split_out, uint32_t *lanes_out, uint32_t *waves_out, float *ms_out,
+                                hipStream_t stream) {
   if (!key || !jobs || n_jobs == 0) return fail(HE_ERR_ARG, "need a key and at least one job");
   static const uint32_t chunks[] = {16, 32, 64, 128, 256, 512};
   hipEvent_t e0, e1;
@@ -765,21 +783,36 @@ extern "C" int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t 
   HE_TRY_HIP(hipEventCreate(&e1));
   TuneVal best{64, 2, 1e30f};
   int rc = HE_OK;
+  auto trial = [&](uint32_t c, uint32_t split, int G, int waves) -> int {
+    int r = hist_run(key, ct, rows, ct_form, jobs, n_jobs, c, split, stream, nullptr, G, waves);  // warm-up
+    if (r) return r;
+    HE_TRY_HIP(hipEventRecord(e0, stream));
+    for (int k = 0; k < 2 && !r; ++k) r = hist_run(key, ct, rows, ct_form, jobs, n_jobs, c, split, stream, nullptr, G, waves);
+    if (r) return r;
+    HE_TRY_HIP(hipEventRecord(e1, stream));
+    HE_TRY_HIP(hipEventSynchronize(e1));
+    float ms = 0;
+    HE_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
+    ms /= 2;
+    if (ms < best.ms) best = TuneVal{c, split, ms, G, waves};
+    return HE_OK;
+  };
+  // work items first (chunk, groups per item) at 16 lanes and the kernel's
+  // own occupancy, then lanes per ciphertext and waves per SIMD at the best
   for (uint32_t split : {2u, 1u}) {
-    for (uint32_t c : chunks) {
-      rc = hist_run(key, ct, rows, ct_form, jobs, n_jobs, c, split, stream);  // warm-up, sizes workspace
-      if (rc) break;
-      HE_TRY_HIP(hipEventRecord(e0, stream));
-      for (int r = 0; r < 2 && !rc; ++r) rc = hist_run(key, ct, rows, ct_form, jobs, n_jobs, c, split, stream);
-      if (rc) break;
-      HE_TRY_HIP(hipEventRecord(e1, stream));
-      HE_TRY_HIP(hipEventSynchronize(e1));
-      float ms = 0;
-      HE_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
-      ms /= 2;
-      if (ms < best.ms) best = TuneVal{c, split, ms};
-    }
+    for (uint32_t c : chunks)
+      if ((rc = trial(c, split, he::kHistGroup, 0))) break;
     if (rc) break;
+  }
+  const int KP = kp_of(key);
+  const uint32_t bc = best.chunk, bs = best.split;
+  for (int G : {he::kHistGroup, 8}) {
+    if (rc || !he::hist_shape_valid(KP, G)) continue;
+    for (int waves : {0, 4, 3, 2}) {
+      if (G == he::kHistGroup && waves == 0) continue;  // measured above
+      if (waves && he::hist_dyn_lds(KP, G, waves) == 0) continue;  // no cap needed: same as waves 0
+      if ((rc = trial(bc, bs, G, waves))) break;
+    }
   }
   hipEventDestroy(e0);
   hipEventDestroy(e1);
@@ -790,6 +823,8 @@ extern "C" int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t 
   }
   if (chunk_out) *chunk_out = best.chunk;
   if (split_out) *split_out = best.split;
+  if (lanes_out) *lanes_out = (uint32_t)best.G;
+  if (waves_out) *waves_out = (uint32_t)best.waves;
   if (ms_out) *ms_out = best.ms;
   return HE_OK;
 }
@@ -922,11 +957,16 @@ extern "C" int he_hist_plan_create(const he_key *key, const uint32_t *ct, uint64
                                    he_hist_plan **out) {
   if (!out) return fail(HE_ERR_ARG, "null out");
   if (!key || !jobs || n_jobs == 0) return fail(HE_ERR_ARG, "need a key and at least one job");
+  int G = he::kHistGroup, waves = 0;
   if (chunk == 0) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto it = g_tune.find(tune_key(key, jobs, n_jobs));
     chunk = it != g_tune.end() ? it->second.chunk : 64;
     if (split == 0) split = it != g_tune.end() ? it->second.split : 2;
+    if (it != g_tune.end()) {
+      G = it->second.G;
+      waves = it->second.waves;
+    }
   }
   if (split == 0) split = 2;
   he_hist_plan *p = new (std::nothrow) he_hist_plan();
@@ -937,14 +977,17 @@ extern "C" int he_hist_plan_create(const he_key *key, const uint32_t *ct, uint64
     delete p;
     return rc;
   }
+  p->lay.G = G;
+  p->lay.waves = waves;
   if (hipMalloc(&p->ws, std::max<size_t>(p->lay.bytes, 256)) != hipSuccess) {
     hipGetLastError();
     delete p;
     return fail(HE_ERR_OOM, "plan workspace allocation of " + std::to_string(p->lay.bytes) + " bytes failed");
   }
-  // resident block counts are queried before capture (occupancy calls are
-  // not stream work, but keep capture free of anything but launches)
-  (void)he::resident_blocks(kp_of(key), 3);
+  // resident block counts and LDS caps are queried before capture
+  // (occupancy calls are not stream work, but keep capture free of anything
+  // but launches)
+  (void)he::hist_resident_blocks(kp_of(key), G, he::hist_dyn_lds(kp_of(key), G, waves));
   hipStream_t cs;
   if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess) {
     he_hist_plan_free(p);

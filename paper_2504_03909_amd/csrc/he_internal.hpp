@@ -146,8 +146,19 @@ hipError_t launch_dec_pre(int KP, const DKey &k, const uint32_t *ct, uint64_t co
 hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count,
                       uint32_t *xpq, int64_t *m, uint32_t *raw, uint32_t *n_overflow,
                       uint32_t *tab, const PowLaunch &l, hipStream_t s);
+// Launch shape of the histogram product kernel: lanes per ciphertext (16,
+// or 8 at 2048-bit keys), grid, and dynamic LDS reserved only to cap its
+// blocks per compute unit.
+struct HistLaunch {
+  int G;
+  uint32_t grid;
+  uint32_t dyn;
+};
+bool hist_shape_valid(int KP, int G);
+uint32_t hist_resident_blocks(int KP, int G, uint32_t dyn);
+uint32_t hist_dyn_lds(int KP, int G, int waves);
 hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *host_jobs,
-                       const HistWs &ws, uint32_t chunk_grid, hipStream_t s);
+                       const HistWs &ws, const HistLaunch &l, hipStream_t s);
 // Work items are chunks of `chunk` samples of one (feature, bin); with
 // split 2 one wave takes one item (two groups per slot, halves combined),
 // with split 1 one wave takes two items (one group per slot).

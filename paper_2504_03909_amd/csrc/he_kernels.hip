@@ -963,7 +963,8 @@ __global__ __launch_bounds__(256) void k_hist_scatter(HistWs ws) {
 // items, so the cross-lane steps of the arithmetic always run on the whole
 // wave.
 template <int KP, int G>
-__global__ __launch_bounds__(kBlockThreads, kHistWaves) void k_hist_chunk(DKey key, const uint32_t *__restrict__ ctm,
+__global__ __launch_bounds__(kBlockThreads, G == 16 ? kHistWaves : 3) void k_hist_chunk(DKey key,
+                                                                                    const uint32_t *__restrict__ ctm,
                                                                       HistWs ws) {
   constexpr int S = 64 * KP, K32 = S / G, GW = 64 / G;
   constexpr int S29 = he29::limbs_for_group(S, G), K = S29 / G, ROW = S29 > S ? S29 : S;
@@ -1380,7 +1381,7 @@ hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {
 
 template <int KP>
 static hipError_t hist(const DKey &k, const uint32_t *ctm, const DJob *host_jobs, const HistWs &ws,
-                       uint32_t chunk_grid, hipStream_t s) {
+                       const HistLaunch &l, hipStream_t s) {
   hipError_t e = launch_fill(ws.counts, ws.total_fb, 0u, s);
   if (e != hipSuccess) return e;
   for (uint32_t j0 = 0; j0 < ws.n_jobs; j0 += kJobsPerSetup) {
@@ -1396,15 +1397,24 @@ static hipError_t hist(const DKey &k, const uint32_t *ctm, const DJob *host_jobs
   hipLaunchKernelGGL(k_hist_items, dim3((uint32_t)ws.total_f), dim3(256), 0, s, ws);
   if (ws.total_blocks)
     hipLaunchKernelGGL(k_hist_scatter, dim3((uint32_t)ws.total_blocks), dim3(256), 0, s, ws);
-  hipLaunchKernelGGL((k_hist_chunk<KP, kHistGroup>), dim3(chunk_grid), dim3(kBlockThreads), 0, s, k, ctm, ws);
+  bool narrow = false;
+  if constexpr (KP == 2) {
+    if (l.G == 8) {
+      hipLaunchKernelGGL((k_hist_chunk<KP, 8>), dim3(l.grid), dim3(kBlockThreads), l.dyn, s, k, ctm, ws);
+      narrow = true;
+    }
+  }
+  if (!narrow)
+    hipLaunchKernelGGL((k_hist_chunk<KP, kHistGroup>), dim3(l.grid), dim3(kBlockThreads), l.dyn, s, k, ctm, ws);
   constexpr uint32_t entries_per_block = 4 * (64 / kHistGroup) / 4;
   const uint32_t fgrid = (uint32_t)std::min<uint64_t>(blocks_for(ws.total_fb, entries_per_block), 1u << 20);
   hipLaunchKernelGGL((k_hist_final<KP, kHistGroup>), dim3(fgrid), dim3(kBlockThreads), 0, s, k, ws);
   return hipGetLastError();
 }
 hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *host_jobs,
-                       const HistWs &ws, uint32_t chunk_grid, hipStream_t s) {
-  return KP == 1 ? hist<1>(k, ctm, host_jobs, ws, chunk_grid, s) : hist<2>(k, ctm, host_jobs, ws, chunk_grid, s);
+                       const HistWs &ws, const HistLaunch &l, hipStream_t s) {
+  if (!hist_shape_valid(KP, l.G)) return hipErrorInvalidValue;
+  return KP == 1 ? hist<1>(k, ctm, host_jobs, ws, l, s) : hist<2>(k, ctm, host_jobs, ws, l, s);
 }
 
 hipError_t launch_probe_mul(uint64_t iters, uint32_t grid, uint32_t *sink, hipStream_t s) {
@@ -1479,19 +1489,54 @@ uint32_t pow_resident_blocks(int S32, int G, uint32_t dyn) {
 // Dynamic LDS that caps k_pow<S32, G> at `waves` blocks (= waves per SIMD)
 // per compute unit: enough that waves + 1 blocks do not fit.  0 when waves
 // is 0 or the kernel's own occupancy is at most `waves`.
-uint32_t pow_dyn_lds(int S32, int G, int waves) {
-  if (waves <= 0 || !pow_shape_valid(S32, G)) return 0;
-  if ((int)(pow_resident_blocks(S32, G, 0) / (uint32_t)device_cus()) <= waves) return 0;
+// Dynamic LDS that makes at most `waves` blocks of `fn` fit a compute unit
+// (0 if its own occupancy `natural` is already at most that).
+static uint32_t cap_dyn_lds(const void *fn, int natural, int waves) {
+  if (waves <= 0 || natural <= waves) return 0;
   int dev = 0, lds_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess ||
       hipDeviceGetAttribute(&lds_cu, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) != hipSuccess ||
       lds_cu <= 0)
     return 0;
   hipFuncAttributes fa{};
-  if (hipFuncGetAttributes(&fa, pow_kernel(S32, G, false)) != hipSuccess) return 0;
+  if (hipFuncGetAttributes(&fa, fn) != hipSuccess) return 0;
   const int64_t per_block = lds_cu / (waves + 1) + 1;
   const int64_t dyn = per_block - (int64_t)fa.sharedSizeBytes;
   return dyn > 0 ? (uint32_t)((dyn + 255) / 256 * 256) : 0u;
+}
+
+uint32_t pow_dyn_lds(int S32, int G, int waves) {
+  if (waves <= 0 || !pow_shape_valid(S32, G)) return 0;
+  return cap_dyn_lds(pow_kernel(S32, G, false), (int)(pow_resident_blocks(S32, G, 0) / (uint32_t)device_cus()),
+                     waves);
+}
+
+// Histogram product kernel shapes: 16-lane groups, or 8-lane groups where
+// their Montgomery form is the 16-lane one (2048-bit keys: S29 = 144 for
+// both; at 1024 bits the 8-lane R' differs).
+bool hist_shape_valid(int KP, int G) { return G == 16 || (G == 8 && KP == 2); }
+static const void *hist_kernel(int KP, int G) {
+  if (KP == 2 && G == 8) return (const void *)k_hist_chunk<2, 8>;
+  return KP == 1 ? (const void *)k_hist_chunk<1, kHistGroup> : (const void *)k_hist_chunk<2, kHistGroup>;
+}
+uint32_t hist_resident_blocks(int KP, int G, uint32_t dyn) {
+  static std::mutex mu;
+  static std::map<std::tuple<int, int, uint32_t>, uint32_t> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find({KP, G, dyn});
+  if (it != cache.end()) return it->second;
+  int nb = 0;
+  if (!hist_shape_valid(KP, G) ||
+      hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, hist_kernel(KP, G), kBlockThreads, dyn) != hipSuccess ||
+      nb < 1)
+    nb = 1;
+  const uint32_t r = (uint32_t)(nb * device_cus());
+  cache[{KP, G, dyn}] = r;
+  return r;
+}
+uint32_t hist_dyn_lds(int KP, int G, int waves) {
+  if (waves <= 0 || !hist_shape_valid(KP, G)) return 0;
+  return cap_dyn_lds(hist_kernel(KP, G), (int)(hist_resident_blocks(KP, G, 0) / (uint32_t)device_cus()), waves);
 }
 
 uint64_t table_bytes_per_block(int KP, int kind, int G) {

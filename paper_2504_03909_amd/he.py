@@ -8,6 +8,7 @@ the shared library is missing, importing this module raises.
 """
 from __future__ import annotations
 
+import collections
 import ctypes
 import os
 from dataclasses import dataclass
@@ -85,15 +86,15 @@ _sub = _sig("he_hist_subtract", _i32, [_vp, _vp, _vp, _u64, _u32, _vp, _vp, _vp]
 _to_mont = _sig("he_to_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
 _from_mont = _sig("he_from_mont", _i32, [_vp, _vp, _u64, _vp, _vp])
 _hist_counted = _sig("he_hist_aggregate_counted", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32,
-                                                         _u32, _u32, _vp, _vp])
+                                                         _u32, _u32, _u32, _u32, _vp, _vp])
 _hist = _sig("he_hist_aggregate_ex", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32, _u32, _vp])
 _decrypt = _sig("he_decrypt", _i32, [_vp, _vp, _u64, _vp, _vp, _vp, _vp])
 _decrypt_noalloc = _sig("he_decrypt_noalloc", _i32, [_vp, _vp, _u64, _vp, _vp, _vp, _vp])
 _probe = _sig("he_probe_int_mul", _i32, [_u64, _u32, ctypes.POINTER(_u64), _vp])
 _last_error = _sig("he_last_error", ctypes.c_char_p, [])
 _autotune = _sig("he_hist_autotune", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32,
-                                            ctypes.POINTER(_u32), ctypes.POINTER(_u32),
-                                            ctypes.POINTER(ctypes.c_float), _vp])
+                                            ctypes.POINTER(_u32), ctypes.POINTER(_u32), ctypes.POINTER(_u32),
+                                            ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float), _vp])
 _crt_autotune = _sig("he_crt_autotune", _i32, [_vp, _u64, _u64, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float),
                                                _vp])
 _plan_create = _sig("he_hist_plan_create", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32, _u32,
@@ -365,26 +366,31 @@ def hist_aggregate(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = 
 
 
 def hist_aggregate_counted(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = HE_FORM_CANONICAL,
-                           chunk: int = 0, split: int = 2, stream=None):
-    """hist_aggregate plus the work counters: returns (hists, [real products,
-    executed products, conversions out of Montgomery form])."""
+                           chunk: int = 0, split: int = 2, lanes: int = 0, waves: int = 0, stream=None):
+    """hist_aggregate at an explicit work shape (chunk, groups per item,
+    lanes per ciphertext, waves per SIMD; 0 = default) plus the work
+    counters: returns (hists, [real products, executed products, conversions
+    out of Montgomery form])."""
     arr = (HistJob * len(jobs))(*[j.as_c(key) for j in jobs])
     cnt = torch.zeros(3, dtype=torch.int64, device=ct.device)
-    _check(_hist_counted(key.handle, _ptr(ct), ct.shape[0], form, arr, len(jobs), chunk, split, _ptr(cnt),
-                         _stream(stream)))
+    _check(_hist_counted(key.handle, _ptr(ct), ct.shape[0], form, arr, len(jobs), chunk, split, lanes, waves,
+                         _ptr(cnt), _stream(stream)))
     return [j.hist for j in jobs], cnt
 
 
+HistTune = collections.namedtuple("HistTune", "chunk split lanes waves ms")
+
+
 def hist_autotune(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = HE_FORM_CANONICAL,
-                  stream=None):
-    """Times the batched aggregation of these jobs over the candidate
-    work-item shapes; returns (chunk, split, ms) of the fastest, which the
+                  stream=None) -> HistTune:
+    """Times the batched aggregation of these jobs over the candidate work
+    shapes; returns the fastest (chunk, split, lanes, waves, ms), which the
     library then uses for this shape class when chunk is 0."""
     arr = (HistJob * len(jobs))(*[j.as_c(key) for j in jobs])
-    c, sp, ms = _u32(), _u32(), ctypes.c_float()
+    c, sp, ln, wv, ms = _u32(), _u32(), _u32(), _u32(), ctypes.c_float()
     _check(_autotune(key.handle, _ptr(ct), ct.shape[0], form, arr, len(jobs), ctypes.byref(c),
-                     ctypes.byref(sp), ctypes.byref(ms), _stream(stream)))
-    return int(c.value), int(sp.value), float(ms.value)
+                     ctypes.byref(sp), ctypes.byref(ln), ctypes.byref(wv), ctypes.byref(ms), _stream(stream)))
+    return HistTune(int(c.value), int(sp.value), int(ln.value), int(wv.value), float(ms.value))
 
 
 def crt_autotune(key: Key, enc_count: int, dec_count: int, stream=None):

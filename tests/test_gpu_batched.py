@@ -154,8 +154,9 @@ def test_autotune_keeps_results(he, small):
     jobs = make_jobs(he, c["tables"], c["shapes"])
     he.hist_aggregate(c["k"], c["ct"], jobs, chunk=64)
     want = [j.hist.clone() for j in jobs]
-    chunk, split, ms = he.hist_autotune(c["k"], c["ct"], jobs)
+    chunk, split, lanes, waves, ms = he.hist_autotune(c["k"], c["ct"], jobs)
     assert chunk in (16, 32, 64, 128, 256, 512) and split in (1, 2) and ms > 0
+    assert lanes in (8, 16) and waves in (0, 2, 3, 4)
     for h, w in zip([j.hist for j in jobs], want):
         assert torch.equal(h, w)
     he.hist_aggregate(c["k"], c["ct"], jobs)  # chunk 0 -> tuned shape
@@ -200,6 +201,13 @@ def test_batched_64_jobs_2048(he):
     for j, hb in zip(jobs, batched):
         (alone,) = he.hist_aggregate(k, ctm, [he.Job(j.sample_idx, j.bins, j.n_bins)], form=he.HE_FORM_MONT)
         assert torch.equal(alone, hb)
+    # every work shape the autotuner can pick gives the same histograms
+    for lanes in (16, 8):
+        for waves in (0, 4, 3, 2):
+            say(f"64 jobs at lanes={lanes} waves={waves}")
+            hs, cnt = he.hist_aggregate_counted(k, ctm, make_jobs(he, tables, shapes), form=he.HE_FORM_MONT,
+                                                chunk=128, split=2, lanes=lanes, waves=waves)
+            assert all(torch.equal(h, hb) for h, hb in zip(hs, batched)), (lanes, waves)
     c = dict(bits=bits, M=M, r_seed=r_seed, sk=sk, k=k, m=m, ct=ct, tables=tables)
     order = np.argsort([sh["sample_idx"].size for sh in shapes])
     for n, ji in enumerate(order):

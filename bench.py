@@ -45,12 +45,12 @@ KEY_SEED, R_SEED, DATA_SEED = 2, 2024, 1
 # (v_mad_u64_u32) per lane per clock.
 PEAK_MUL32_PER_S = 256 * 64 * 2.4e9
 MI355X_HBM_BPS = 8.0e12
-# HBM-side bytes of one encryption launch (k_enc_p1 + k_enc_p2 + k_enc_crt_b
-# over 200,000 ciphertexts), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes
+# HBM-side bytes of one encryption launch (k_enc_r + k_pow mod p + k_pow lift
+# + k_enc_crt_b over 200,000 ciphertexts), from rocprofv3 FETCH_SIZE and WRITE_SIZE passes
 # scaled by a 256 MiB copy (profiles/enc_crt_2048_100k_counters.md), and the
 # digest of the kernel sources those passes ran on (kernel_sources_digest()).
 # The figure is reported only while the sources still have that digest.
-ENC_LAUNCH_TRAFFIC = {"bytes": 5.6182e10, "sources_sha256_16": "none"}
+ENC_LAUNCH_TRAFFIC = {"bytes": 5.1400e10, "sources_sha256_16": "a3e4d1d752456d96"}
 KERNEL_SOURCES = ("he_kernels.hip", "he_internal.hpp", "hist_bucket.hpp", "mont.hpp", "mont29.hpp",
                   "radix29.hpp")
 
@@ -410,7 +410,7 @@ def main():
         "step_latency_ms": {"p50": round(percentile(stage_ms["step"], 0.5), 3),
                             "p99": round(percentile(stage_ms["step"], 0.99), 3)},
         "roofline": {
-            "kernel": "k_enc_p1 + k_enc_p2 + k_enc_crt_b (CRT encryption)",
+            "kernel": "k_enc_r + k_pow (mod p) + k_pow (lift mod p^2) + k_enc_crt_b (CRT encryption)",
             "bound": "alu",
             "achieved": round(achieved / 1e12, 3),
             "peak": round(PEAK_MUL32_PER_S / 1e12, 3),

@@ -50,21 +50,22 @@ MI355X_HBM_BPS = 8.0e12
 # scaled by a 256 MiB copy (profiles/enc_crt_2048_100k_counters.md), and the
 # digest of the kernel sources those passes ran on (kernel_sources_digest()).
 # The figure is reported only while the sources still have that digest.
-ENC_LAUNCH_TRAFFIC = {"bytes": 5.1400e10, "sources_sha256_16": "a3e4d1d752456d96"}
+ENC_LAUNCH_TRAFFIC = {"bytes": 5.1400e10, "sources_sha256_16": "40a529b5c670a953"}
 KERNEL_SOURCES = ("he_kernels.hip", "he_internal.hpp", "hist_bucket.hpp", "mont.hpp", "mont29.hpp",
                   "radix29.hpp")
 
 
 def kernel_sources_digest() -> str:
     """First 16 hex digits of the SHA-256 of the kernel sources and the build
-    flags they compile with."""
+    flags they compile with (include paths relative to the repository, so the
+    digest is the same wherever the tree is checked out)."""
     import hashlib
     from paper_2504_03909_amd import build as B
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2504_03909_amd", "csrc", name), "rb") as f:
             h.update(name.encode() + b"\0" + f.read())
-    h.update(" ".join(B.COMMON).encode())
+    h.update(" ".join(f.replace(ROOT, ".") for f in B.COMMON).encode())
     return h.hexdigest()[:16]
 
 

@@ -7,13 +7,15 @@ all of them (seeded r, CRT path), the root node's encrypted histogram over
 ciphertexts.  Inputs (gradients, bins, sample list, key) are resident in HBM
 before timing starts.  Prints one JSON line, which also carries (after the
 timed steps) the 64-job batched comparison ("batched": one job per launch
-against graph replay of one persistent launch), the served request loop
-("served": a 2,000-request Poisson trace at 200 requests/s and a
-1,000-request trace at 0.8x the measured capacity, continuous batching
-against FIFO, p50/p99 latency) and the CPU oracle baseline.
+against graph replay of one persistent launch), the depth-6 tree over
+1,000,000 samples ("tree": encryption, one job per launch and one graph per
+level, decryption of every node), the served request loop ("served": a
+2,000-request Poisson trace at 200 requests/s and a 1,000-request trace at
+0.8x the measured capacity, continuous batching against FIFO, p50/p99
+latency) and the CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--no-batched] [--no-served]
+                    [--no-batched] [--no-served] [--no-tree]
 
 Other workloads (each prints its own JSON line; not the default):
     --workload tree      2048-bit, 1,000,000 samples, 64 x 256 Zipf bins, depth-6
@@ -208,6 +210,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="leave the 64-job batched comparison out of the line")
     ap.add_argument("--no-served", action="store_true", help="leave the served request loop out of the line")
+    ap.add_argument("--no-tree", action="store_true", help="leave the depth-6 tree (1,000,000 samples) out of the line")
     ap.add_argument("--workload", default="pass", choices=("pass", "tree", "batched", "served", "horizontal"))
     ap.add_argument("--requests", type=int, default=2000, help="requests of the served trace at --rate")
     ap.add_argument("--capacity-requests", type=int, default=1000,
@@ -451,6 +454,10 @@ def main():
     if not args.no_batched:
         print("[bench] batched: 64 uneven node jobs", file=sys.stderr, flush=True)
         line["batched"] = bench_batched(args, compact=True)
+    if not args.no_tree:
+        print("[bench] tree: 1,000,000 samples, depth 6, one job per launch", file=sys.stderr, flush=True)
+        line["tree"] = bench_tree(args, compact=True)
+        torch.cuda.empty_cache()
     if not args.no_served:
         print(f"[bench] served: {args.requests} requests at {args.rate:g}/s", file=sys.stderr, flush=True)
         line["served"] = bench_served(args, compact=True)
@@ -472,9 +479,11 @@ def _timed(fn, label=""):
     return out, dt
 
 
-def bench_tree(args):
+def bench_tree(args, compact=False):
     """2048-bit key, 1,000,000 samples, 64 features x 256 Zipf(1.1) bins,
-    depth-6 tree (63 nodes, seeded splits, direct aggregation of every node)."""
+    depth-6 tree (63 nodes, seeded splits, direct aggregation of every node).
+    compact: encryption, one job per launch and one graph per level, and the
+    decryption of every node only (the default line's sub-object)."""
     import numpy as np
     import torch
     from paper_2504_03909_amd import he, pipeline
@@ -494,6 +503,23 @@ def bench_tree(args):
     torch.cuda.synchronize()
     _, t_graph = _timed(lambda: [p.launch() for p in plans.plans], "tree graphs")
     same = all(torch.equal(a, b) for la, lb in zip(run_plain.hists, plans.hists) for a, b in zip(la, lb))
+    contrib = 2 * Jt * sum(int(n.numel()) for lvl in levels for n in lvl)
+    n_dec = 63 * Jt * Kt * 2
+    if compact:
+        del plans
+        _, t_dec = _timed(lambda: pipeline.decrypt_levels(key, run_plain), "tree decrypt")
+        return {
+            "workload": "2048-bit key, 1000000 samples, 64 features x 256 Zipf(1.1) bins, depth-6 tree "
+                        "(63 nodes), direct aggregation of every node",
+            "encrypt_s": round(t_enc, 3), "encryptions_per_s": round(2 * Mt / t_enc, 1),
+            "aggregate_one_job_per_launch_s": round(t_plain, 3),
+            "aggregate_per_level_graph_s": round(t_graph, 3),
+            "sample_adds_per_s": {"one_job_per_launch": round(contrib / t_plain, 1),
+                                  "graph": round(contrib / t_graph, 1)},
+            "decrypt_s": round(t_dec, 3), "decryptions_per_s": round(n_dec / t_dec, 1),
+            "graph_equals_one_job_per_launch": bool(same),
+            "total_s_one_job_per_launch": round(t_enc + t_plain + t_dec, 3),
+        }
     pipeline.aggregate_levels(res, levels[:2], bins, Kt, mode="sibling")  # warm-up
     run_sib, t_sib = _timed(lambda: pipeline.aggregate_levels(res, levels, bins, Kt, mode="sibling"),
                             "tree sibling")
@@ -531,10 +557,8 @@ def bench_tree(args):
     he.decrypt_packed(key, pk0, h0.numel() // h0.shape[-1], s0)
     _, t_pack1 = _timed(lambda: he.pack(key, h0))
     _, t_decp1 = _timed(lambda: he.decrypt_packed(key, pk0, h0.numel() // h0.shape[-1], s0))
-    contrib = 2 * Jt * sum(int(n.numel()) for lvl in levels for n in lvl)
     contrib_sib = 2 * Jt * (Mt + sum(min(int(lvl[i].numel()), int(lvl[i + 1].numel()))
                                      for lvl in levels[1:] for i in range(0, len(lvl), 2)))
-    n_dec = 63 * Jt * Kt * 2
     return {
         "metric": "Paillier encryptions/s + encrypted hist sample-adds/s at 2048-bit key",
         "workload": "2048-bit key, 1000000 samples, 64 features x 256 Zipf(1.1) bins, depth-6 tree "

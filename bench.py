@@ -86,12 +86,35 @@ def nwin(e: int) -> int:
     return max(1, -(-e.bit_length() // 5))
 
 
+def sliding_ops(e: int, width: int = 6):
+    """(general products, squarings) of the sliding-window exponentiation by
+    e: windows of up to `width` bits ending in a 1 bit, left to right, after
+    a table of the 2^(width-1) odd powers (one squaring for x^2 and one
+    product per further odd power)."""
+    mults, sqs = 2 ** (width - 1) - 1, 1
+    i, first = e.bit_length() - 1, True
+    while i >= 0:
+        if not (e >> i) & 1:
+            sqs += 1
+            i -= 1
+            continue
+        j = max(i - width + 1, 0)
+        while not (e >> j) & 1:
+            j += 1
+        if not first:
+            sqs += i - j + 1
+            mults += 1
+        first = False
+        i = j - 1
+    return mults, sqs
+
+
 def modexp_products(e: int, s: int) -> int:
-    """Products of one 5-bit fixed-window exponentiation mod an s-limb
-    modulus: 30 general products for the table, then per window after the
-    first 5 squarings and one general product."""
-    w = nwin(e) - 1
-    return (30 + w) * mm_products(s) + 5 * w * sq_products(s)
+    """Products of one exponentiation mod an s-limb modulus as the kernels
+    run it without constant-time table reads (sliding windows of up to 6
+    bits): general products at 2s^2 + s, squarings at s(s+1)/2 + s^2 + s."""
+    mults, sqs = sliding_ops(e)
+    return mults * mm_products(s) + sqs * sq_products(s)
 
 
 def crt_encrypt_products(p: int, q: int, L: int) -> int:

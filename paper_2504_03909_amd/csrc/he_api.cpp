@@ -53,7 +53,9 @@ he::DMod mk_mod(const uint32_t *base, const hekey::ModOff &o) {
   }
   return m;
 }
-he::DExp mk_exp(const uint32_t *base, const hekey::ExpOff &o) { return he::DExp{base + o.e, o.nwin}; }
+he::DExp mk_exp(const uint32_t *base, const hekey::ExpOff &o) {
+  return he::DExp{base + o.e, o.nwin, base + o.ops, o.nops};
+}
 
 // Builds every constant of the key and uploads them to the current device.
 int build_key(he_key *k) {

@@ -19,10 +19,13 @@ struct DMod {
   const uint32_t *R2_29[he29::kVariants]; // R'^2 mod N
 };
 
-// Exponent as limbs with one zero limb of padding, and its window count.
+// Exponent as limbs with one zero limb of padding and its fixed-window
+// count, and its sliding-window schedule (keysetup.hpp, sliding_schedule).
 struct DExp {
   const uint32_t *e;
   int nwin;
+  const uint32_t *ops;
+  int nops;
 };
 
 // Per-prime constants for the CRT paths; P is this prime, Q the other one.

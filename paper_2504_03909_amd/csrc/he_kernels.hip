@@ -127,7 +127,7 @@ __global__ __launch_bounds__(kBlockThreads, 3) void k_pow(PowArgs a) {
   uint32_t *lds = lds_all + (threadIdx.x / G) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = a.tabs + (gw * NG + g) * (uint64_t)(kTable * S29);
+  uint32_t *tab = a.tabs + (gw * NG + g) * (uint64_t)((kTable + 1) * S29);
   const uint64_t nunits = 2 * ((a.count + NG - 1) / NG);
   for (uint64_t qd = gw; qd < nunits; qd += nw) {
     const int which = (int)(qd & 1);
@@ -137,7 +137,7 @@ __global__ __launch_bounds__(kBlockThreads, 3) void k_pow(PowArgs a) {
     const uint64_t u = i * 2 + which;
     uint32_t x[K32];
     ld_part<K32, G>(x, a.in + u * a.in_stride, (int)a.in_limbs);
-    pow29<K32, G>(x, a.exp[which].e, a.exp[which].nwin, tab, a.mod[which], lds, zeros, CT);
+    pow29<K32, G>(x, a.exp[which], tab, a.mod[which], lds, zeros, CT);
     if (valid) st<K32, G>(a.out + u * a.out_stride, x);
   }
 }
@@ -257,7 +257,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
   uint32_t *lds = lds_all + (wave_in_block() * 4 + g) * ROW;
   const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
   const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * 4 + g) * (uint64_t)(kTable * S29);
+  uint32_t *tab = tabs + (gw * 4 + g) * (uint64_t)((kTable + 1) * S29);
   const uint64_t nquads = (count + 3) / 4;
   const uint64_t W = (uint64_t)L / 2 + 1;
   const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
@@ -276,7 +276,7 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
     mont_mul<KN2>(x, x, c, M, lds);
     set_small(c, 1u);
     mont_mul<KN2>(x, x, c, M, lds);
-    pow29<KN2, 16>(x, key.e_n.e, key.e_n.nwin, tab, key.n2, lds, zeros, false);  // public exponent
+    pow29<KN2, 16>(x, key.e_n, tab, key.n2, lds, zeros, false);  // public exponent
     // f = 1 + (m mod n) n, exact (< n^2), in Montgomery form
     ld_part<KN2>(c, key.n.N, L);
     signed_mod<KN2>(f, m ? m[i] : 0, c);
@@ -1544,7 +1544,7 @@ uint64_t table_bytes_per_block(int KP, int kind, int G) {
   // (radix-2^29 limbs); kind 1 the public-key kernel at 16-lane groups
   const uint64_t S = (uint64_t)he29::limbs_for_group(kind == 1 ? 64 * KP : (kind == 4 ? 16 * KP : 32 * KP),
                                                     kind == 1 ? 16 : G);
-  return (uint64_t)(kBlockThreads / G) * kTable * S * sizeof(uint32_t);
+  return (uint64_t)(kBlockThreads / G) * (kTable + 1) * S * sizeof(uint32_t);
 }
 
 // Group width for a private-key exponentiation (kind 4 mod P, 0 lift, 2

@@ -3,6 +3,7 @@
 #pragma once
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "hostbn.hpp"
@@ -49,7 +50,43 @@ struct ModOff {  // Montgomery modulus N of S limbs, R = 2^(32 S)
 struct ExpOff {
   size_t e;
   int nwin;
+  size_t ops;  // sliding-window schedule (see sliding_schedule)
+  int nops;
 };
+
+// Sliding-window schedule of e >= 1 with windows of up to kSlideBits bits
+// whose lowest bit is 1 (Koc 1995, left to right): the first op loads the
+// odd power x^(2 k + 1) of its window (k in bits 0..7); every later op is
+// `nsq` squarings (bits 8..31) and then a multiplication by the odd power
+// of its window, or no multiplication when k = kSlideNoMul (the trailing
+// zero bits).  Evaluating e' = 2 k0 + 1, then e' = e' 2^nsq + (2 k + 1) per
+// op rebuilds e.  Empty for e = 0.
+constexpr int kSlideBits = 6;
+constexpr uint32_t kSlideNoMul = 0xFF;
+inline std::vector<uint32_t> sliding_schedule(const Limbs &e) {
+  std::vector<uint32_t> ops;
+  int i = (int)hebn::bit_length(e) - 1;
+  uint32_t pend = 0;
+  bool first = true;
+  while (i >= 0) {
+    if (!hebn::bit(e, (size_t)i)) {
+      ++pend;
+      --i;
+      continue;
+    }
+    int j = std::max(i - kSlideBits + 1, 0);
+    while (!hebn::bit(e, (size_t)j)) ++j;
+    uint32_t val = 0;
+    for (int b = i; b >= j; --b) val = (val << 1) | (uint32_t)hebn::bit(e, (size_t)b);
+    const uint32_t k = (val - 1) >> 1;
+    ops.push_back(first ? k : (((pend + (uint32_t)(i - j + 1)) << 8) | k));
+    first = false;
+    pend = 0;
+    i = j - 1;
+  }
+  if (pend) ops.push_back((pend << 8) | kSlideNoMul);
+  return ops;
+}
 struct PrimeOff {
   ModOff P, P2;
   ExpOff e_enc, e_lift, e_dec;
@@ -93,6 +130,11 @@ inline ExpOff put_exp(Blob &b, const Limbs &e, size_t limbs) {
   x.e = b.put(e, limbs, 1);
   const size_t bits = std::max<size_t>(hebn::bit_length(e), 1);
   x.nwin = (int)((bits + kWindowBits - 1) / kWindowBits);
+  const std::vector<uint32_t> ops = sliding_schedule(e);
+  x.nops = (int)ops.size();
+  x.ops = b.words.size();
+  b.words.insert(b.words.end(), ops.begin(), ops.end());
+  b.words.resize((b.words.size() + 3) & ~size_t(3), 0u);
   return x;
 }
 

@@ -465,17 +465,25 @@ __device__ __forceinline__ void tab_entry(uint32_t (&v)[K], const uint32_t *tab,
 }
 
 // x <- x^e mod N for canonical x < N in 32-bit limbs (K32 per lane), result
-// canonical.  Left-to-right fixed 5-bit windows over `nwin` windows in the
-// radix-2^29 Montgomery domain; a multiplication by the table entry is done
-// for every window, zero digits included, so the sequence of operations does
-// not depend on the exponent; with ct the table reads do not either (see
-// tab_entry), otherwise each window reads the entry its digit names.  `tab`:
-// this group's table, kTable entries of S29 words in global memory; `lds`:
-// this group's row of at least max(G K32, 2 S29) words; `zeros`: S29 zero
-// words in the row's LDS array (see sq29).
+// canonical, in the radix-2^29 Montgomery domain.  Two schedules, neither
+// with a branch on the exponent's bits inside the arithmetic:
+//  * ct (the exponent is secret and its table reads must not reveal it):
+//    left-to-right fixed 5-bit windows over E.nwin windows, a table of the
+//    powers x^0 .. x^31, a multiplication by the table entry for every
+//    window, zero digits included, and every entry read for each window
+//    (tab_entry), so neither the operations nor the addresses depend on e;
+//  * otherwise: E's sliding-window schedule (windows of up to 6 bits ending
+//    in a 1 bit; keysetup.hpp), a table of the odd powers x, x^3 .. x^63
+//    built with x^2, and per op its squarings and one multiplication by the
+//    odd power its window names: about 146 multiplications per 1024-bit
+//    exponent instead of 204, with as many squarings.  The schedule is
+//    fixed per key and the same for the whole wave.
+// `tab`: this group's table, kTable + 1 entries of S29 words in global
+// memory; `lds`: this group's row of at least max(G K32, 2 S29) words;
+// `zeros`: S29 zero words in the row's LDS array (see sq29).
 template <int K32, int G>
-__device__ __forceinline__ void pow29(uint32_t (&x)[K32], const uint32_t *e, int nwin, uint32_t *tab,
-                                      const DMod &D, uint32_t *lds, const uint32_t *zeros, bool ct) {
+__device__ __forceinline__ void pow29(uint32_t (&x)[K32], const DExp &E, uint32_t *tab, const DMod &D,
+                                      uint32_t *lds, const uint32_t *zeros, bool ct) {
   constexpr int S29 = he29::limbs_for_group(G * K32, G);
   constexpr int K = S29 / G;
   constexpr int v = he29::variant(G);
@@ -486,29 +494,56 @@ __device__ __forceinline__ void pow29(uint32_t (&x)[K32], const uint32_t *e, int
     to29<K32, K, G>(cur, x, lds);
     ld29<K, G>(c, D.R2_29[v]);
     mm29<K, G>(cur, cur, c, M, lds);  // Montgomery form of x
-    ld29<K, G>(c, D.R1_29[v]);        // Montgomery form of 1
-    st29<K, G>(tab, c);
-    st29<K, G>(tab + S29, cur);
   }
-  // table entries d = x^d; the multiplier x comes back from the table so
-  // that only the running power is held in registers
+  if (ct) {
+    {
+      uint32_t c[K];
+      ld29<K, G>(c, D.R1_29[v]);  // Montgomery form of 1
+      st29<K, G>(tab, c);
+      st29<K, G>(tab + S29, cur);
+    }
+    // table entries d = x^d; the multiplier x comes back from the table so
+    // that only the running power is held in registers
 #pragma unroll 1
-  for (int d = 2; d < kTable; ++d) {
-    mm29_mem<K, G>(cur, tab + S29, cur, M, lds);
-    st29<K, G>(tab + d * S29, cur);
-  }
-  __threadfence_block();
-  tab_entry<K, G>(cur, tab, exp_digit(e, nwin - 1), ct);
+    for (int d = 2; d < kTable; ++d) {
+      mm29_mem<K, G>(cur, tab + S29, cur, M, lds);
+      st29<K, G>(tab + d * S29, cur);
+    }
+    __threadfence_block();
+    tab_entry<K, G>(cur, tab, exp_digit(E.e, E.nwin - 1), true);
 #pragma unroll 1
-  for (int w = nwin - 2; w >= 0; --w) {
+    for (int w = E.nwin - 2; w >= 0; --w) {
 #pragma unroll 1
-    for (int s = 0; s < kWindow; ++s) sq29<K, G>(cur, cur, M, lds, zeros);
-    if (ct) {
-      uint32_t v[K];
-      tab_entry<K, G>(v, tab, exp_digit(e, w), true);
-      mm29<K, G>(cur, v, cur, M, lds);
+      for (int s = 0; s < kWindow; ++s) sq29<K, G>(cur, cur, M, lds, zeros);
+      uint32_t t[K];
+      tab_entry<K, G>(t, tab, exp_digit(E.e, w), true);
+      mm29<K, G>(cur, t, cur, M, lds);
+    }
+  } else {
+    // odd powers: entry k = x^(2k+1); x^2 in entry kTable, read back as
+    // the multiplier of each step
+    st29<K, G>(tab, cur);
+    sq29<K, G>(cur, cur, M, lds, zeros);
+    st29<K, G>(tab + kTable * S29, cur);
+    ld29<K, G>(cur, tab);
+#pragma unroll 1
+    for (int k = 1; k < kTable; ++k) {
+      mm29_mem<K, G>(cur, tab + kTable * S29, cur, M, lds);
+      st29<K, G>(tab + k * S29, cur);
+    }
+    __threadfence_block();
+    if (E.nops == 0) {
+      ld29<K, G>(cur, D.R1_29[v]);  // x^0
     } else {
-      mm29_mem<K, G>(cur, tab + exp_digit(e, w) * S29, cur, M, lds);
+      ld29<K, G>(cur, tab + (E.ops[0] & 0xFFu) * S29);
+#pragma unroll 1
+      for (int t = 1; t < E.nops; ++t) {
+        const uint32_t op = E.ops[t];
+        const uint32_t k = op & 0xFFu;
+#pragma unroll 1
+        for (uint32_t s = op >> 8; s > 0; --s) sq29<K, G>(cur, cur, M, lds, zeros);
+        if (k < (uint32_t)kTable) mm29_mem<K, G>(cur, tab + k * S29, cur, M, lds);
+      }
     }
   }
   // leave the Montgomery domain: cur R'^-1 (a product with 1, at most N)

@@ -190,6 +190,11 @@ static void out(const char *tag, size_t off, size_t limbs) {
   for (size_t i = limbs; i-- > 0;) printf("%08x", B->words[off + i]);
   printf("\n");
 }
+static void sched(const char *t, const hekey::ExpOff &e) {
+  printf("%s.ops ", t);
+  for (int i = 0; i < e.nops; ++i) printf("%s%x", i ? "," : "", B->words[e.ops + i]);
+  printf("\n");
+}
 static void mod(const char *t, const hekey::ModOff &m, size_t S) {
   std::string s(t);
   out((s + ".N").c_str(), m.N, S); out((s + ".R1").c_str(), m.R1, S); out((s + ".R2").c_str(), m.R2, S);
@@ -202,7 +207,7 @@ int main(int argc, char **argv) {
   B = &k.blob;
   size_t L = bits / 32, SP = L / 2;
   mod("n", k.n, L); mod("n2", k.n2, 2 * L);
-  out("e_n", k.e_n.e, L + 1); printf("e_n.nwin %x\n", k.e_n.nwin);
+  out("e_n", k.e_n.e, L + 1); printf("e_n.nwin %x\n", k.e_n.nwin); sched("e_n", k.e_n);
   out("nR_n2", k.nR_n2, 2 * L); out("half", k.half, L);
   for (int w = 0; w < 2; ++w) {
     std::string s = w ? "q" : "p";
@@ -210,6 +215,8 @@ int main(int argc, char **argv) {
     mod((s + ".P").c_str(), o.P, SP); mod((s + ".P2").c_str(), o.P2, 2 * SP);
     out((s + ".e_enc").c_str(), o.e_enc.e, SP + 1); printf("%s.e_enc.nwin %x\n", s.c_str(), o.e_enc.nwin);
     out((s + ".e_lift").c_str(), o.e_lift.e, SP + 1); out((s + ".e_dec").c_str(), o.e_dec.e, SP + 1);
+    sched((s + ".e_enc").c_str(), o.e_enc); sched((s + ".e_lift").c_str(), o.e_lift);
+    sched((s + ".e_dec").c_str(), o.e_dec);
     out((s + ".QR_P").c_str(), o.QR_P, SP); out((s + ".PR_P2").c_str(), o.PR_P2, 2 * SP);
     out((s + ".Pinv").c_str(), o.Pinv, SP); out((s + ".hR_P").c_str(), o.hR_P, SP);
   }
@@ -232,7 +239,13 @@ def test_key_constants_against_definitions(tmp_path, bits, seed):
     p, q = P.keygen(bits, seed)
     r = subprocess.run([str(exe), str(bits), format(p, "x"), format(q, "x")], capture_output=True, text=True)
     assert r.returncode == 0, r.stderr
-    c = {a: int(b, 16) for a, b in (line.split() for line in r.stdout.splitlines())}
+    c, ops = {}, {}
+    for line in r.stdout.splitlines():
+        a, b = line.split()
+        if a.endswith(".ops"):
+            ops[a[:-4]] = [int(x, 16) for x in b.split(",")]
+        else:
+            c[a] = int(b, 16)
     n, L = p * q, bits // 32
     n2, g = n * n, n + 1
 
@@ -264,6 +277,20 @@ def test_key_constants_against_definitions(tmp_path, bits, seed):
     assert c["q2R_n2"] == q * q * (1 << (64 * L)) % n2
     assert c["qinv_p"] == pow(q, -1, p)
     assert c["qR_n"] == q * (1 << (32 * L)) % n
+    # the sliding-window schedules rebuild their exponents, with windows of
+    # at most 6 bits ending in a 1 bit and odd-power indices below 32
+    for tag, e in [("e_n", n)] + [(f"{t}.{k}", v) for t, A, Bq in (("p", p, q), ("q", q, p))
+                                  for k, v in (("e_enc", Bq % (A - 1)), ("e_lift", A), ("e_dec", A - 1))]:
+        o = ops[tag]
+        acc = 2 * (o[0] & 0xFF) + 1
+        assert o[0] >> 8 == 0 and (o[0] & 0xFF) < 32
+        for op in o[1:]:
+            k, nsq = op & 0xFF, op >> 8
+            assert nsq >= 1 and (k < 32 or k == 0xFF)
+            acc = (acc << nsq) + (2 * k + 1 if k != 0xFF else 0)
+        assert acc == e, tag
+        mults = sum(1 for op in o[1:] if op & 0xFF != 0xFF)
+        assert mults <= e.bit_length() // 6 + 1, (tag, mults)
 
 
 # ------------------------------------------------- bucketing index logic

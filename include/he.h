@@ -201,19 +201,21 @@ typedef struct he_hist_job {
 int he_hist_aggregate(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
                       const he_hist_job *jobs, uint32_t n_jobs, hipStream_t stream);
 
-/* he_hist_aggregate with an explicit work-item length: `chunk` samples of
- * one (feature, bin) per item (0 picks the library default).  The result
- * does not depend on `chunk`; only the load balance does. */
+/* he_hist_aggregate with an explicit work-item length: at most `chunk`
+ * samples of one (feature, bin) per item, each bin's samples split into
+ * equal parts (0 picks the library default).  The result does not depend
+ * on `chunk`; only the load balance does. */
 int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
                          const he_hist_job *jobs, uint32_t n_jobs, uint32_t chunk,
                          hipStream_t stream);
 
 /* Autotuner for the batched aggregation: times he_hist_aggregate on these
  * jobs (synchronising `stream`), first for work-item lengths of 16..512
- * samples and one or two groups per (item, slot), then, at the best of
- * those, for the product kernel's lanes per ciphertext (16, or 8 at
- * 2048-bit keys) and waves per SIMD (its own occupancy, or 4, 3 or 2 by
- * reserving LDS), and remembers the fastest choice for the shape class (key
+ * samples (32..256 at 8 lanes) and one or two groups per (item, slot) at
+ * each of the product kernel's lanes per ciphertext (16, and 8 at 2048-bit
+ * keys), then, at the best items of each, for waves per SIMD (4, 3 or 2 by
+ * reserving LDS, where that is below the kernel's own occupancy), and
+ * remembers the fastest choice for the shape class (key
  * size, total contributions and job count rounded to powers of two, largest
  * bin count).  Later he_hist_aggregate calls and plans with chunk 0 in the
  * same class use it.  The histograms are written (correctly) several times.

@@ -784,6 +784,7 @@ extern "C" int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t 
   HE_TRY_HIP(hipEventCreate(&e0));
   HE_TRY_HIP(hipEventCreate(&e1));
   TuneVal best{64, 2, 1e30f};
+  TuneVal best_g[2] = {{64, 2, 1e30f}, {64, 2, 1e30f}};  // per lanes per ciphertext: [0] 16, [1] 8
   int rc = HE_OK;
   auto trial = [&](uint32_t c, uint32_t split, int G, int waves) -> int {
     int r = hist_run(key, ct, rows, ct_form, jobs, n_jobs, c, split, stream, nullptr, G, waves);  // warm-up
@@ -796,24 +797,32 @@ extern "C" int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t 
     float ms = 0;
     HE_TRY_HIP(hipEventElapsedTime(&ms, e0, e1));
     ms /= 2;
-    if (ms < best.ms) best = TuneVal{c, split, ms, G, waves};
+    const TuneVal v{c, split, ms, G, waves};
+    if (ms < best.ms) best = v;
+    TuneVal &bg = best_g[G == he::kHistGroup ? 0 : 1];
+    if (ms < bg.ms) bg = v;
     return HE_OK;
   };
-  // work items first (chunk, groups per item) at 16 lanes and the kernel's
-  // own occupancy, then lanes per ciphertext and waves per SIMD at the best
-  for (uint32_t split : {2u, 1u}) {
-    for (uint32_t c : chunks)
-      if ((rc = trial(c, split, he::kHistGroup, 0))) break;
-    if (rc) break;
-  }
+  // work items (chunk, groups per item) for each lane count at the kernel's
+  // own occupancy (the 8-lane waves take two or four items at once, so their
+  // best items differ), then waves per SIMD at the best items of each
   const int KP = kp_of(key);
-  const uint32_t bc = best.chunk, bs = best.split;
   for (int G : {he::kHistGroup, 8}) {
     if (rc || !he::hist_shape_valid(KP, G)) continue;
-    for (int waves : {0, 4, 3, 2}) {
-      if (G == he::kHistGroup && waves == 0) continue;  // measured above
-      if (waves && he::hist_dyn_lds(KP, G, waves) == 0) continue;  // no cap needed: same as waves 0
-      if ((rc = trial(bc, bs, G, waves))) break;
+    for (uint32_t split : {2u, 1u}) {
+      for (uint32_t c : chunks) {
+        if (G != he::kHistGroup && (c < 32 || c > 256)) continue;  // 8 lanes: the middle lengths only
+        if ((rc = trial(c, split, G, 0))) break;
+      }
+      if (rc) break;
+    }
+  }
+  for (int G : {he::kHistGroup, 8}) {
+    if (rc || !he::hist_shape_valid(KP, G)) continue;
+    const TuneVal bg = best_g[G == he::kHistGroup ? 0 : 1];
+    for (int waves : {4, 3, 2}) {
+      if (he::hist_dyn_lds(KP, G, waves) == 0) continue;  // no cap needed: same as its own occupancy
+      if ((rc = trial(bg.chunk, bg.split, G, waves))) break;
     }
   }
   hipEventDestroy(e0);

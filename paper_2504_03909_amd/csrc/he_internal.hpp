@@ -90,7 +90,7 @@ struct HistWs {
   uint32_t *partials;                              // [items_cap][2][S29], 29-bit limbs
   uint64_t total_fb, total_f, total_blocks, items_cap;
   uint64_t rows;                                   // resident ciphertext rows
-  uint32_t chunk;                                  // samples per item
+  uint32_t chunk;                                  // most samples per item
   uint32_t split;                                  // groups per (item, slot): 1 or 2
   unsigned long long *mm_count;                    // optional debug counters [3], else null
 };
@@ -162,7 +162,8 @@ uint32_t hist_resident_blocks(int KP, int G, uint32_t dyn);
 uint32_t hist_dyn_lds(int KP, int G, int waves);
 hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *host_jobs,
                        const HistWs &ws, const HistLaunch &l, hipStream_t s);
-// Work items are chunks of `chunk` samples of one (feature, bin); with
+// Work items are equal parts (at most `chunk` samples) of one (feature, bin)'s
+// sample run, laid out by decreasing bin count in each feature; with
 // split 2 one wave takes one item (two groups per slot, halves combined),
 // with split 1 one wave takes two items (one group per slot).
 hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);

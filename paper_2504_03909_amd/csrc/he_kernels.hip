@@ -839,10 +839,13 @@ __global__ __launch_bounds__(256) void k_hist_count(HistWs ws) {
   if (threadIdx.x == 0 && nbad && J.n_bad) atomicAdd(J.n_bad, nbad);
 }
 
-// Per (job, feature): exclusive scan of the bin counts, chunk counts per bin
-// and their local prefix; ftot = chunks of this feature.
+// Per (job, feature): exclusive scan of the bin counts (the bins' sample runs
+// in bin order), chunk counts per bin and their local prefix, taken over the
+// bins in decreasing order of their counts (ties: lower bin first), so that
+// consecutive work items have about the same length and the waves that take
+// several items at once pad little; ftot = chunks of this feature.
 __global__ __launch_bounds__(256) void k_hist_scan(HistWs ws) {
-  __shared__ uint32_t sc[256], sh[256];
+  __shared__ uint32_t sc[256], sh[256], cn[256];
   const uint64_t jf = blockIdx.x;
   const uint32_t jn = find_job_by_f(ws.jobs, ws.n_jobs, jf);
   const DJob J = ws.jobs[jn];
@@ -851,8 +854,20 @@ __global__ __launch_bounds__(256) void k_hist_scan(HistWs ws) {
   const uint32_t t = threadIdx.x;
   const uint32_t cnt = t < J.B ? ws.counts[e] : 0u;
   const uint32_t nch = (cnt + ws.chunk - 1) / ws.chunk;
+  cn[t] = cnt;
+  __syncthreads();
+  // this bin's place in the item order (bins past J.B keep their own index,
+  // which no bin below J.B takes)
+  uint32_t rank = t;
+  if (t < J.B) {
+    rank = 0;
+    for (uint32_t b = 0; b < J.B; ++b) {
+      const uint32_t c = cn[b];
+      rank += (c > cnt || (c == cnt && b < t)) ? 1u : 0u;
+    }
+  }
   sc[t] = cnt;
-  sh[t] = nch;
+  sh[rank] = nch;
   __syncthreads();
   for (uint32_t d = 1; d < 256; d <<= 1) {  // inclusive Hillis-Steele scans
     const uint32_t a = t >= d ? sc[t - d] : 0u, b = t >= d ? sh[t - d] : 0u;
@@ -865,7 +880,7 @@ __global__ __launch_bounds__(256) void k_hist_scan(HistWs ws) {
     ws.offs[e] = sc[t] - cnt;
     ws.cursor[e] = sc[t] - cnt;
     ws.fch[e] = nch;
-    ws.fitem[e] = sh[t] - nch;  // local; made global by k_hist_items
+    ws.fitem[e] = sh[rank] - nch;  // local; made global by k_hist_items
   }
   if (t == 255) ws.ftot[jf] = sh[255];
 }
@@ -895,7 +910,8 @@ __global__ __launch_bounds__(1024) void k_hist_base(HistWs ws) {
   if (threadIdx.x == 0) *ws.n_items = carry;
 }
 
-// Items of one (job, feature): every bin's sample run split into chunks.
+// Items of one (job, feature): every bin's sample run split into its nch
+// chunks of equal length (to one sample), each at most `chunk` samples.
 __global__ __launch_bounds__(256) void k_hist_items(HistWs ws) {
   const uint64_t jf = blockIdx.x;
   const uint32_t jn = find_job_by_f(ws.jobs, ws.n_jobs, jf);
@@ -909,9 +925,10 @@ __global__ __launch_bounds__(256) void k_hist_items(HistWs ws) {
   const uint32_t nch = ws.fch[e], cnt = ws.counts[e];
   const uint64_t start = J.perm_off + (uint64_t)f * J.n + ws.offs[e];
   for (uint32_t c = 0; c < nch; ++c) {
+    const uint32_t lo = (uint32_t)((uint64_t)c * cnt / nch), hi = (uint32_t)((uint64_t)(c + 1) * cnt / nch);
     HistItem it;
-    it.start = start + (uint64_t)c * ws.chunk;
-    it.len = min(ws.chunk, cnt - c * ws.chunk);
+    it.start = start + lo;
+    it.len = hi - lo;
     it.pad = 0;
     ws.items[first + c] = it;
   }

@@ -203,11 +203,12 @@ def test_batched_64_jobs_2048(he):
         assert torch.equal(alone, hb)
     # every work shape the autotuner can pick gives the same histograms
     for lanes in (16, 8):
-        for waves in (0, 4, 3, 2):
-            say(f"64 jobs at lanes={lanes} waves={waves}")
-            hs, cnt = he.hist_aggregate_counted(k, ctm, make_jobs(he, tables, shapes), form=he.HE_FORM_MONT,
-                                                chunk=128, split=2, lanes=lanes, waves=waves)
-            assert all(torch.equal(h, hb) for h, hb in zip(hs, batched)), (lanes, waves)
+        for split, chunk in ((2, 128), (1, 64)):
+            for waves in (0, 4, 3, 2):
+                say(f"64 jobs at lanes={lanes} split={split} chunk={chunk} waves={waves}")
+                hs, cnt = he.hist_aggregate_counted(k, ctm, make_jobs(he, tables, shapes), form=he.HE_FORM_MONT,
+                                                    chunk=chunk, split=split, lanes=lanes, waves=waves)
+                assert all(torch.equal(h, hb) for h, hb in zip(hs, batched)), (lanes, split, chunk, waves)
     c = dict(bits=bits, M=M, r_seed=r_seed, sk=sk, k=k, m=m, ct=ct, tables=tables)
     order = np.argsort([sh["sample_idx"].size for sh in shapes])
     for n, ji in enumerate(order):

@@ -197,7 +197,11 @@ typedef struct he_hist_job {
  *     form given by ct_form (HE_FORM_MONT avoids a conversion per call).
  * jobs: host array of n_jobs descriptors.  All jobs' (feature, bin, chunk)
  * work items run in one persistent launch; the result is independent of
- * batching, chunking and order (exact modular products). */
+ * batching, chunking and order (exact modular products).  Work shape: the
+ * one he_hist_autotune found for the batch's shape class, else, at 2048-bit
+ * keys for batches of at least 16384 items (estimated at 128 samples per
+ * item), 8 lanes per ciphertext and items of up to 128 samples, and 16
+ * lanes with items of up to 64 samples otherwise. */
 int he_hist_aggregate(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
                       const he_hist_job *jobs, uint32_t n_jobs, hipStream_t stream);
 

@@ -741,6 +741,22 @@ TuneKey tune_key(const he_key *key, const he_hist_job *jobs, uint32_t n_jobs) {
   return TuneKey{key->n_bits, ilog2(contrib + 1), ilog2(n_jobs), mb};
 }
 
+// Work shape of an untuned batch (chunk 0, no autotuner entry for its
+// class): at 2048-bit keys, a batch with enough items to fill the device
+// several times over takes 8 lanes per ciphertext and items of up to 128
+// samples (two items per wave, fewer instructions per product); a smaller
+// one 16 lanes and items of up to 64 samples (one item per wave, so that
+// its few items spread over more waves).
+TuneVal default_hist_shape(const he_key *key, const he_hist_job *jobs, uint32_t n_jobs) {
+  constexpr uint64_t kLargeBatchItems = 16384;
+  uint64_t items = 0;
+  for (uint32_t j = 0; j < n_jobs; ++j)
+    items += (uint64_t)jobs[j].n_features *
+             ((jobs[j].n_samples + 127) / 128 + std::min<uint64_t>(jobs[j].n_bins, jobs[j].n_samples));
+  if (kp_of(key) == 2 && items >= kLargeBatchItems) return TuneVal{128, 2, 0.f, 8, 0};
+  return TuneVal{64, 2, 0.f, he::kHistGroup, 0};
+}
+
 }  // namespace
 
 extern "C" int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_form,
@@ -749,14 +765,16 @@ extern "C" int he_hist_aggregate_ex(const he_key *key, const uint32_t *ct, uint6
   uint32_t split = 2;
   int G = he::kHistGroup, waves = 0;
   if (chunk == 0 && key && jobs && n_jobs) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(tune_key(key, jobs, n_jobs));
-    if (it != g_tune.end()) {
-      chunk = it->second.chunk;
-      split = it->second.split;
-      G = it->second.G;
-      waves = it->second.waves;
+    TuneVal v = default_hist_shape(key, jobs, n_jobs);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(tune_key(key, jobs, n_jobs));
+      if (it != g_tune.end()) v = it->second;
     }
+    chunk = v.chunk;
+    split = v.split;
+    G = v.G;
+    waves = v.waves;
   }
   return hist_run(key, ct, rows, ct_form, jobs, n_jobs, chunk, split, stream, nullptr, G, waves);
 }
@@ -970,14 +988,16 @@ extern "C" int he_hist_plan_create(const he_key *key, const uint32_t *ct, uint64
   if (!key || !jobs || n_jobs == 0) return fail(HE_ERR_ARG, "need a key and at least one job");
   int G = he::kHistGroup, waves = 0;
   if (chunk == 0) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(tune_key(key, jobs, n_jobs));
-    chunk = it != g_tune.end() ? it->second.chunk : 64;
-    if (split == 0) split = it != g_tune.end() ? it->second.split : 2;
-    if (it != g_tune.end()) {
-      G = it->second.G;
-      waves = it->second.waves;
+    TuneVal v = default_hist_shape(key, jobs, n_jobs);
+    {
+      std::lock_guard<std::mutex> lk(g_tune_mu);
+      auto it = g_tune.find(tune_key(key, jobs, n_jobs));
+      if (it != g_tune.end()) v = it->second;
     }
+    chunk = v.chunk;
+    if (split == 0) split = v.split;
+    G = v.G;
+    waves = v.waves;
   }
   if (split == 0) split = 2;
   he_hist_plan *p = new (std::nothrow) he_hist_plan();

@@ -415,8 +415,9 @@ def main():
             "encrypt_path": "crt", "hist_chunk": tuned_chunk, "hist_split": tuned_split,
             "hist_lanes": hist_tune.lanes, "hist_waves_per_simd": hist_tune.waves or "own occupancy",
             "hist_shape": "autotuned before timing" if args.chunk == 0 else "given",
-            "exponentiation_shapes": {k: {"lanes": v[0], "waves_per_simd": v[1] or "own occupancy",
-                                          "tuning_ms": round(v[2], 3)} for k, v in exp_shapes.items()},
+            "exponentiation_shapes": {k: {"lanes": v.lanes, "waves_per_simd": v.waves or "own occupancy",
+                                          "last_round_lanes": v.tail_lanes or "same launch",
+                                          "tuning_ms": round(v.ms, 3)} for k, v in exp_shapes.items()},
         },
         "stages": {
             "encode_ms": round(avg["encode"], 3),

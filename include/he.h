@@ -233,18 +233,35 @@ int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t rows, int c
  * encryptions for M samples) and decryption's exponentiation mod p^2.  Times
  * every built launch shape of each -- lanes per integer (2, 4, 8 or 16) and
  * waves per SIMD (the kernel's own occupancy, or 3 or 2 by reserving LDS) --
- * on enc_count encryptions and dec_count decryptions of trial operands (the
- * running time of the fixed-window exponentiations does not depend on the
- * data), and remembers the fastest per kind for the count's size class (bit
- * length) on this device and key size; later he_encrypt, he_obfuscators and
- * he_decrypt calls of that class use it.  Results never depend on the shape.
- * Allocates trial buffers and synchronises `stream`.
- * choice: optional host uint32[6]: lanes and waves (0 = own occupancy) of
- *         the mod-p exponentiation, the lift and decryption.
+ * and then, at the best of those, the same work in two launches: the
+ * ciphertexts that fill whole rounds of the resident waves at that shape,
+ * and the remainder (less than one round) at a wider group per integer, so
+ * that the last partial round spreads over more waves.  Trials run on
+ * enc_count encryptions and dec_count decryptions of trial operands (the
+ * sliding-window schedule is fixed per key, so the running time does not
+ * depend on the data), and the fastest per kind is remembered for the
+ * count's size class (bit length) on this device and key size; later
+ * he_encrypt, he_obfuscators and he_decrypt calls of that class use it.
+ * Results never depend on the shape.  Allocates trial buffers and
+ * synchronises `stream`.
+ * choice: optional host uint32[9]: per kind (the mod-p exponentiation, the
+ *         lift, decryption) lanes, waves (0 = own occupancy) and lanes of
+ *         the remainder's launch (0 = one launch).
  * ms: optional host float[3]: their launch times.
  * HE_ERR_NOPRIV for a public key, HE_ERR_ARG for a zero count. */
 int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t dec_count, uint32_t *choice, float *ms,
                     hipStream_t stream);
+
+/* Sets the launch shape he_crt_autotune would remember, without timing (a
+ * shape measured once, pinned in a deployment): for kind 0 (the mod-p
+ * exponentiation of encryption), 1 (the lift) or 2 (decryption) at this
+ * key's size, on the current device, for counts of count's size class (bit
+ * length): lanes per integer (2, 4, 8 or 16 where built for the kind),
+ * waves per SIMD (0 = own occupancy, 2 or 3) and lanes of the last partial
+ * round's launch (0 = one launch, else a built width above lanes).  Results
+ * never depend on the shape.  HE_ERR_ARG for anything else. */
+int he_crt_set_shape(const he_key *key, uint32_t kind, uint64_t count, uint32_t lanes, uint32_t waves,
+                     uint32_t tail_lanes);
 
 /* Work-count check of the aggregation: he_hist_aggregate_ex at an explicit
  * work shape -- work-item length (chunk, 0 = default), groups per item

@@ -186,6 +186,7 @@ uint32_t persistent_grid(int KP, int kind, uint64_t work_blocks) {
 // he_crt_autotune; count class = bit length of the count.
 struct PowShape {
   int G = 0, waves = 0;  // waves 0: the kernel's own occupancy
+  int tailG = 0;         // lanes per integer of the last partial round's launch (0: no separate launch)
 };
 std::mutex g_pow_mu;
 std::map<std::tuple<int, int, int, int>, PowShape> g_pow_tuned;
@@ -212,10 +213,38 @@ he::PowLaunch pow_launch_at(int KP, int kind, uint64_t count, PowShape sh) {
   return he::PowLaunch{sh.G, grid, dyn};
 }
 
-// The launch shape of a private-key exponentiation over `count` ciphertexts:
-// the tuned one for its class if the autotuner ran, else the default
-// (pick_group's width, the kernel's maximum occupancy).
-he::PowLaunch pow_launch(int KP, int kind, uint64_t count) {
+// The launches of shape `sh` over `count` ciphertexts.  With sh.tailG, the
+// ciphertexts that fill whole rounds of the main launch's resident waves
+// (every wave the same number of units of 64 / G integers of one prime) go
+// to the main launch and the rest, less than one round, to a launch at
+// sh.tailG lanes per integer, whose fewer integers per wave spread that
+// remainder over more waves.  No split when there is no whole round or no
+// remainder.
+he::PowPlan pow_plan_at(int KP, int kind, uint64_t count, PowShape sh) {
+  he::PowPlan p{pow_launch_at(KP, kind, count, sh), count, he::PowLaunch{0, 0, 0}};
+  const int S32 = pow_s32(KP, kind);
+  if (sh.tailG == 0 || sh.tailG == p.main.G || !he::pow_shape_valid(S32, sh.tailG)) return p;
+  const uint64_t per_wave = 64 / p.main.G;
+  const uint64_t units = 2 * ((count + per_wave - 1) / per_wave);
+  const uint64_t waves = 4ull * p.main.grid;
+  const uint64_t rounds = units / waves;
+  if (rounds == 0 || units % waves == 0) return p;
+  p.main_count = rounds * waves / 2 * per_wave;  // < count: at least one unit pair is left
+  p.tail = pow_launch_at(KP, kind, count - p.main_count, PowShape{sh.tailG, 0, 0});
+  return p;
+}
+
+// Window-table bytes a plan's launches need (they run one after the other).
+uint64_t plan_table_bytes(int KP, int kind, const he::PowPlan &p) {
+  uint64_t b = (uint64_t)p.main.grid * he::table_bytes_per_block(KP, kind, p.main.G);
+  if (p.tail.G) b = std::max<uint64_t>(b, (uint64_t)p.tail.grid * he::table_bytes_per_block(KP, kind, p.tail.G));
+  return b;
+}
+
+// The launches of a private-key exponentiation over `count` ciphertexts:
+// the tuned shape for its class if the autotuner ran, else the default
+// (pick_group's width, the kernel's maximum occupancy, one launch).
+he::PowPlan pow_plan(int KP, int kind, uint64_t count) {
   PowShape sh;
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -224,7 +253,7 @@ he::PowLaunch pow_launch(int KP, int kind, uint64_t count) {
     auto it = g_pow_tuned.find({dev, KP, kind, count_class(count)});
     if (it != g_pow_tuned.end()) sh = it->second;
   }
-  return pow_launch_at(KP, kind, count, sh);
+  return pow_plan_at(KP, kind, count, sh);
 }
 
 // m == nullptr encrypts zeros (the obfuscators r^n mod n^2).
@@ -237,9 +266,8 @@ int encrypt_impl(const he_key *key, const int64_t *m, uint64_t count, const uint
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
   if (key->priv && !force_pub) {
-    const he::PowLaunch l1 = pow_launch(KP, 4, count), l2 = pow_launch(KP, 0, count);
-    int rc = ensure(w->tab, std::max(l1.grid * he::table_bytes_per_block(KP, 4, l1.G),
-                                     l2.grid * he::table_bytes_per_block(KP, 0, l2.G)), stream);
+    const he::PowPlan p1 = pow_plan(KP, 4, count), p2 = pow_plan(KP, 0, count);
+    int rc = ensure(w->tab, std::max(plan_table_bytes(KP, 4, p1), plan_table_bytes(KP, 0, p2)), stream);
     if (rc) return rc;
     // omega / c_P per (ciphertext, prime) (2L limbs per ciphertext), then
     // r mod P / t per (ciphertext, prime) (L limbs)
@@ -247,7 +275,7 @@ int encrypt_impl(const he_key *key, const int64_t *m, uint64_t count, const uint
     if (rc) return rc;
     uint32_t *cpq = (uint32_t *)w->tmp.p, *tq = cpq + count * 2 * L;
     HE_TRY_HIP(he::launch_enc_crt(KP, key->dk, m, count, r, r_seed, r_offset, tq, cpq, ct, (uint32_t *)w->tab.p,
-                                  l1, l2, stream));
+                                  p1, p2, stream));
   } else {
     const uint32_t grid = persistent_grid(KP, 1, ((count + 3) / 4 + 3) / 4);
     int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 1), stream);
@@ -441,14 +469,14 @@ int he_decrypt(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m
   Workspace *w = workspace(stream);
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
-  const he::PowLaunch l = pow_launch(KP, 2, count);
-  int rc = ensure(w->tab, l.grid * he::table_bytes_per_block(KP, 2, l.G), stream);
+  const he::PowPlan p = pow_plan(KP, 2, count);
+  int rc = ensure(w->tab, plan_table_bytes(KP, 2, p), stream);
   if (rc) return rc;
   // c mod P^2, then c^(P-1) mod P^2, per (ciphertext, prime): 2L limbs per ciphertext
   rc = ensure(w->tmp, count * 2 * L * sizeof(uint32_t), stream);
   if (rc) return rc;
   HE_TRY_HIP(he::launch_dec(KP, key->dk, ct, count, (uint32_t *)w->tmp.p, m, raw, n_overflow,
-                            (uint32_t *)w->tab.p, l, stream));
+                            (uint32_t *)w->tab.p, p, stream));
   return HE_OK;
 }
 
@@ -507,13 +535,15 @@ int he_decrypt_noalloc(const he_key *key, const uint32_t *ct, uint64_t count, in
   int rc = scratch_address(&base);
   if (rc) return rc;
   const size_t xpq_bytes = (count * 2 * L * sizeof(uint32_t) + 255) / 256 * 256;
-  he::PowLaunch l = pow_launch(KP, 2, count);
+  // one launch whose grid is cut to the tables the scratch holds
+  he::PowLaunch l = pow_plan(KP, 2, count).main;
   const uint64_t fit = (kNoAllocBytes - xpq_bytes) / he::table_bytes_per_block(KP, 2, l.G);
   if (fit == 0) return fail(HE_ERR_ARG, "he_decrypt_noalloc: no room for one block's window tables");
   l.grid = (uint32_t)std::min<uint64_t>(fit, l.grid);
   uint32_t *xpq = (uint32_t *)base;
   uint32_t *tab = (uint32_t *)((char *)base + xpq_bytes);
-  HE_TRY_HIP(he::launch_dec(KP, key->dk, ct, count, xpq, m, raw, n_overflow, tab, l, stream));
+  HE_TRY_HIP(he::launch_dec(KP, key->dk, ct, count, xpq, m, raw, n_overflow, tab,
+                            he::PowPlan{l, count, he::PowLaunch{0, 0, 0}}, stream));
   return HE_OK;
 }
 
@@ -923,26 +953,41 @@ extern "C" int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t d
   for (int t = 0; t < 3 && !rc; ++t) {
     const int kind = kinds[t];
     const uint64_t count = kind == 2 ? dec_count : enc_count;
+    auto trial = [&](const PowShape &sh, const he::PowPlan &p) -> int {
+      auto run = [&]() -> hipError_t {
+        if (kind == 4) return he::launch_pow_kind(KP, key->dk, 4, tq_p, SP, SP, tq_p, SP, count, tab_p, p, stream);
+        if (kind == 0) return he::launch_pow_kind(KP, key->dk, 0, tq_p, SP, SP, cpq_p, SP2, count, tab_p, p, stream);
+        return he::launch_pow_kind(KP, key->dk, 2, xpq_p, SP2, SP2, xpq_p, SP2, count, tab_p, p, stream);
+      };
+      float ms = 0;
+      const int r = time_ms(run, stream, e0, e1, &ms);
+      if (r) return r;
+      if (ms < best_ms[t]) {
+        best_ms[t] = ms;
+        best[t] = sh;
+      }
+      return HE_OK;
+    };
+    // lanes per integer and waves per SIMD in one launch, then, at the best
+    // of those, a separate launch for the last partial round at each wider
+    // group
     for (int G : {2, 4, 8, 16}) {
       if (!he::pow_shape_valid(pow_s32(KP, kind), G)) continue;
       for (int waves : {0, 3, 2}) {
-        const PowShape sh{G, waves};
-        const he::PowLaunch l = pow_launch_at(KP, kind, count, sh);
-        if (waves && l.dyn == 0) continue;  // the kernel's own occupancy is already at most `waves`
-        auto run = [&]() -> hipError_t {
-          if (kind == 4) return he::launch_pow_kind(KP, key->dk, 4, tq_p, SP, SP, tq_p, SP, count, tab_p, l, stream);
-          if (kind == 0) return he::launch_pow_kind(KP, key->dk, 0, tq_p, SP, SP, cpq_p, SP2, count, tab_p, l, stream);
-          return he::launch_pow_kind(KP, key->dk, 2, xpq_p, SP2, SP2, xpq_p, SP2, count, tab_p, l, stream);
-        };
-        float ms = 0;
-        rc = time_ms(run, stream, e0, e1, &ms);
-        if (rc) break;
-        if (ms < best_ms[t]) {
-          best_ms[t] = ms;
-          best[t] = sh;
-        }
+        const PowShape sh{G, waves, 0};
+        const he::PowPlan p = pow_plan_at(KP, kind, count, sh);
+        if (waves && p.main.dyn == 0) continue;  // the kernel's own occupancy is already at most `waves`
+        if ((rc = trial(sh, p))) break;
       }
       if (rc) break;
+    }
+    const PowShape one = best[t];
+    for (int tg : {4, 8, 16}) {
+      if (rc || tg <= one.G || !he::pow_shape_valid(pow_s32(KP, kind), tg)) continue;
+      const PowShape sh{one.G, one.waves, tg};
+      const he::PowPlan p = pow_plan_at(KP, kind, count, sh);
+      if (p.tail.G == 0) break;  // whole rounds only, or less than one: nothing to split
+      rc = trial(sh, p);
     }
   }
   hipEventDestroy(e0);
@@ -956,11 +1001,31 @@ extern "C" int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t d
   }
   for (int t = 0; t < 3; ++t) {
     if (choice) {
-      choice[2 * t] = (uint32_t)best[t].G;
-      choice[2 * t + 1] = (uint32_t)best[t].waves;
+      choice[3 * t] = (uint32_t)best[t].G;
+      choice[3 * t + 1] = (uint32_t)best[t].waves;
+      choice[3 * t + 2] = (uint32_t)best[t].tailG;
     }
     if (ms_out) ms_out[t] = best_ms[t];
   }
+  return HE_OK;
+}
+
+extern "C" int he_crt_set_shape(const he_key *key, uint32_t kind, uint64_t count, uint32_t lanes, uint32_t waves,
+                                uint32_t tail_lanes) {
+  if (!key) return fail(HE_ERR_ARG, "null key");
+  if (kind > 2) return fail(HE_ERR_ARG, "kind must be 0 (mod p), 1 (lift) or 2 (decryption)");
+  if (count == 0) return fail(HE_ERR_ARG, "count must be at least 1");
+  const int KP = kp_of(key), k = kind == 0 ? 4 : (kind == 1 ? 0 : 2);
+  const int S32 = pow_s32(KP, k);
+  if (!he::pow_shape_valid(S32, (int)lanes))
+    return fail(HE_ERR_ARG, "lanes " + std::to_string(lanes) + " not built for this kind and key size");
+  if (waves != 0 && waves != 2 && waves != 3) return fail(HE_ERR_ARG, "waves must be 0 (own occupancy), 2 or 3");
+  if (tail_lanes != 0 && (tail_lanes <= lanes || !he::pow_shape_valid(S32, (int)tail_lanes)))
+    return fail(HE_ERR_ARG, "tail_lanes must be 0 or a built width above lanes");
+  int dev = 0;
+  HE_TRY_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lk(g_pow_mu);
+  g_pow_tuned[{dev, KP, k, count_class(count)}] = PowShape{(int)lanes, (int)waves, (int)tail_lanes};
   return HE_OK;
 }
 

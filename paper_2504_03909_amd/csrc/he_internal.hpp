@@ -112,10 +112,21 @@ struct PowLaunch {
   uint32_t grid;
   uint32_t dyn;
 };
+// A private-key exponentiation over `count` ciphertexts in up to two
+// launches: the first main_count ciphertexts at `main`, whose resident waves
+// then all take the same number of work units, and the rest (what would be
+// a last, partly filled round) at `tail`, a narrower group per integer so
+// that it spreads over more waves.  tail.G == 0: one launch of everything
+// at `main` (main_count unused).
+struct PowPlan {
+  PowLaunch main;
+  uint64_t main_count;
+  PowLaunch tail;
+};
 // tq: [count][2][S_P] (r mod P, then t in place), cpq: [count][2][S_P2].
 hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
                           uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab,
-                          const PowLaunch &l1, const PowLaunch &l2, hipStream_t s);
+                          const PowPlan &p1, const PowPlan &p2, hipStream_t s);
 hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
                           const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *ct,
                           uint32_t *tab, uint32_t grid, hipStream_t s);
@@ -143,12 +154,12 @@ hipError_t launch_enc_r(int KP, const DKey &k, uint64_t count, const uint32_t *r
                         uint32_t *tq, hipStream_t s);
 hipError_t launch_pow_kind(int KP, const DKey &k, int kind, const uint32_t *in, uint32_t in_stride,
                            uint32_t in_limbs, uint32_t *out, uint32_t out_stride, uint64_t count, uint32_t *tab,
-                           const PowLaunch &l, hipStream_t s);
+                           const PowPlan &p, hipStream_t s);
 hipError_t launch_dec_pre(int KP, const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *xpq, hipStream_t s);
 // xpq: [count][2][S_P2] (c mod P^2, then c^(P-1) mod P^2 in place).
 hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count,
                       uint32_t *xpq, int64_t *m, uint32_t *raw, uint32_t *n_overflow,
-                      uint32_t *tab, const PowLaunch &l, hipStream_t s);
+                      uint32_t *tab, const PowPlan &p, hipStream_t s);
 // Launch shape of the histogram product kernel: lanes per ciphertext (16,
 // or 8 at 2048-bit keys), grid, and dynamic LDS reserved only to cap its
 // blocks per compute unit.

@@ -1218,12 +1218,35 @@ static hipError_t launch_pow(int S32, bool ct, PowArgs a, const PowLaunch &l, hi
   return hipLaunchKernel(pow_kernel(S32, l.G, ct), dim3(l.grid), dim3(kBlockThreads), args, l.dyn, s);
 }
 
+// The plan's launches over a.count ciphertexts: the first main_count at
+// p.main, the rest at p.tail (in and out advanced by the units before them,
+// two per ciphertext).
+static hipError_t launch_pow_plan(int S32, bool ct, PowArgs a, const PowPlan &p, hipStream_t s) {
+  const uint64_t count = a.count;
+  const uint64_t mc = p.tail.G ? std::min(p.main_count, count) : count;
+  if (mc) {
+    PowArgs am = a;
+    am.count = mc;
+    const hipError_t e = launch_pow(S32, ct, am, p.main, s);
+    if (e != hipSuccess) return e;
+  }
+  if (mc < count) {
+    PowArgs at = a;
+    at.in += mc * 2 * a.in_stride;
+    at.out += mc * 2 * a.out_stride;
+    at.count = count - mc;
+    return launch_pow(S32, ct, at, p.tail, s);
+  }
+  return hipSuccess;
+}
+
 hipError_t launch_pow_kind(int KP, const DKey &k, int kind, const uint32_t *in, uint32_t in_stride,
                            uint32_t in_limbs, uint32_t *out, uint32_t out_stride, uint64_t count, uint32_t *tab,
-                           const PowLaunch &l, hipStream_t s) {
+                           const PowPlan &p, hipStream_t s) {
   if (!count) return hipSuccess;
   const int S32 = kind == 4 ? 16 * KP : 32 * KP;
-  return launch_pow(S32, k.ct != 0, pow_args(k, kind, in, in_stride, in_limbs, out, out_stride, count, tab), l, s);
+  return launch_pow_plan(S32, k.ct != 0, pow_args(k, kind, in, in_stride, in_limbs, out, out_stride, count, tab), p,
+                         s);
 }
 
 hipError_t launch_enc_r(int KP, const DKey &k, uint64_t count, const uint32_t *r, uint64_t seed, uint64_t roff,
@@ -1250,13 +1273,13 @@ hipError_t launch_dec_pre(int KP, const DKey &k, const uint32_t *ct, uint64_t co
 template <int KP>
 static hipError_t enc_crt(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
                           uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab,
-                          const PowLaunch &l1, const PowLaunch &l2, hipStream_t s) {
+                          const PowPlan &p1, const PowPlan &p2, hipStream_t s) {
   constexpr int SP = 16 * KP, SP2 = 32 * KP;
   hipLaunchKernelGGL(k_enc_r<KP>, dim3(blocks_for(2 * count, 16)), dim3(kBlockThreads), 0, s, k, count, r, seed,
                      roff, tq);
-  hipError_t e = launch_pow(SP, k.ct != 0, pow_args(k, 4, tq, SP, SP, tq, SP, count, tab), l1, s);
+  hipError_t e = launch_pow_plan(SP, k.ct != 0, pow_args(k, 4, tq, SP, SP, tq, SP, count, tab), p1, s);
   if (e != hipSuccess) return e;
-  e = launch_pow(SP2, k.ct != 0, pow_args(k, 0, tq, SP, SP, cpq, SP2, count, tab), l2, s);
+  e = launch_pow_plan(SP2, k.ct != 0, pow_args(k, 0, tq, SP, SP, cpq, SP2, count, tab), p2, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_enc_crt_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k, m,
                      (const uint32_t *)cpq, count, ct);
@@ -1264,10 +1287,10 @@ static hipError_t enc_crt(const DKey &k, const int64_t *m, uint64_t count, const
 }
 hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
                           uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab,
-                          const PowLaunch &l1, const PowLaunch &l2, hipStream_t s) {
+                          const PowPlan &p1, const PowPlan &p2, hipStream_t s) {
   if (!count) return hipSuccess;
-  return KP == 1 ? enc_crt<1>(k, m, count, r, seed, roff, tq, cpq, ct, tab, l1, l2, s)
-                 : enc_crt<2>(k, m, count, r, seed, roff, tq, cpq, ct, tab, l1, l2, s);
+  return KP == 1 ? enc_crt<1>(k, m, count, r, seed, roff, tq, cpq, ct, tab, p1, p2, s)
+                 : enc_crt<2>(k, m, count, r, seed, roff, tq, cpq, ct, tab, p1, p2, s);
 }
 
 hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
@@ -1372,21 +1395,21 @@ hipError_t launch_mont_convert(int KP, const DKey &k, const uint32_t *in, uint64
 
 template <int KP>
 static hipError_t dec(const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *xpq, int64_t *m,
-                      uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, const PowLaunch &l, hipStream_t s) {
+                      uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, const PowPlan &p, hipStream_t s) {
   constexpr int SP2 = 32 * KP;
   hipLaunchKernelGGL(k_dec_pre<KP>, dim3(blocks_for(2 * count, 16)), dim3(kBlockThreads), 0, s, k, ct, count, xpq);
-  hipError_t e = launch_pow(SP2, k.ct != 0, pow_args(k, 2, xpq, SP2, SP2, xpq, SP2, count, tab), l, s);
+  hipError_t e = launch_pow_plan(SP2, k.ct != 0, pow_args(k, 2, xpq, SP2, SP2, xpq, SP2, count, tab), p, s);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_dec_b<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k,
                      (const uint32_t *)xpq, count, m, raw, n_overflow);
   return hipGetLastError();
 }
 hipError_t launch_dec(int KP, const DKey &k, const uint32_t *ct, uint64_t count, uint32_t *xpq,
-                      int64_t *m, uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, const PowLaunch &l,
+                      int64_t *m, uint32_t *raw, uint32_t *n_overflow, uint32_t *tab, const PowPlan &p,
                       hipStream_t s) {
   if (!count) return hipSuccess;
-  return KP == 1 ? dec<1>(k, ct, count, xpq, m, raw, n_overflow, tab, l, s)
-                 : dec<2>(k, ct, count, xpq, m, raw, n_overflow, tab, l, s);
+  return KP == 1 ? dec<1>(k, ct, count, xpq, m, raw, n_overflow, tab, p, s)
+                 : dec<2>(k, ct, count, xpq, m, raw, n_overflow, tab, p, s);
 }
 
 hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s) {

@@ -30,7 +30,7 @@ EXPORTED = (
     "he_hist_autotune", "he_hist_plan_create", "he_hist_plan_launch", "he_hist_plan_free",
     "he_obfuscators", "he_encrypt_obfuscated", "he_hist_subtract", "he_split_find",
     "he_hist_aggregate_counted", "he_ct_mul", "he_pack_slots", "he_pack", "he_decrypt_packed",
-    "he_decrypt_noalloc", "he_key_set_constant_time", "he_crt_autotune",
+    "he_decrypt_noalloc", "he_key_set_constant_time", "he_crt_autotune", "he_crt_set_shape",
 )
 
 
@@ -97,6 +97,7 @@ _autotune = _sig("he_hist_autotune", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER
                                             ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float), _vp])
 _crt_autotune = _sig("he_crt_autotune", _i32, [_vp, _u64, _u64, ctypes.POINTER(_u32), ctypes.POINTER(ctypes.c_float),
                                                _vp])
+_crt_set_shape = _sig("he_crt_set_shape", _i32, [_vp, _u32, _u64, _u32, _u32, _u32])
 _plan_create = _sig("he_hist_plan_create", _i32, [_vp, _vp, _u64, _i32, ctypes.POINTER(HistJob), _u32, _u32,
                                                   _u32, ctypes.POINTER(_vp)])
 _plan_launch = _sig("he_hist_plan_launch", _i32, [_vp, _vp])
@@ -393,15 +394,29 @@ def hist_autotune(key: Key, ct: torch.Tensor, jobs: Sequence[Job], form: int = H
     return HistTune(int(c.value), int(sp.value), int(ln.value), int(wv.value), float(ms.value))
 
 
+PowTune = collections.namedtuple("PowTune", "lanes waves tail_lanes ms")
+
+
 def crt_autotune(key: Key, enc_count: int, dec_count: int, stream=None):
     """Tunes the launch shapes of the private-key exponentiations for these
-    counts (see he_crt_autotune); returns {kind: (lanes, waves, ms)} for
-    "mod_p", "lift" and "decrypt"."""
-    choice = (_u32 * 6)()
+    counts (see he_crt_autotune); returns {kind: PowTune(lanes, waves,
+    tail_lanes, ms)} for "mod_p", "lift" and "decrypt" (tail_lanes 0: one
+    launch)."""
+    choice = (_u32 * 9)()
     ms = (ctypes.c_float * 3)()
     _check(_crt_autotune(key.handle, enc_count, dec_count, choice, ms, _stream(stream)))
-    return {name: (int(choice[2 * i]), int(choice[2 * i + 1]), float(ms[i]))
+    return {name: PowTune(int(choice[3 * i]), int(choice[3 * i + 1]), int(choice[3 * i + 2]), float(ms[i]))
             for i, name in enumerate(("mod_p", "lift", "decrypt"))}
+
+
+POW_KINDS = {"mod_p": 0, "lift": 1, "decrypt": 2}
+
+
+def crt_set_shape(key: Key, kind: str, count: int, lanes: int, waves: int = 0, tail_lanes: int = 0) -> None:
+    """Pins the launch shape of one private-key exponentiation kind ("mod_p",
+    "lift" or "decrypt") for counts of count's size class (see
+    he_crt_set_shape)."""
+    _check(_crt_set_shape(key.handle, POW_KINDS[kind], count, lanes, waves, tail_lanes))
 
 
 class HistPlan:

@@ -244,8 +244,9 @@ def test_crt_autotune_keeps_results(he):
     enc_count, dec_count = 5003, 3001
     say(f"crt autotune {enc_count}/{dec_count}")
     tuned = he.crt_autotune(k, enc_count, dec_count)
-    for kind, (lanes, waves, ms) in tuned.items():
+    for kind, (lanes, waves, tail, ms) in tuned.items():
         assert lanes in (2, 4, 8, 16) and waves in (0, 2, 3) and ms > 0, (kind, lanes, waves, ms)
+        assert tail == 0 or (tail in (4, 8, 16) and tail > lanes), (kind, lanes, tail)
     assert tuned["lift"][0] != 2 and tuned["decrypt"][0] != 2
     rng = np.random.default_rng(77)
     m = rng.integers(-(1 << 62), 1 << 62, size=enc_count, dtype=np.int64)
@@ -256,6 +257,35 @@ def test_crt_autotune_keeps_results(he):
     want = pool.encrypt_many(pk, [int(m[i]) % pk.n for i in pick],
                              [P.seeded_r(pk.n, bits, 5, int(i)) for i in pick])
     assert he.limbs_to_ints(host(ct)[pick]) == want
+
+
+def test_last_round_launch_exact(he):
+    """Encryption and decryption with the last partial round of each
+    exponentiation in a launch of its own (pinned shapes with tail lanes)
+    stay exact: every decryption equals its plaintext, and sampled
+    ciphertexts, across the range and densely in its last few percent
+    (where the second launch works), equal the oracle's.  Bad pins are
+    refused."""
+    bits, n = 2048, 200_000
+    sk = oracle_key(bits, 2)
+    pk = sk.public
+    k = gpu_key(bits, 2)
+    say(f"pinned split launches, {n} encryptions and decryptions")
+    he.crt_set_shape(k, "mod_p", n, 2, 0, 8)
+    he.crt_set_shape(k, "lift", n, 4, 0, 16)
+    he.crt_set_shape(k, "decrypt", n, 4, 0, 8)
+    rng = np.random.default_rng(91)
+    m = rng.integers(-(1 << 62), 1 << 62, size=n, dtype=np.int64)
+    ct = he.encrypt(k, dev(m), seed=9)
+    dm, _, ovf = he.decrypt(k, ct)
+    assert host(dm).tolist() == m.tolist() and int(host(ovf)[0]) == 0
+    pick = sorted(set(rng.choice(n, size=40, replace=False).tolist()) | set(range(n - 4000, n, 151))
+                  | set(range(n - 24, n)))
+    want = pool.encrypt_many(pk, [int(m[i]) % pk.n for i in pick], [P.seeded_r(pk.n, bits, 9, i) for i in pick])
+    assert he.limbs_to_ints(host(ct)[pick]) == want
+    for bad in (("lift", 2, 0, 0), ("mod_p", 4, 0, 4), ("decrypt", 4, 1, 0), ("mod_p", 3, 0, 0)):
+        with pytest.raises(he.HEError):
+            he.crt_set_shape(k, bad[0], n, *bad[1:])
 
 
 # ---------------------------------------------------------- decryption

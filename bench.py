@@ -15,7 +15,12 @@ level, decryption of every node), the served request loop ("served": a
 latency) and the CPU oracle baseline.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
-                    [--no-batched] [--no-served] [--no-tree]
+                    [--no-batched] [--no-served] [--no-tree] [--chunk C | --fixed-shapes]
+
+--chunk C fixes the histogram's items (16 lanes, at most C samples per item);
+--fixed-shapes skips both autotuners (the library's default histogram shape,
+pinned exponentiation shapes) so that separate profiler passes run the same
+kernels.
 
 Other workloads (each prints its own JSON line; not the default):
     --workload tree      2048-bit, 1,000,000 samples, 64 x 256 Zipf bins, depth-6
@@ -52,9 +57,10 @@ MI355X_HBM_BPS = 8.0e12
 # scaled by a 256 MiB copy (profiles/enc_crt_2048_100k_counters.md), and the
 # digest of the kernel sources those passes ran on (kernel_sources_digest()).
 # The figure is reported only while the sources still have that digest.
-ENC_LAUNCH_TRAFFIC = {"bytes": 3.9526e10, "sources_sha256_16": "42f76456907f2887"}
+ENC_LAUNCH_TRAFFIC = {"bytes": 3.9416e10, "sources_sha256_16": "91b28d270eb8db76"}
+# the kernels and the host code that picks their launches and exponent schedules
 KERNEL_SOURCES = ("he_kernels.hip", "he_internal.hpp", "hist_bucket.hpp", "mont.hpp", "mont29.hpp",
-                  "radix29.hpp")
+                  "radix29.hpp", "he_api.cpp", "keysetup.hpp")
 
 
 def kernel_sources_digest() -> str:
@@ -230,6 +236,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--chunk", type=int, default=0)
+    ap.add_argument("--fixed-shapes", action="store_true",
+                    help="no autotuners: default histogram shape, pinned exponentiation shapes (profiler passes)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true", help="leave the 64-job batched comparison out of the line")
     ap.add_argument("--no-served", action="store_true", help="leave the served request loop out of the line")
@@ -299,12 +307,24 @@ def main():
     # Setup: one encryption of the gradients so the autotuner can pick the
     # histogram work shape for this shape class (used by every step below).
     he.encrypt(key, he.encode(grads), seed=R_SEED, out=ct.view(-1, 2 * L))
-    hist_tune = (he.hist_autotune(key, ct, [he.Job(idx, bins, K)]) if args.chunk == 0
-                 else he.HistTune(args.chunk, 2, 16, 0, None))
+    if args.fixed_shapes:
+        # no autotuner: the library's default histogram shape at this size
+        # (8 lanes per ciphertext, items of up to 128 samples, two groups per
+        # item) and pinned exponentiation shapes, so that every profiler pass
+        # runs the same kernels
+        hist_tune = he.HistTune(128, 2, 8, 0, None)
+        exp_shapes = {}
+        for kind, count, lanes, tail in (("mod_p", 2 * M, 2, 8), ("lift", 2 * M, 4, 8), ("decrypt", J * K * 2, 4, 0)):
+            he.crt_set_shape(key, kind, count, lanes, 0, tail)
+            exp_shapes[kind] = he.PowTune(lanes, 0, tail, 0.0)
+    else:
+        hist_tune = (he.hist_autotune(key, ct, [he.Job(idx, bins, K)]) if args.chunk == 0
+                     else he.HistTune(args.chunk, 2, 16, 0, None))
+        # launch shapes of the exponentiations (lanes per integer, waves per
+        # SIMD, last round's launch) for 200,000 encryptions and 16,384
+        # decryptions, tuned before timing
+        exp_shapes = he.crt_autotune(key, 2 * M, J * K * 2)
     tuned_chunk, tuned_split = hist_tune.chunk, hist_tune.split
-    # launch shapes of the exponentiations (lanes per integer, waves per SIMD)
-    # for 200,000 encryptions and 16,384 decryptions, tuned before timing
-    exp_shapes = he.crt_autotune(key, 2 * M, J * K * 2)
     for _ in range(args.warmup):
         step([ev() for _ in range(5)])
     torch.cuda.synchronize()
@@ -414,7 +434,8 @@ def main():
             "key_bits": KEY_BITS, "samples": M, "features": J, "bins": K, "r": "seeded",
             "encrypt_path": "crt", "hist_chunk": tuned_chunk, "hist_split": tuned_split,
             "hist_lanes": hist_tune.lanes, "hist_waves_per_simd": hist_tune.waves or "own occupancy",
-            "hist_shape": "autotuned before timing" if args.chunk == 0 else "given",
+            "hist_shape": ("library default, exponentiation shapes pinned" if args.fixed_shapes else
+                           "autotuned before timing" if args.chunk == 0 else "given"),
             "exponentiation_shapes": {k: {"lanes": v.lanes, "waves_per_simd": v.waves or "own occupancy",
                                           "last_round_lanes": v.tail_lanes or "same launch",
                                           "tuning_ms": round(v.ms, 3)} for k, v in exp_shapes.items()},

@@ -664,7 +664,7 @@ int plan_layout(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_for
   lay.o_fitem = take(lay.total_fb * 4);
   lay.o_ftot = take(lay.total_f * 4);
   lay.o_fbase = take(lay.total_f * 4);
-  lay.o_nitems = take(4);
+  lay.o_nitems = take(8);  // item count, then the product kernel's work counter
   lay.o_items = take(std::max<uint64_t>(lay.items_cap, 1) * sizeof(he::HistItem));
   lay.o_perm = take(std::max<uint64_t>(lay.total_perm, 1) * 4);
   // partial products in the histogram kernels' 29-bit limbs
@@ -688,6 +688,7 @@ he::HistWs bind_layout(const HistLayout &lay, char *base) {
   ws.ftot = (uint32_t *)(base + lay.o_ftot);
   ws.fbase = (uint32_t *)(base + lay.o_fbase);
   ws.n_items = (uint32_t *)(base + lay.o_nitems);
+  ws.next = ws.n_items + 1;
   ws.items = (he::HistItem *)(base + lay.o_items);
   ws.perm = (uint32_t *)(base + lay.o_perm);
   ws.partials = (uint32_t *)(base + lay.o_part);

@@ -85,6 +85,7 @@ struct HistWs {
   uint32_t *counts, *offs, *cursor, *fch, *fitem;  // [total_fb]
   uint32_t *ftot, *fbase;                          // [total_f]
   uint32_t *n_items;                               // device scalar
+  uint32_t *next;                                  // device scalar: the product kernel's next wave unit
   HistItem *items;                                 // [items_cap]
   uint32_t *perm;                                  // [total_perm]
   uint32_t *partials;                              // [items_cap][2][S29], 29-bit limbs

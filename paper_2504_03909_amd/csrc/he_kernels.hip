@@ -907,7 +907,10 @@ __global__ __launch_bounds__(1024) void k_hist_base(HistWs ws) {
     if (threadIdx.x == 1023) carry += s[1023];
     __syncthreads();
   }
-  if (threadIdx.x == 0) *ws.n_items = carry;
+  if (threadIdx.x == 0) {
+    *ws.n_items = carry;
+    *ws.next = 0;  // k_hist_chunk's work counter
+  }
 }
 
 // Items of one (job, feature): every bin's sample run split into its nch
@@ -967,6 +970,14 @@ __global__ __launch_bounds__(256) void k_hist_scatter(HistWs ws) {
     if (ok[k]) pf[bucket_slot(base[bn[k]], rk[k])] = rows[k];
 }
 
+// The next work unit for this wave: one atomic add by the wave's first lane,
+// its result made wave-uniform.
+__device__ __forceinline__ uint64_t claim_unit(uint32_t *next) {
+  uint32_t v = 0;
+  if (lane_id() == 0) v = atomicAdd(next, 1u);
+  return __builtin_amdgcn_readfirstlane(v);
+}
+
 // Product of the ciphertexts of one item (chunk) per (item, slot), in
 // groups of G lanes (GW = 64 / G groups per wave; bit 0 of a group's index is
 // the slot g/h).  With split 2 an item is taken by four groups: bit 1 of the
@@ -989,8 +1000,6 @@ __global__ __launch_bounds__(kBlockThreads, G == 16 ? kHistWaves : 3) void k_his
   const uint32_t g = (threadIdx.x & 63u) / G;
   const uint32_t wrow = wave_in_block() * GW;
   uint32_t *lds = lds_all + (wrow + g) * ROW;
-  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
-  const uint64_t nw = (uint64_t)gridDim.x * 4;
   const uint32_t slot = g & 1u;
   const bool split = ws.split == 2;
   const uint32_t half = (g >> 1) & 1u;
@@ -998,7 +1007,11 @@ __global__ __launch_bounds__(kBlockThreads, G == 16 ? kHistWaves : 3) void k_his
   const uint32_t *one29 = key.n2.R1_29[he29::variant(G)];  // Montgomery form of 1
   const uint64_t n_items = *ws.n_items;
   const uint64_t per_wave = split ? GW / 4 : GW / 2;
-  for (uint64_t w0 = gw * per_wave; w0 < n_items; w0 += nw * per_wave) {
+  // wave units (per_wave consecutive items) are claimed from a counter, so a
+  // wave that finishes early takes the next unit and the waves end together
+  // to within about one unit; the items come longest first within each
+  // feature
+  for (uint64_t w0 = claim_unit(ws.next) * per_wave; w0 < n_items; w0 = claim_unit(ws.next) * per_wave) {
     // this group's sample run and the wave-wide trip count
     const uint64_t it = w0 + (split ? (g >> 2) : (g >> 1));
     const bool valid = it < n_items;

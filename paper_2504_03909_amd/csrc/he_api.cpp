@@ -138,7 +138,7 @@ struct Buf {
   size_t bytes = 0;
 };
 struct Workspace {
-  Buf tab, tmp, hist, unpack;
+  Buf tab, tmp, hist, unpack, ctr;  // ctr: the exponentiation launches' work counters
 };
 std::mutex g_ws_mu;
 std::map<std::pair<int, hipStream_t>, Workspace *> g_ws;
@@ -266,9 +266,13 @@ int encrypt_impl(const he_key *key, const int64_t *m, uint64_t count, const uint
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
   if (key->priv && !force_pub) {
-    const he::PowPlan p1 = pow_plan(KP, 4, count), p2 = pow_plan(KP, 0, count);
+    he::PowPlan p1 = pow_plan(KP, 4, count), p2 = pow_plan(KP, 0, count);
     int rc = ensure(w->tab, std::max(plan_table_bytes(KP, 4, p1), plan_table_bytes(KP, 0, p2)), stream);
     if (rc) return rc;
+    rc = ensure(w->ctr, 256, stream);
+    if (rc) return rc;
+    p1.ctr = (uint32_t *)w->ctr.p;
+    p2.ctr = p1.ctr + 2;
     // omega / c_P per (ciphertext, prime) (2L limbs per ciphertext), then
     // r mod P / t per (ciphertext, prime) (L limbs)
     rc = ensure(w->tmp, count * 3 * L * sizeof(uint32_t), stream);
@@ -469,9 +473,12 @@ int he_decrypt(const he_key *key, const uint32_t *ct, uint64_t count, int64_t *m
   Workspace *w = workspace(stream);
   const int KP = kp_of(key);
   const size_t L = key->n_bits / 32;
-  const he::PowPlan p = pow_plan(KP, 2, count);
+  he::PowPlan p = pow_plan(KP, 2, count);
   int rc = ensure(w->tab, plan_table_bytes(KP, 2, p), stream);
   if (rc) return rc;
+  rc = ensure(w->ctr, 256, stream);
+  if (rc) return rc;
+  p.ctr = (uint32_t *)w->ctr.p;
   // c mod P^2, then c^(P-1) mod P^2, per (ciphertext, prime): 2L limbs per ciphertext
   rc = ensure(w->tmp, count * 2 * L * sizeof(uint32_t), stream);
   if (rc) return rc;
@@ -542,8 +549,9 @@ int he_decrypt_noalloc(const he_key *key, const uint32_t *ct, uint64_t count, in
   l.grid = (uint32_t)std::min<uint64_t>(fit, l.grid);
   uint32_t *xpq = (uint32_t *)base;
   uint32_t *tab = (uint32_t *)((char *)base + xpq_bytes);
+  // static units: no work counter in the scratch
   HE_TRY_HIP(he::launch_dec(KP, key->dk, ct, count, xpq, m, raw, n_overflow, tab,
-                            he::PowPlan{l, count, he::PowLaunch{0, 0, 0}}, stream));
+                            he::PowPlan{l, count, he::PowLaunch{0, 0, 0}, nullptr}, stream));
   return HE_OK;
 }
 
@@ -922,17 +930,18 @@ extern "C" int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t d
   const uint64_t n_ct = std::max(enc_count, dec_count);
   int dev = 0;
   HE_TRY_HIP(hipGetDevice(&dev));
-  // trial buffers: r mod P / t, omega, ciphertexts, c mod P^2, window tables
-  DevBuf tq, cpq, ct, xpq, tab;
+  // trial buffers: r mod P / t, omega, ciphertexts, c mod P^2, window tables,
+  // work counters
+  DevBuf tq, cpq, ct, xpq, tab, ctr;
   size_t tab_bytes = 0;
   for (int kind : {4, 0, 2})
     for (int G : {2, 4, 8, 16})
       if (he::pow_shape_valid(pow_s32(KP, kind), G))
         tab_bytes = std::max<size_t>(tab_bytes, (size_t)he::pow_resident_blocks(pow_s32(KP, kind), G, 0) *
                                                    he::table_bytes_per_block(KP, kind, G));
-  const size_t sizes[5] = {n_ct * L * 4, n_ct * 2 * L * 4, n_ct * 2 * L * 4, n_ct * 2 * L * 4, tab_bytes};
-  DevBuf *bufs[5] = {&tq, &cpq, &ct, &xpq, &tab};
-  for (int b = 0; b < 5; ++b)
+  const size_t sizes[6] = {n_ct * L * 4, n_ct * 2 * L * 4, n_ct * 2 * L * 4, n_ct * 2 * L * 4, tab_bytes, 256};
+  DevBuf *bufs[6] = {&tq, &cpq, &ct, &xpq, &tab, &ctr};
+  for (int b = 0; b < 6; ++b)
     if (hipMalloc(&bufs[b]->p, sizes[b]) != hipSuccess) {
       hipGetLastError();
       return fail(HE_ERR_OOM, "autotuner trial buffers");
@@ -954,7 +963,8 @@ extern "C" int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t d
   for (int t = 0; t < 3 && !rc; ++t) {
     const int kind = kinds[t];
     const uint64_t count = kind == 2 ? dec_count : enc_count;
-    auto trial = [&](const PowShape &sh, const he::PowPlan &p) -> int {
+    auto trial = [&](const PowShape &sh, he::PowPlan p) -> int {
+      p.ctr = (uint32_t *)ctr.p;
       auto run = [&]() -> hipError_t {
         if (kind == 4) return he::launch_pow_kind(KP, key->dk, 4, tq_p, SP, SP, tq_p, SP, count, tab_p, p, stream);
         if (kind == 0) return he::launch_pow_kind(KP, key->dk, 0, tq_p, SP, SP, cpq_p, SP2, count, tab_p, p, stream);

@@ -118,11 +118,13 @@ struct PowLaunch {
 // then all take the same number of work units, and the rest (what would be
 // a last, partly filled round) at `tail`, a narrower group per integer so
 // that it spreads over more waves.  tail.G == 0: one launch of everything
-// at `main` (main_count unused).
+// at `main` (main_count unused).  ctr: two device words for the launches'
+// work counters (cleared by the launcher), or null for static units.
 struct PowPlan {
   PowLaunch main;
   uint64_t main_count;
   PowLaunch tail;
+  uint32_t *ctr;
 };
 // tq: [count][2][S_P] (r mod P, then t in place), cpq: [count][2][S_P2].
 hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,

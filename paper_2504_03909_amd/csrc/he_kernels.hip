@@ -78,6 +78,14 @@ __device__ __forceinline__ void seeded_limbs(uint32_t (&x)[K], uint64_t seed, ui
 // persistent loops derive from it (unit index, prime, modulus and exponent
 // pointers) then lives in SGPRs.
 __device__ __forceinline__ uint32_t wave_in_block() { return __builtin_amdgcn_readfirstlane(threadIdx.x >> 6); }
+
+// The next work unit for this wave: one atomic add by the wave's first lane,
+// its result made wave-uniform.
+__device__ __forceinline__ uint64_t claim_unit(uint32_t *next) {
+  uint32_t v = 0;
+  if (lane_id() == 0) v = atomicAdd(next, 1u);
+  return __builtin_amdgcn_readfirstlane(v);
+}
 __device__ __forceinline__ uint32_t group_in_wave() { return (threadIdx.x >> 4) & 3u; }
 
 // ------------------------------------------------------------------- encode
@@ -106,6 +114,9 @@ __global__ void k_encode(const double *__restrict__ x, uint64_t count, uint32_t 
 // CT: constant-time window-table reads.  At most 3 waves per SIMD: the
 // 18-limb-per-lane shapes need about 168 VGPRs to run their step loops
 // without spills (at 128, for 4 waves, the loops spill and run 25% slower).
+// With `next` (a counter zeroed before the launch) the waves claim units as
+// they finish them, so they end together; without, wave w takes units w,
+// w + waves, ...
 struct PowArgs {
   DMod mod[2];
   DExp exp[2];
@@ -114,6 +125,7 @@ struct PowArgs {
   uint32_t in_stride, in_limbs, out_stride;
   uint64_t count;
   uint32_t *tabs;
+  uint32_t *next;
 };
 
 template <int S32, int G, bool CT>
@@ -129,7 +141,7 @@ __global__ __launch_bounds__(kBlockThreads, 3) void k_pow(PowArgs a) {
   const uint64_t nw = (uint64_t)gridDim.x * 4;
   uint32_t *tab = a.tabs + (gw * NG + g) * (uint64_t)((kTable + 1) * S29);
   const uint64_t nunits = 2 * ((a.count + NG - 1) / NG);
-  for (uint64_t qd = gw; qd < nunits; qd += nw) {
+  for (uint64_t qd = a.next ? claim_unit(a.next) : gw; qd < nunits; qd = a.next ? claim_unit(a.next) : qd + nw) {
     const int which = (int)(qd & 1);
     uint64_t i = (qd >> 1) * NG + g;
     const bool valid = i < a.count;
@@ -970,14 +982,6 @@ __global__ __launch_bounds__(256) void k_hist_scatter(HistWs ws) {
     if (ok[k]) pf[bucket_slot(base[bn[k]], rk[k])] = rows[k];
 }
 
-// The next work unit for this wave: one atomic add by the wave's first lane,
-// its result made wave-uniform.
-__device__ __forceinline__ uint64_t claim_unit(uint32_t *next) {
-  uint32_t v = 0;
-  if (lane_id() == 0) v = atomicAdd(next, 1u);
-  return __builtin_amdgcn_readfirstlane(v);
-}
-
 // Product of the ciphertexts of one item (chunk) per (item, slot), in
 // groups of G lanes (GW = 64 / G groups per wave; bit 0 of a group's index is
 // the slot g/h).  With split 2 an item is taken by four groups: bit 1 of the
@@ -1233,13 +1237,19 @@ static hipError_t launch_pow(int S32, bool ct, PowArgs a, const PowLaunch &l, hi
 
 // The plan's launches over a.count ciphertexts: the first main_count at
 // p.main, the rest at p.tail (in and out advanced by the units before them,
-// two per ciphertext).
+// two per ciphertext), each with its work counter in p.ctr when given
+// (cleared here, in stream order).
 static hipError_t launch_pow_plan(int S32, bool ct, PowArgs a, const PowPlan &p, hipStream_t s) {
   const uint64_t count = a.count;
   const uint64_t mc = p.tail.G ? std::min(p.main_count, count) : count;
+  if (p.ctr) {
+    const hipError_t e = launch_fill(p.ctr, 2, 0u, s);
+    if (e != hipSuccess) return e;
+  }
   if (mc) {
     PowArgs am = a;
     am.count = mc;
+    am.next = p.ctr;
     const hipError_t e = launch_pow(S32, ct, am, p.main, s);
     if (e != hipSuccess) return e;
   }
@@ -1248,6 +1258,7 @@ static hipError_t launch_pow_plan(int S32, bool ct, PowArgs a, const PowPlan &p,
     at.in += mc * 2 * a.in_stride;
     at.out += mc * 2 * a.out_stride;
     at.count = count - mc;
+    at.next = p.ctr ? p.ctr + 1 : nullptr;
     return launch_pow(S32, ct, at, p.tail, s);
   }
   return hipSuccess;

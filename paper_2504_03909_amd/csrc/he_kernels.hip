@@ -1122,12 +1122,16 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_hist_final(DKey key, HistW
       lo_max = max(lo_max, (ws.fch[w] + 1) >> 1);
       hi_any |= ws.fch[w] >> 1;
     }
-    uint32_t acc[K], b[K];
+    // past this group's partials the multiplier is the Montgomery form of 1;
+    // each partial is loaded one product ahead of its use
+    uint32_t acc[K], b[K], nb[K];
     ld29<K, G>(acc, my_n ? ws.partials + (p0 * 2 + slot) * S29 : one29);
+    ld29<K, G>(nb, 1 < my_n ? ws.partials + ((p0 + 1) * 2 + slot) * S29 : one29);
 #pragma unroll 1
     for (uint32_t k = 1; k < lo_max; ++k) {
-      // past this group's partials the multiplier is the Montgomery form of 1
-      ld29<K, G>(b, k < my_n ? ws.partials + ((p0 + k) * 2 + slot) * S29 : one29);
+#pragma unroll
+      for (int j = 0; j < K; ++j) b[j] = nb[j];
+      if (k + 1 < lo_max) ld29<K, G>(nb, k + 1 < my_n ? ws.partials + ((p0 + k + 1) * 2 + slot) * S29 : one29);
       mm29<K, G>(acc, b, acc, M, lds);
     }
     if (hi_any) {  // wave-uniform

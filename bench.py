@@ -57,22 +57,48 @@ MI355X_HBM_BPS = 8.0e12
 # scaled by a 256 MiB copy (profiles/enc_crt_2048_100k_counters.md), and the
 # digest of the kernel sources those passes ran on (kernel_sources_digest()).
 # The figure is reported only while the sources still have that digest.
-ENC_LAUNCH_TRAFFIC = {"bytes": 4.0916e10, "sources_sha256_16": "8d7ba548e6080c75"}
+ENC_LAUNCH_TRAFFIC = {"bytes": 4.0916e10, "sources_sha256_16": "38e45e0dc621ef3b"}
 # the kernels and the host code that picks their launches and exponent schedules
 KERNEL_SOURCES = ("he_kernels.hip", "he_internal.hpp", "hist_bucket.hpp", "mont.hpp", "mont29.hpp",
                   "radix29.hpp", "he_api.cpp", "keysetup.hpp")
 
 
+def _code_only(text: str) -> str:
+    """C++ source without its comments and with runs of white space collapsed,
+    so that edits of comments or layout leave the digest unchanged."""
+    out, i, n = [], 0, len(text)
+    while i < n:
+        c = text[i]
+        if c in "\"'":
+            j = i + 1
+            while j < n and text[j] != c:
+                j += 2 if text[j] == "\\" else 1
+            out.append(text[i:j + 1])
+            i = j + 1
+        elif text.startswith("//", i):
+            j = text.find("\n", i)
+            i = n if j < 0 else j
+        elif text.startswith("/*", i):
+            j = text.find("*/", i + 2)
+            i = n if j < 0 else j + 2
+            out.append(" ")
+        else:
+            out.append(c)
+            i += 1
+    return " ".join("".join(out).split())
+
+
 def kernel_sources_digest() -> str:
-    """First 16 hex digits of the SHA-256 of the kernel sources and the build
-    flags they compile with (include paths relative to the repository, so the
-    digest is the same wherever the tree is checked out)."""
+    """First 16 hex digits of the SHA-256 of the kernel sources (code only:
+    comments and layout do not count) and the build flags they compile with
+    (include paths relative to the repository, so the digest is the same
+    wherever the tree is checked out)."""
     import hashlib
     from paper_2504_03909_amd import build as B
     h = hashlib.sha256()
     for name in KERNEL_SOURCES:
-        with open(os.path.join(ROOT, "paper_2504_03909_amd", "csrc", name), "rb") as f:
-            h.update(name.encode() + b"\0" + f.read())
+        with open(os.path.join(ROOT, "paper_2504_03909_amd", "csrc", name), encoding="utf-8") as f:
+            h.update(name.encode() + b"\0" + _code_only(f.read()).encode())
     h.update(" ".join(f.replace(ROOT, ".") for f in B.COMMON).encode())
     return h.hexdigest()[:16]
 

@@ -215,11 +215,11 @@ he::PowLaunch pow_launch_at(int KP, int kind, uint64_t count, PowShape sh) {
 
 // The launches of shape `sh` over `count` ciphertexts.  With sh.tailG, the
 // ciphertexts that fill whole rounds of the main launch's resident waves
-// (every wave the same number of units of 64 / G integers of one prime) go
-// to the main launch and the rest, less than one round, to a launch at
-// sh.tailG lanes per integer, whose fewer integers per wave spread that
-// remainder over more waves.  No split when there is no whole round or no
-// remainder.
+// (as many units of 64 / G integers of one prime as a whole number of
+// units per wave) go to the main launch and the rest, less than one round,
+// to a launch at sh.tailG lanes per integer, whose fewer integers per wave
+// spread that remainder over more waves.  No split when there is no whole
+// round or no remainder.
 he::PowPlan pow_plan_at(int KP, int kind, uint64_t count, PowShape sh) {
   he::PowPlan p{pow_launch_at(KP, kind, count, sh), count, he::PowLaunch{0, 0, 0}};
   const int S32 = pow_s32(KP, kind);

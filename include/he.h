@@ -86,12 +86,15 @@ int he_key_export(const he_key *key, uint32_t *n, uint32_t *p, uint32_t *q);
 /* Side-channel hardening of the private-key exponentiations (the CRT
  * encryption's r^(q mod (p-1)) mod p and x^p mod p^2, and decryption's
  * c^(p-1) mod p^2, whose exponents are secret; Sec. III-B: only the active
- * party holds p and q).  Their sequence of operations never depends on the
- * exponent.  With on != 0 the window-table reads do not either: every window
- * reads all 32 table entries and keeps the one its digit names by a mask, so
- * the device addresses touched are a function of the sizes only.  Off (the
- * default) each window reads the one entry it needs.  Results are identical
- * bit for bit.  Applies to calls enqueued after it returns; must not run
+ * party holds p and q).  Off (the default), each exponentiation follows the
+ * key's sliding-window schedule: the same sequence of operations for every
+ * ciphertext and call, a function of p and q (not of the data), and each
+ * window reads the one table entry it names.  With on != 0 they use fixed
+ * 5-bit windows, one multiplication per window whatever its digit, and
+ * every window reads all 32 table entries and keeps the one its digit names
+ * by a mask, so neither the operations nor the device addresses touched
+ * depend on the exponent (about 1.6x the default's encryption time on the
+ * 2048-bit pass).  Results are identical bit for bit.  Applies to calls enqueued after it returns; must not run
  * concurrently with other calls on the same key.  HE_ERR_ARG for a null key. */
 int he_key_set_constant_time(he_key *key, int on);
 

@@ -396,6 +396,23 @@ def main():
     obf_same = bool(torch.equal(ct_obf, ct.view(-1, 2 * L)))
     t_off, t_on = obf_marks[0].elapsed_time(obf_marks[1]), obf_marks[1].elapsed_time(obf_marks[2])
     del rho, ct_obf
+    # Beside the step: the public-key path, c = (1 + m n) r^n mod n^2 by one
+    # exponentiation mod n^2 (what a holder of n alone runs), on the step's
+    # first 50,000 values; bit-identical to the CRT path's ciphertexts.
+    n_pub = 50_000
+    pub = he.Key.public(KEY_BITS, n)
+    ct_pub = he.encrypt(pub, m_last[:n_pub], seed=R_SEED)
+    pub_marks = [ev() for _ in range(2)]
+    pub_marks[0].record(stream)
+    he.encrypt(pub, m_last[:n_pub], seed=R_SEED, out=ct_pub)
+    pub_marks[1].record(stream)
+    torch.cuda.synchronize()
+    pub_same = bool(torch.equal(ct_pub, ct.view(-1, 2 * L)[:n_pub]))
+    t_pub = pub_marks[0].elapsed_time(pub_marks[1])
+    # x mod n^2 (2 products), into and out of the exponentiation's form (2),
+    # the exponentiation by n, f = 1 + m n and the product with it (3)
+    pub_products = modexp_products(n, 2 * L) + 7 * mm_products(2 * L)
+    del ct_pub, pub
     # Beside the step: packed decryption of the same 16,384 histogram
     # ciphertexts (the passive party folds 4 per ciphertext).
     pk_marks = [ev() for _ in range(3)]
@@ -518,6 +535,13 @@ def main():
             "online_encrypt_ms": round(t_on, 3),
             "online_encryptions_per_s": round(2 * M / (t_on / 1e3), 1),
             "equals_encrypt": obf_same,
+        },
+        "public_key_encryption": {
+            "count": n_pub, "ms": round(t_pub, 3),
+            "encryptions_per_s": round(n_pub / (t_pub / 1e3), 1),
+            "products_per_encryption": pub_products,
+            "alu_frac": round(n_pub * pub_products / (t_pub / 1e3) / PEAK_MUL32_PER_S, 4),
+            "equals_crt_encrypt": pub_same,
         },
     }
     del ct, hist, job

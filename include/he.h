@@ -257,9 +257,12 @@ int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t dec_count, u
 
 /* Sets the launch shape he_crt_autotune would remember, without timing (a
  * shape measured once, pinned in a deployment): for kind 0 (the mod-p
- * exponentiation of encryption), 1 (the lift) or 2 (decryption) at this
- * key's size, on the current device, for counts of count's size class (bit
- * length): lanes per integer (2, 4, 8 or 16 where built for the kind),
+ * exponentiation of encryption), 1 (the lift), 2 (decryption) or 3 (the
+ * exponentiation by n mod n^2 of public-key encryption, also the path of a
+ * key holding n only) at this key's size, on the current device, for counts
+ * of count's size class (bit length; for kind 3 of (count + 1) / 2): lanes
+ * per integer (2, 4, 8 or 16 where built for the kind; 8 or 16 for kind 3 at
+ * 2048-bit keys),
  * waves per SIMD (0 = own occupancy, 2 or 3) and lanes of the last partial
  * round's launch (0 = one launch, else a built width above lanes).  Results
  * never depend on the shape.  HE_ERR_ARG for anything else. */

@@ -175,11 +175,6 @@ int ensure(Buf &b, size_t bytes, hipStream_t s) {
   return HE_OK;
 }
 
-uint32_t persistent_grid(int KP, int kind, uint64_t work_blocks) {
-  const uint32_t res = he::resident_blocks(KP, kind);
-  return (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(res, work_blocks));
-}
-
 // ------------------------------------------------- exponentiation launch shapes
 // Tuned shapes (lanes per integer, waves per SIMD) of the private-key
 // exponentiations per (device, key size, kind, count class), filled by
@@ -200,7 +195,9 @@ int count_class(uint64_t count) {
   return b;
 }
 
-int pow_s32(int KP, int kind) { return kind == 4 ? 16 * KP : 32 * KP; }
+// 32-bit limbs of the modulus of an exponentiation of `kind`: 4 mod P, 0
+// and 2 mod P^2, 1 (public key) mod n^2.
+int pow_s32(int KP, int kind) { return kind == 4 ? 16 * KP : (kind == 1 ? 64 * KP : 32 * KP); }
 
 he::PowLaunch pow_launch_at(int KP, int kind, uint64_t count, PowShape sh) {
   const int S32 = pow_s32(KP, kind);
@@ -281,11 +278,19 @@ int encrypt_impl(const he_key *key, const int64_t *m, uint64_t count, const uint
     HE_TRY_HIP(he::launch_enc_crt(KP, key->dk, m, count, r, r_seed, r_offset, tq, cpq, ct, (uint32_t *)w->tab.p,
                                   p1, p2, stream));
   } else {
-    const uint32_t grid = persistent_grid(KP, 1, ((count + 3) / 4 + 3) / 4);
-    int rc = ensure(w->tab, grid * he::table_bytes_per_block(KP, 1), stream);
+    // the exponentiation's units pair consecutive ciphertexts (both "primes"
+    // of a public-key unit pair are n^2)
+    he::PowPlan p = pow_plan(KP, 1, (count + 1) / 2);
+    int rc = ensure(w->tab, plan_table_bytes(KP, 1, p), stream);
     if (rc) return rc;
-    HE_TRY_HIP(he::launch_enc_pub(KP, key->dk, m, count, r, r_seed, r_offset, ct, (uint32_t *)w->tab.p, grid,
-                                  stream));
+    rc = ensure(w->ctr, 256, stream);
+    if (rc) return rc;
+    p.ctr = (uint32_t *)w->ctr.p;
+    // r mod n^2, then r^n mod n^2 in place: count + (count & 1) rows of 2L limbs
+    rc = ensure(w->tmp, (count + 1) * 2 * L * sizeof(uint32_t), stream);
+    if (rc) return rc;
+    HE_TRY_HIP(he::launch_enc_pub(KP, key->dk, m, count, r, r_seed, r_offset, (uint32_t *)w->tmp.p, ct,
+                                  (uint32_t *)w->tab.p, p, stream));
   }
   return HE_OK;
 }
@@ -1024,9 +1029,12 @@ extern "C" int he_crt_autotune(const he_key *key, uint64_t enc_count, uint64_t d
 extern "C" int he_crt_set_shape(const he_key *key, uint32_t kind, uint64_t count, uint32_t lanes, uint32_t waves,
                                 uint32_t tail_lanes) {
   if (!key) return fail(HE_ERR_ARG, "null key");
-  if (kind > 2) return fail(HE_ERR_ARG, "kind must be 0 (mod p), 1 (lift) or 2 (decryption)");
+  if (kind > 3)
+    return fail(HE_ERR_ARG, "kind must be 0 (mod p), 1 (lift), 2 (decryption) or 3 (public-key encryption)");
   if (count == 0) return fail(HE_ERR_ARG, "count must be at least 1");
-  const int KP = kp_of(key), k = kind == 0 ? 4 : (kind == 1 ? 0 : 2);
+  const int KP = kp_of(key), k = kind == 0 ? 4 : (kind == 1 ? 0 : (kind == 2 ? 2 : 1));
+  // public-key encryption plans its exponentiation over unit pairs of two ciphertexts
+  const uint64_t units = kind == 3 ? (count + 1) / 2 : count;
   const int S32 = pow_s32(KP, k);
   if (!he::pow_shape_valid(S32, (int)lanes))
     return fail(HE_ERR_ARG, "lanes " + std::to_string(lanes) + " not built for this kind and key size");
@@ -1036,7 +1044,7 @@ extern "C" int he_crt_set_shape(const he_key *key, uint32_t kind, uint64_t count
   int dev = 0;
   HE_TRY_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lk(g_pow_mu);
-  g_pow_tuned[{dev, KP, k, count_class(count)}] = PowShape{(int)lanes, (int)waves, (int)tail_lanes};
+  g_pow_tuned[{dev, KP, k, count_class(units)}] = PowShape{(int)lanes, (int)waves, (int)tail_lanes};
   return HE_OK;
 }
 

@@ -130,9 +130,11 @@ struct PowPlan {
 hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
                           uint64_t roff, uint32_t *tq, uint32_t *cpq, uint32_t *ct, uint32_t *tab,
                           const PowPlan &p1, const PowPlan &p2, hipStream_t s);
-hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
-                          const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *ct,
-                          uint32_t *tab, uint32_t grid, hipStream_t s);
+// Public-key encryption: x holds count + (count & 1) rows of S_N2 limbs (r mod
+// n^2, then x^n in place); p plans the exponentiation over (count + 1) / 2
+// unit pairs (kind 1).
+hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
+                          uint64_t roff, uint32_t *x, uint32_t *ct, uint32_t *tab, const PowPlan &p, hipStream_t s);
 hipError_t launch_enc_obf(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *rho,
                           uint32_t *ct, hipStream_t s);
 uint32_t ct_div_batch(uint64_t count);
@@ -183,9 +185,6 @@ hipError_t launch_hist(int KP, const DKey &k, const uint32_t *ctm, const DJob *h
 hipError_t launch_fill(uint32_t *p, uint64_t n, uint32_t v, hipStream_t s);
 hipError_t launch_probe_mul(uint64_t iters, uint32_t grid, uint32_t *sink, hipStream_t s);
 
-// Resident blocks of 256 threads the device holds for the persistent
-// public-key encryption (kind 1) and histogram product (kind 3) kernels.
-uint32_t resident_blocks(int KP, int kind);
 // The private-key exponentiation k_pow over an S32-limb modulus (S_P or
 // S_P2 32-bit limbs) at G lanes per integer: whether that shape is built,
 // its resident blocks with `dyn` bytes of dynamic LDS, and the dynamic LDS
@@ -193,11 +192,11 @@ uint32_t resident_blocks(int KP, int kind);
 bool pow_shape_valid(int S32, int G);
 uint32_t pow_resident_blocks(int S32, int G, uint32_t dyn);
 uint32_t pow_dyn_lds(int S32, int G, int waves);
-// Window-table scratch bytes per resident block: kinds 4 (mod P), 0 (lift
-// mod P^2), 2 (decryption mod P^2) at G lanes, 1 (public key, 16 lanes).
-uint64_t table_bytes_per_block(int KP, int kind, int G = 16);
-// Default lanes per integer for a private-key exponentiation of `kind`
-// over `count` ciphertexts.
+// Window-table scratch bytes per resident block of k_pow at G lanes: kinds 4
+// (mod P), 0 (lift mod P^2), 2 (decryption mod P^2), 1 (public key, mod n^2).
+uint64_t table_bytes_per_block(int KP, int kind, int G);
+// Default lanes per integer for an exponentiation of `kind` over `count`
+// unit pairs (ciphertexts for the private-key kinds).
 int pick_group(int KP, int kind, uint64_t count);
 
 }  // namespace he

@@ -254,52 +254,65 @@ __global__ __launch_bounds__(kBlockThreads) void k_enc_crt_b(DKey key, const int
 }
 
 // ------------------------------------------------------ public-key encryption
-// c = (1 + (m mod n) n) r^n mod n^2 by one exponentiation mod n^2.  The seeded
-// X (L + 2 limbs) is used as is: r^n mod n^2 depends only on r mod n.
+// c = (1 + (m mod n) n) r^n mod n^2 by one exponentiation mod n^2, in three
+// launches like the CRT path: k_pub_pre reduces r mod n^2 (the seeded X of
+// L + 2 limbs is used as is: r^n mod n^2 depends only on r mod n), k_pow
+// raises it to n (its units of both "primes" are n^2 and n, so a unit pair
+// covers two consecutive ciphertexts), k_pub_post multiplies by 1 + (m mod
+// n) n.  One 16-lane group per ciphertext in the light kernels.  x has
+// count + (count & 1) rows: an odd count's last row is repeated, so the
+// exponentiation's last unit pair reads and writes a row of its own.
 template <int KP>
-__global__ __launch_bounds__(kBlockThreads) void k_enc_pub(
-    DKey key, const int64_t *__restrict__ m, uint64_t count, const uint32_t *__restrict__ r,
-    uint64_t seed, uint64_t roff, uint32_t *__restrict__ ct, uint32_t *__restrict__ tabs) {
+__global__ __launch_bounds__(kBlockThreads) void k_pub_pre(DKey key, uint64_t count, const uint32_t *__restrict__ r,
+                                                          uint64_t seed, uint64_t roff, uint32_t *__restrict__ x) {
   constexpr int KN2 = 4 * KP, SN2 = 64 * KP, L = 32 * KP;
-  constexpr int S29 = he29::limbs_for_group(SN2, 16), ROW = 2 * S29 > SN2 ? 2 * S29 : SN2;
-  __shared__ __align__(16) uint32_t lds_all[16 * ROW + S29];
-  uint32_t *const zeros = lds_all + 16 * ROW;
-  zero_lds(zeros, S29);
-  const uint32_t g = group_in_wave();
-  uint32_t *lds = lds_all + (wave_in_block() * 4 + g) * ROW;
-  const uint64_t gw = (uint64_t)blockIdx.x * 4 + wave_in_block();
-  const uint64_t nw = (uint64_t)gridDim.x * 4;
-  uint32_t *tab = tabs + (gw * 4 + g) * (uint64_t)((kTable + 1) * S29);
-  const uint64_t nquads = (count + 3) / 4;
+  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SN2;
+  const uint64_t rows = count + (count & 1);
+  uint64_t row = (uint64_t)blockIdx.x * 16 + gi;
+  const bool valid = row < rows;
+  if (!valid) row = rows - 1;
+  const uint64_t i = row < count ? row : count - 1;
   const uint64_t W = (uint64_t)L / 2 + 1;
   const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
-  for (uint64_t qd = gw; qd < nquads; qd += nw) {
-    uint64_t i = qd * 4 + g;
-    const bool valid = i < count;
-    if (!valid) i = count - 1;
-    uint32_t x[KN2], c[KN2], f[KN2];
-    if (r)
-      ld_part<KN2>(x, r + i * L, L);
-    else
-      seeded_limbs<KN2>(x, seed, (roff + i) * W, 0, L + 2);
-    // x mod n^2 (a Montgomery product with R^2 gives x R, one with 1 leaves
-    // the Montgomery domain), then x^n mod n^2
-    ld<KN2>(c, key.n2.R2);
-    mont_mul<KN2>(x, x, c, M, lds);
-    set_small(c, 1u);
-    mont_mul<KN2>(x, x, c, M, lds);
-    pow29<KN2, 16>(x, key.e_n, tab, key.n2, lds, zeros, false);  // public exponent
-    // f = 1 + (m mod n) n, exact (< n^2), in Montgomery form
-    ld_part<KN2>(c, key.n.N, L);
-    signed_mod<KN2>(f, m ? m[i] : 0, c);
-    ld<KN2>(c, key.nR_n2);
-    mont_mul<KN2>(f, f, c, M, lds);
-    add_one<KN2>(f);
-    ld<KN2>(c, key.n2.R2);
-    mont_mul<KN2>(f, f, c, M, lds);
-    mont_mul<KN2>(x, x, f, M, lds);
-    if (valid) st<KN2>(ct + i * SN2, x);
-  }
+  uint32_t v[KN2], c[KN2];
+  if (r)
+    ld_part<KN2>(v, r + i * L, L);
+  else
+    seeded_limbs<KN2>(v, seed, (roff + i) * W, 0, L + 2);
+  // v mod n^2: a Montgomery product with R^2 gives v R, one with 1 leaves
+  // the Montgomery domain
+  ld<KN2>(c, key.n2.R2);
+  mont_mul<KN2>(v, v, c, M, lds);
+  set_small(c, 1u);
+  mont_mul<KN2>(v, v, c, M, lds);
+  if (valid) st<KN2>(x + row * SN2, v);
+}
+
+template <int KP>
+__global__ __launch_bounds__(kBlockThreads) void k_pub_post(DKey key, const int64_t *__restrict__ m, uint64_t count,
+                                                           const uint32_t *__restrict__ x, uint32_t *__restrict__ ct) {
+  constexpr int KN2 = 4 * KP, SN2 = 64 * KP, L = 32 * KP;
+  __shared__ __align__(16) uint32_t lds_all[16 * SN2];
+  const uint32_t gi = wave_in_block() * 4 + group_in_wave();
+  uint32_t *lds = lds_all + gi * SN2;
+  uint64_t i = (uint64_t)blockIdx.x * 16 + gi;
+  const bool valid = i < count;
+  if (!valid) i = count - 1;
+  const Mod<KN2> M = load_mod<KN2>(key.n2.N, key.n2.ninv);
+  uint32_t v[KN2], c[KN2], f[KN2];
+  ld<KN2>(v, x + i * SN2);
+  // f = 1 + (m mod n) n, exact (< n^2), in Montgomery form
+  ld_part<KN2>(c, key.n.N, L);
+  signed_mod<KN2>(f, m ? m[i] : 0, c);
+  ld<KN2>(c, key.nR_n2);
+  mont_mul<KN2>(f, f, c, M, lds);
+  add_one<KN2>(f);
+  ld<KN2>(c, key.n2.R2);
+  mont_mul<KN2>(f, f, c, M, lds);
+  mont_mul<KN2>(v, v, f, M, lds);
+  if (valid) st<KN2>(ct + i * SN2, v);
 }
 
 // ------------------------------------------------ obfuscated encryption
@@ -1205,20 +1218,29 @@ static const void *pow_kernel(int S32, int G, bool ct) {
       return G == 2 ? pow_fn<16, 2>(ct) : G == 4 ? pow_fn<16, 4>(ct) : G == 8 ? pow_fn<16, 8>(ct) : pow_fn<16, 16>(ct);
     case 32:
       return G == 2 ? pow_fn<32, 2>(ct) : G == 4 ? pow_fn<32, 4>(ct) : G == 8 ? pow_fn<32, 8>(ct) : pow_fn<32, 16>(ct);
-    default:  // 64: 2-lane groups would exceed the column bound of the radix-2^29 products
+    case 64:  // 2-lane groups would exceed the column bound of the radix-2^29 products
       return G == 4 ? pow_fn<64, 4>(ct) : G == 8 ? pow_fn<64, 8>(ct) : pow_fn<64, 16>(ct);
+    default:  // 128: the public exponent n mod n^2 at 2048-bit keys, never secret
+      return G == 8 ? (const void *)k_pow<128, 8, false> : (const void *)k_pow<128, 16, false>;
   }
 }
 bool pow_shape_valid(int S32, int G) {
-  return (G == 2 || G == 4 || G == 8 || G == 16) && (S32 == 16 || S32 == 32 || (S32 == 64 && G != 2));
+  return (G == 2 || G == 4 || G == 8 || G == 16) &&
+         (S32 == 16 || S32 == 32 || (S32 == 64 && G != 2) || (S32 == 128 && G >= 8));
 }
 
-// Modulus and exponent of a private-key exponentiation per prime: kind 4
-// r^(Q mod (P-1)) mod P, kind 0 t^P mod P^2, kind 2 c^(P-1) mod P^2.
+// Modulus and exponent of an exponentiation per prime: kind 4
+// r^(Q mod (P-1)) mod P, kind 0 t^P mod P^2, kind 2 c^(P-1) mod P^2; kind 1
+// (public key) x^n mod n^2 for both.
 static PowArgs pow_args(const DKey &k, int kind, const uint32_t *in, uint32_t in_stride, uint32_t in_limbs,
                         uint32_t *out, uint32_t out_stride, uint64_t count, uint32_t *tabs) {
   PowArgs a{};
   for (int w = 0; w < 2; ++w) {
+    if (kind == 1) {
+      a.mod[w] = k.n2;
+      a.exp[w] = k.e_n;
+      continue;
+    }
     const DPrime &P = k.pr[w];
     a.mod[w] = kind == 4 ? P.P : P.P2;
     a.exp[w] = kind == 4 ? P.e_enc : (kind == 0 ? P.e_lift : P.e_dec);
@@ -1272,7 +1294,7 @@ hipError_t launch_pow_kind(int KP, const DKey &k, int kind, const uint32_t *in, 
                            uint32_t in_limbs, uint32_t *out, uint32_t out_stride, uint64_t count, uint32_t *tab,
                            const PowPlan &p, hipStream_t s) {
   if (!count) return hipSuccess;
-  const int S32 = kind == 4 ? 16 * KP : 32 * KP;
+  const int S32 = kind == 4 ? 16 * KP : (kind == 1 ? 64 * KP : 32 * KP);
   return launch_pow_plan(S32, k.ct != 0, pow_args(k, kind, in, in_stride, in_limbs, out, out_stride, count, tab), p,
                          s);
 }
@@ -1321,15 +1343,23 @@ hipError_t launch_enc_crt(int KP, const DKey &k, const int64_t *m, uint64_t coun
                  : enc_crt<2>(k, m, count, r, seed, roff, tq, cpq, ct, tab, p1, p2, s);
 }
 
-hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count,
-                          const uint32_t *r, uint64_t seed, uint64_t roff, uint32_t *ct,
-                          uint32_t *tab, uint32_t grid, hipStream_t s) {
-  if (!count) return hipSuccess;
-  if (KP == 1)
-    hipLaunchKernelGGL(k_enc_pub<1>, dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff, ct, tab);
-  else
-    hipLaunchKernelGGL(k_enc_pub<2>, dim3(grid), dim3(kBlockThreads), 0, s, k, m, count, r, seed, roff, ct, tab);
+template <int KP>
+static hipError_t enc_pub(const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
+                          uint64_t roff, uint32_t *x, uint32_t *ct, uint32_t *tab, const PowPlan &p, hipStream_t s) {
+  constexpr int SN2 = 64 * KP;
+  hipLaunchKernelGGL(k_pub_pre<KP>, dim3(blocks_for(count + (count & 1), 16)), dim3(kBlockThreads), 0, s, k, count,
+                     r, seed, roff, x);
+  const hipError_t e = launch_pow_plan(SN2, false, pow_args(k, 1, x, SN2, SN2, x, SN2, (count + 1) / 2, tab), p, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_pub_post<KP>, dim3(blocks_for(count, 16)), dim3(kBlockThreads), 0, s, k, m, count,
+                     (const uint32_t *)x, ct);
   return hipGetLastError();
+}
+hipError_t launch_enc_pub(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *r, uint64_t seed,
+                          uint64_t roff, uint32_t *x, uint32_t *ct, uint32_t *tab, const PowPlan &p, hipStream_t s) {
+  if (!count) return hipSuccess;
+  return KP == 1 ? enc_pub<1>(k, m, count, r, seed, roff, x, ct, tab, p, s)
+                 : enc_pub<2>(k, m, count, r, seed, roff, x, ct, tab, p, s);
 }
 
 hipError_t launch_enc_obf(int KP, const DKey &k, const int64_t *m, uint64_t count, const uint32_t *rho,
@@ -1490,13 +1520,6 @@ hipError_t launch_probe_mul(uint64_t iters, uint32_t grid, uint32_t *sink, hipSt
   return hipGetLastError();
 }
 
-static uint32_t occupancy_blocks(const void *fn) {
-  int dev = 0, cus = 0, nb = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 1;
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kBlockThreads, 0) != hipSuccess || nb < 1) nb = 1;
-  return (uint32_t)(nb * std::max(cus, 1));
-}
 
 // Elements per inversion batch of k_ct_div: enough groups for about two
 // waves per SIMD, each group then chains as many elements as needed.
@@ -1510,19 +1533,6 @@ uint32_t ct_div_batch(uint64_t count) {
   }
   const uint64_t groups = (uint64_t)cus * 4 * 2 * 4;
   return (uint32_t)std::max<uint64_t>(1, (count + groups - 1) / groups);
-}
-
-template <int KP>
-static const void *kernel_of(int kind) {
-  return kind == 1 ? (const void *)k_enc_pub<KP> : (const void *)k_hist_chunk<KP, kHistGroup>;
-}
-
-uint32_t resident_blocks(int KP, int kind) {
-  static uint32_t cache[2][5] = {};
-  uint32_t &c = cache[KP - 1][kind];
-  if (c) return c;
-  c = occupancy_blocks(KP == 1 ? kernel_of<1>(kind) : kernel_of<2>(kind));
-  return c;
 }
 
 static int device_cus() {
@@ -1609,22 +1619,20 @@ uint32_t hist_dyn_lds(int KP, int G, int waves) {
 
 uint64_t table_bytes_per_block(int KP, int kind, int G) {
   // limbs of the modulus the kernel's exponentiation tables work in
-  // (radix-2^29 limbs); kind 1 the public-key kernel at 16-lane groups
-  const uint64_t S = (uint64_t)he29::limbs_for_group(kind == 1 ? 64 * KP : (kind == 4 ? 16 * KP : 32 * KP),
-                                                    kind == 1 ? 16 : G);
+  // (radix-2^29 limbs): mod P (kind 4), mod P^2 (0, 2), mod n^2 (1)
+  const uint64_t S = (uint64_t)he29::limbs_for_group(kind == 1 ? 64 * KP : (kind == 4 ? 16 * KP : 32 * KP), G);
   return (uint64_t)(kBlockThreads / G) * (kTable + 1) * S * sizeof(uint32_t);
 }
 
-// Group width for a private-key exponentiation (kind 4 mod P, 0 lift, 2
-// decryption) over `count` ciphertexts: the narrowest group (more limbs per
-// lane, less cross-lane work per product) whose launch still gives every
-// SIMD at least two waves; below that, wider groups buy parallelism.
+// Group width for an exponentiation (kind 4 mod P, 0 lift, 2 decryption, 1
+// public key) over `count` units pairs: the narrowest built group (more
+// limbs per lane, less cross-lane work per product) whose launch still gives
+// every SIMD at least two waves; below that, wider groups buy parallelism.
 int pick_group(int KP, int kind, uint64_t count) {
-  (void)KP;
+  const int S32 = kind == 4 ? 16 * KP : (kind == 1 ? 64 * KP : 32 * KP);
   const uint64_t need = 2ull * 4 * (uint64_t)device_cus();  // two waves on each of the 4 SIMDs per CU
-  // the mod-P exponentiation (kind 4) also has 2-lane groups
   for (int G : {2, 4, 8}) {
-    if (G == 2 && kind != 4) continue;
+    if (!pow_shape_valid(S32, G) || (G == 2 && kind != 4)) continue;  // 2 lanes: the mod-P exponentiation only
     const uint64_t waves = 2 * ((count + 64 / G - 1) / (64 / G));
     if (waves >= need) return G;
   }

@@ -409,12 +409,12 @@ def crt_autotune(key: Key, enc_count: int, dec_count: int, stream=None):
             for i, name in enumerate(("mod_p", "lift", "decrypt"))}
 
 
-POW_KINDS = {"mod_p": 0, "lift": 1, "decrypt": 2}
+POW_KINDS = {"mod_p": 0, "lift": 1, "decrypt": 2, "public": 3}
 
 
 def crt_set_shape(key: Key, kind: str, count: int, lanes: int, waves: int = 0, tail_lanes: int = 0) -> None:
-    """Pins the launch shape of one private-key exponentiation kind ("mod_p",
-    "lift" or "decrypt") for counts of count's size class (see
+    """Pins the launch shape of one exponentiation kind ("mod_p", "lift",
+    "decrypt" or "public") for counts of count's size class (see
     he_crt_set_shape)."""
     _check(_crt_set_shape(key.handle, POW_KINDS[kind], count, lanes, waves, tail_lanes))
 

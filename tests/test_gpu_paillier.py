@@ -288,6 +288,36 @@ def test_last_round_launch_exact(he):
             he.crt_set_shape(k, bad[0], n, *bad[1:])
 
 
+def test_public_key_path_pinned_shapes_equal_crt(he):
+    """The public-key path (r mod n^2, the exponentiation by n in the
+    exponentiation kernel over pairs of ciphertexts, the product with
+    1 + m n) at pinned shapes -- 16 lanes, and 8 lanes with the last partial
+    round at 16 -- on an odd count equals the CRT path's ciphertexts for the
+    same seeded r, which equal the oracle's; a key holding n only takes the
+    same path.  Widths that are not built are refused."""
+    import torch
+    bits, n = 2048, 60_001
+    sk = oracle_key(bits, 2)
+    pk = sk.public
+    k = gpu_key(bits, 2)
+    kp = he.Key.public(bits, pk.n)
+    say(f"public path, pinned shapes, {n} encryptions")
+    rng = np.random.default_rng(93)
+    m = rng.integers(-(1 << 62), 1 << 62, size=n, dtype=np.int64)
+    want = he.encrypt(k, dev(m), seed=11)
+    pick = [0, 1, n // 2, n - 2, n - 1]
+    assert he.limbs_to_ints(host(want)[pick]) == pool.encrypt_many(
+        pk, [int(m[i]) % pk.n for i in pick], [P.seeded_r(pk.n, bits, 11, i) for i in pick])
+    for lanes, tail in ((16, 0), (8, 16)):
+        he.crt_set_shape(k, "public", n, lanes, 0, tail)
+        he.crt_set_shape(kp, "public", n, lanes, 0, tail)
+        assert torch.equal(he.encrypt(k, dev(m), seed=11, public=True), want), (lanes, tail)
+        assert torch.equal(he.encrypt(kp, dev(m), seed=11), want), (lanes, tail)
+    for bad in ((4, 0, 0), (8, 0, 8), (16, 1, 0)):
+        with pytest.raises(he.HEError):
+            he.crt_set_shape(k, "public", n, *bad)
+
+
 # ---------------------------------------------------------- decryption
 @pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
 def test_decrypt_exact(he, bits, seed):

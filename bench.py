@@ -273,6 +273,9 @@ def main():
     ap.add_argument("--capacity-requests", type=int, default=1000,
                     help="requests of the served trace at 0.8x the measured capacity")
     ap.add_argument("--rate", type=float, default=200.0)
+    ap.add_argument("--enc-slice", type=int, default=0,
+                    help="served, continuous policy: encryptions longer than this go out as several launches "
+                         "(0: one launch)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB (counter calibration)")
     args = ap.parse_args()
@@ -844,7 +847,7 @@ def bench_served(args, compact=False):
 
     # one backend per policy for every run (the library keeps one workspace
     # per stream)
-    backends = {"continuous": serve.backend_for(setups, n_streams=4, enc_slice=16384),
+    backends = {"continuous": serve.backend_for(setups, n_streams=4, enc_slice=args.enc_slice),
                 "fifo": serve.backend_for(setups, n_streams=1)}
 
     def run(rate, n, policy, seed):

@@ -245,8 +245,11 @@ int he_hist_autotune(const he_key *key, const uint32_t *ct, uint64_t rows, int c
  * depend on the data), and the fastest per kind is remembered for the
  * count's size class (bit length) on this device and key size; later
  * he_encrypt, he_obfuscators and he_decrypt calls of that class use it.
- * Results never depend on the shape.  Allocates trial buffers and
- * synchronises `stream`.
+ * Results never depend on the shape.  Without a tuned (or pinned) shape a
+ * kind runs at the narrowest built width that gives every SIMD two waves,
+ * at the kernel's own occupancy, or at two waves per SIMD where those take
+ * as many rounds of units (units / resident waves, rounded up).  Allocates
+ * trial buffers and synchronises `stream`.
  * choice: optional host uint32[9]: per kind (the mod-p exponentiation, the
  *         lift, decryption) lanes, waves (0 = own occupancy) and lanes of
  *         the remainder's launch (0 = one launch).

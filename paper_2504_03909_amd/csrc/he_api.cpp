@@ -210,6 +210,23 @@ he::PowLaunch pow_launch_at(int KP, int kind, uint64_t count, PowShape sh) {
   return he::PowLaunch{sh.G, grid, dyn};
 }
 
+// The shape used when the autotuner has not run: pick_group's width, at the
+// kernel's own occupancy unless two waves per SIMD take as many rounds of
+// units (the resident waves each claiming one) to get through the batch.
+// Fewer waves per SIMD each run faster, so in that case they finish sooner.
+PowShape default_pow_shape(int KP, int kind, uint64_t count) {
+  const int S32 = pow_s32(KP, kind);
+  PowShape sh{he::pick_group(KP, kind, count), 0, 0};
+  const uint32_t dyn2 = he::pow_dyn_lds(S32, sh.G, 2);
+  if (dyn2 == 0) return sh;
+  const uint64_t per_wave = 64 / sh.G;
+  const uint64_t units = 2 * ((count + per_wave - 1) / per_wave);
+  const uint64_t w_own = 4ull * he::pow_resident_blocks(S32, sh.G, 0);
+  const uint64_t w_two = 4ull * he::pow_resident_blocks(S32, sh.G, dyn2);
+  if (w_two < w_own && (units + w_two - 1) / w_two == (units + w_own - 1) / w_own) sh.waves = 2;
+  return sh;
+}
+
 // The launches of shape `sh` over `count` ciphertexts.  With sh.tailG, the
 // ciphertexts that fill whole rounds of the main launch's resident waves
 // (as many units of 64 / G integers of one prime as a whole number of
@@ -238,11 +255,11 @@ uint64_t plan_table_bytes(int KP, int kind, const he::PowPlan &p) {
   return b;
 }
 
-// The launches of a private-key exponentiation over `count` ciphertexts:
-// the tuned shape for its class if the autotuner ran, else the default
-// (pick_group's width, the kernel's maximum occupancy, one launch).
+// The launches of an exponentiation over `count` ciphertexts (units): the
+// tuned shape for its class if the autotuner ran, else default_pow_shape's
+// (one launch).
 he::PowPlan pow_plan(int KP, int kind, uint64_t count) {
-  PowShape sh;
+  PowShape sh = default_pow_shape(KP, kind, count);
   int dev = 0;
   (void)hipGetDevice(&dev);
   {

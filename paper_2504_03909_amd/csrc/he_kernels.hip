@@ -1564,9 +1564,6 @@ uint32_t pow_resident_blocks(int S32, int G, uint32_t dyn) {
   return r;
 }
 
-// Dynamic LDS that caps k_pow<S32, G> at `waves` blocks (= waves per SIMD)
-// per compute unit: enough that waves + 1 blocks do not fit.  0 when waves
-// is 0 or the kernel's own occupancy is at most `waves`.
 // Dynamic LDS that makes at most `waves` blocks of `fn` fit a compute unit
 // (0 if its own occupancy `natural` is already at most that).
 static uint32_t cap_dyn_lds(const void *fn, int natural, int waves) {
@@ -1583,6 +1580,9 @@ static uint32_t cap_dyn_lds(const void *fn, int natural, int waves) {
   return dyn > 0 ? (uint32_t)((dyn + 255) / 256 * 256) : 0u;
 }
 
+// Dynamic LDS that caps k_pow<S32, G> at `waves` blocks (= waves per SIMD)
+// per compute unit: enough that waves + 1 blocks do not fit.  0 when waves
+// is 0 or the kernel's own occupancy is at most `waves`.
 uint32_t pow_dyn_lds(int S32, int G, int waves) {
   if (waves <= 0 || !pow_shape_valid(S32, G)) return 0;
   return cap_dyn_lds(pow_kernel(S32, G, false), (int)(pow_resident_blocks(S32, G, 0) / (uint32_t)device_cus()),

@@ -202,6 +202,33 @@ def test_exponentiation_group_widths(he):
         assert got == want
 
 
+def test_untuned_default_shapes_exact(he):
+    """32,768 encryptions and decryptions at the untuned default shapes --
+    at 2048 bits the lift's and decryption's 4,096 units take two rounds at
+    three or at two waves per SIMD, so the default runs two -- equal the
+    same work at pinned own-occupancy shapes: every decryption equals its
+    plaintext and sampled ciphertexts equal the oracle's."""
+    import torch
+    bits, n = 2048, 32768
+    sk = oracle_key(bits, 2)
+    pk = sk.public
+    k = gpu_key(bits, 2)
+    say(f"untuned default shapes, {n} encryptions and decryptions")
+    rng = np.random.default_rng(95)
+    m = rng.integers(-(1 << 62), 1 << 62, size=n, dtype=np.int64)
+    ct = he.encrypt(k, dev(m), seed=13)
+    dm, raw, ovf = he.decrypt(k, ct, raw=True)
+    assert host(dm).tolist() == m.tolist() and int(host(ovf)[0]) == 0
+    pick = [0, 1, n // 3, n - 17, n - 1]
+    want = pool.encrypt_many(pk, [int(m[i]) % pk.n for i in pick], [P.seeded_r(pk.n, bits, 13, i) for i in pick])
+    assert he.limbs_to_ints(host(ct)[pick]) == want
+    for kind, lanes in (("mod_p", 2), ("lift", 4), ("decrypt", 4)):
+        he.crt_set_shape(k, kind, n, lanes, 0, 0)
+    assert torch.equal(he.encrypt(k, dev(m), seed=13), ct)
+    dm2, raw2, _ = he.decrypt(k, ct, raw=True)
+    assert torch.equal(dm2, dm) and torch.equal(raw2, raw)
+
+
 @pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
 def test_constant_time_exponentiations(he, bits, seed):
     """With the key's constant-time table reads on, CRT encryption (every

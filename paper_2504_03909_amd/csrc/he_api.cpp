@@ -629,7 +629,7 @@ struct HistLayout {
   std::vector<he::DJob> dj;
   uint64_t total_fb = 0, total_f = 0, total_blocks = 0, total_perm = 0, items_cap = 0;
   uint64_t contributions = 0, rows = 0;
-  size_t o_jobs = 0, o_counts = 0, o_offs = 0, o_cursor = 0, o_fch = 0, o_fitem = 0, o_ftot = 0,
+  size_t o_jobs = 0, o_counts = 0, o_offs = 0, o_cursor = 0, o_fch = 0, o_fitem = 0, o_border = 0, o_ftot = 0,
          o_fbase = 0, o_nitems = 0, o_items = 0, o_perm = 0, o_part = 0, o_ctm = 0, bytes = 0;
   uint32_t chunk = 64, split = 2;
   int G = he::kHistGroup, waves = 0;  // product kernel: lanes per ciphertext, waves per SIMD cap (0: none)
@@ -692,6 +692,7 @@ int plan_layout(const he_key *key, const uint32_t *ct, uint64_t rows, int ct_for
   lay.o_cursor = take(lay.total_fb * 4);
   lay.o_fch = take(lay.total_fb * 4);
   lay.o_fitem = take(lay.total_fb * 4);
+  lay.o_border = take(lay.total_fb * 4);
   lay.o_ftot = take(lay.total_f * 4);
   lay.o_fbase = take(lay.total_f * 4);
   lay.o_nitems = take(8);  // item count, then the product kernel's work counter
@@ -715,6 +716,7 @@ he::HistWs bind_layout(const HistLayout &lay, char *base) {
   ws.cursor = (uint32_t *)(base + lay.o_cursor);
   ws.fch = (uint32_t *)(base + lay.o_fch);
   ws.fitem = (uint32_t *)(base + lay.o_fitem);
+  ws.border = (uint32_t *)(base + lay.o_border);
   ws.ftot = (uint32_t *)(base + lay.o_ftot);
   ws.fbase = (uint32_t *)(base + lay.o_fbase);
   ws.n_items = (uint32_t *)(base + lay.o_nitems);

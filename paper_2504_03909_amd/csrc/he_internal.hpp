@@ -83,6 +83,7 @@ struct HistWs {
   DJob *jobs;
   uint32_t n_jobs;
   uint32_t *counts, *offs, *cursor, *fch, *fitem;  // [total_fb]
+  uint32_t *border;                                // [total_fb]: per (job, feature), its bins by decreasing count
   uint32_t *ftot, *fbase;                          // [total_f]
   uint32_t *n_items;                               // device scalar
   uint32_t *next;                                  // device scalar: the product kernel's next wave unit

@@ -180,6 +180,61 @@ def test_split_and_chunk_variants(he, small, split, chunk):
 
 
 # ------------------------------------------------------- full-size shapes
+@pytest.mark.parametrize("bits,seed", [(1024, 1), (2048, 2)])
+def test_final_join_of_runs(he, bits, seed):
+    """Bins holding exactly 0 to 100 samples, aggregated with one partial per
+    sample (chunk 1) and per three, so that the final kernel joins every
+    number of runs (1, 2, 4, 8) with run lengths on both sides of the powers
+    of two; three features hold the same counts in different bins (other
+    ranks), and a second job in the same launch has 5 bins (ranks past its
+    bins are skipped).  Every decrypted sum is exact, sampled ciphertexts
+    equal the closed form, the counters equal the algorithm's count, and the
+    histograms equal those of the default chunk."""
+    import torch
+    say(f"final join of runs, {bits}-bit")
+    counts = [0, 1, 2, 3, 4, 5, 6, 7, 8, 9, 11, 15, 16, 17, 31, 32, 33, 35, 63, 64, 65, 100]
+    B, F, r_seed = len(counts), 3, 17
+    M = sum(counts)
+    sk, k = keys(bits, seed)
+    rng = np.random.default_rng(bits + 3)
+    base = np.repeat(np.arange(B), counts)
+    tab = np.stack([rng.permutation(B)[base][rng.permutation(M)] for _ in range(F)]).astype(np.uint8)
+    m = encode_all(W.gradients(M, W.streams(8)[1]))
+    ct = he.encrypt(k, dev(m.reshape(-1)), seed=r_seed).view(M, 2, -1)
+    idx2 = np.sort(rng.choice(M, size=300, replace=False)).astype(np.int64)
+    tab2 = (tab % 5).astype(np.uint8)
+    c = dict(bits=bits, sk=sk, k=k, m=m, r_seed=r_seed)
+
+    def jobs():
+        return [he.Job(dev(np.arange(M, dtype=np.int32)), dev(tab), B),
+                he.Job(dev(idx2.astype(np.int32)), dev(tab2), 5)]
+
+    hs64, _ = he.hist_aggregate_counted(k, ct, jobs(), chunk=64)
+    for chunk in (1, 3):
+        hs, cnt = he.hist_aggregate_counted(k, ct, jobs(), chunk=chunk, split=2)
+        for h, h64 in zip(hs, hs64):
+            assert torch.equal(h, h64), chunk
+        real = conv = 0
+        for (ix, tb, nb) in ((np.arange(M), tab, B), (idx2, tab2, 5)):
+            for f in range(F):
+                real += 2 * (ix.size - np.unique(tb[f][ix]).size)
+            conv += F * nb * 2
+        got = host(cnt).tolist()
+        assert got[0] == real and got[2] == conv and got[1] >= real + conv, (chunk, got, real, conv)
+    pk = sk.public
+    for (ix, tb, nb, h) in ((np.arange(M), tab, B, hs[0]), (idx2, tab2, 5, hs[1])):
+        dm, _, ovf = he.decrypt(k, h)
+        dm = host(dm)
+        assert int(host(ovf)[0]) == 0
+        for f in range(F):
+            assert np.array_equal(dm[f], plain_sums(m, ix, tb[f], nb)), (nb, f)
+    hh = host(hs[0])
+    for f, cnt_want, t in ((0, 100, 0), (1, 65, 1), (2, 17, 0), (0, 8, 1), (1, 1, 0), (2, 0, 1)):
+        b = int(np.flatnonzero(np.bincount(tab[f], minlength=B) == cnt_want)[0])
+        members = np.flatnonzero(tab[f] == b)
+        assert he.limbs_to_ints(hh[f, b, t][None])[0] == closed_form(pk, bits, r_seed, m, members, t), (f, b, t)
+
+
 def test_batched_64_jobs_2048(he):
     """64 uneven jobs (|S| log-uniform in [1e3, 2e5], F in [8, 128],
     B in {16, 64, 256}) over a pool of 200,000 samples, 2048-bit key: one

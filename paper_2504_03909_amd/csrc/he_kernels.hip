@@ -1102,102 +1102,168 @@ __global__ __launch_bounds__(kBlockThreads, G == 16 ? kHistWaves : 3) void k_his
   }
 }
 
+// Out of Montgomery form (a product with 1), exact, back to 32-bit limbs;
+// stored by the groups with `store`.
+template <int G, int K, int K32>
+__device__ __forceinline__ void final_out(uint32_t (&acc)[K], const Mod29<K> &M, uint32_t *lds, uint32_t *dst,
+                                          bool store) {
+  uint32_t one[K];
+  set_small<K, G>(one, 1u);
+  mm29<K, G>(acc, acc, one, M, lds);
+  canon29<K, G>(acc, M);
+  uint32_t y[K32];
+  to32<K, K32, G>(y, acc, lds);
+  if (store) st<K32, G>(dst, y);
+}
+
+// Ranks (within a feature, by decreasing bin count) that k_hist_final takes
+// one per block; higher ranks go four to a block.
+constexpr uint32_t kFinalSolo = 8;
+
 // Final product over the chunks of one (job, feature, bin), conversion out of
-// Montgomery form, and the store into the job's histogram.  One entry per
-// block at a time; the block's 16 groups are (slot g/h) x (8 parts).  The
-// entry's nch partials are cut into P runs of equal length (to one), P the
-// largest power of two that is at most 8 and at most nch / 2, so that a
-// heavy bin's chain is about nch / 8 products long instead of nch / 2; each
-// run's product is taken by one group, and the P products are joined in
-// log2(P) levels through LDS.  Blocks take the entries in the order of their
-// bins' rank by sample count within the feature, rank-major over all
-// (job, feature) pairs, so the longest chains start first.
+// Montgomery form, and the store into the job's histogram.  A block takes
+// one rank of one (job, feature) among the first kFinalSolo ranks, else four
+// consecutive ranks; the units go rank-major over all (job, feature) pairs,
+// so the heaviest bins start first.  An entry of nch >= 4 partials is taken
+// by the whole block, its 16 groups as (slot g/h) x (8 runs): the partials
+// are cut into P runs of equal length (to one), P the largest power of two
+// that is at most 8 and at most nch / 2, each run's product is one group's
+// chain (about nch / P products instead of nch / 2), and the P products are
+// joined in log2(P) levels through LDS.  Ranks are in decreasing count, so
+// once an entry has fewer than 4 partials so have the block's remaining
+// ones; those are taken one per wave, its 4 groups as (slot) x (first or
+// second half of the partials).
 template <int KP, int G>
 __global__ __launch_bounds__(kBlockThreads, 4) void k_hist_final(DKey key, HistWs ws) {
   static_assert(G == 16, "four groups per wave: two slots x two parts");
-  constexpr int S = 64 * KP, K32 = S / G, GW = 64 / G, kParts = 2 * (kBlockThreads / 64);
+  constexpr int S = 64 * KP, K32 = S / G, GW = 64 / G, kWaves = kBlockThreads / 64, kParts = 2 * kWaves;
   constexpr int S29 = he29::limbs_for_group(S, G), K = S29 / G, ROW = S29 > S ? S29 : S;
-  __shared__ __align__(16) uint32_t lds_all[(kBlockThreads / 64) * GW * ROW];
+  __shared__ __align__(16) uint32_t lds_all[kWaves * GW * ROW];
   const uint32_t wv = wave_in_block();
   const uint32_t g = (threadIdx.x & 63u) / G;
   uint32_t *lds = lds_all + (wv * GW + g) * ROW;
-  const uint32_t slot = g & 1u, part = 2 * wv + (g >> 1);
+  const uint32_t slot = g & 1u, half = g >> 1, part = 2 * wv + half;
   const Mod29<K> M = load_mod29<K, G>(key.n2);
   const uint32_t *one29 = key.n2.R1_29[he29::variant(G)];  // Montgomery form of 1
-  const uint64_t units = ws.total_f * 256;  // (rank, job-feature) pairs; ranks past a job's bins are skipped
+  const uint64_t solo = ws.total_f * kFinalSolo;
+  const uint64_t units = solo + ws.total_f * ((256 - kFinalSolo) / kWaves);  // ranks past a job's bins are skipped
   for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
-    const uint64_t jf = u % ws.total_f;
-    const uint32_t r = (uint32_t)(u / ws.total_f);
-    const DJob J = ws.jobs[find_job_by_f(ws.jobs, ws.n_jobs, jf)];
-    if (r >= J.B) continue;  // block-uniform
-    const uint64_t fb_f = (jf - J.f_off) * J.B;  // the feature's first entry within the job
-    const uint32_t bin = ws.border[J.fb_off + fb_f + r];
-    const uint64_t e = J.fb_off + fb_f + bin;
-    const uint32_t nch = ws.fch[e], first = ws.fitem[e];
-    uint32_t P = 1;
-    while (P < (uint32_t)kParts && 4 * P <= nch) P *= 2;
-    const bool mine = part < P;
-    const uint32_t lo = mine ? (uint32_t)((uint64_t)part * nch / P) : 0u;
-    const uint32_t len = mine ? (uint32_t)((uint64_t)(part + 1) * nch / P) - lo : 0u;
-    const uint32_t maxlen = (nch + P - 1) / P;
-    const bool wave_on = 2 * wv < P;  // wave-uniform: the wave holds a run
-    uint64_t done = 0;
-    uint32_t acc[K];
-    if (wave_on) {
-      // past this group's run the multiplier is the Montgomery form of 1;
-      // each partial is loaded one product ahead of its use
-      const uint64_t p0 = (uint64_t)first + lo;
-      uint32_t b[K], nb[K];
-      ld29<K, G>(acc, len ? ws.partials + (p0 * 2 + slot) * S29 : one29);
-      ld29<K, G>(nb, 1 < len ? ws.partials + ((p0 + 1) * 2 + slot) * S29 : one29);
-#pragma unroll 1
-      for (uint32_t k = 1; k < maxlen; ++k) {
-#pragma unroll
-        for (int j = 0; j < K; ++j) b[j] = nb[j];
-        if (k + 1 < maxlen) ld29<K, G>(nb, k + 1 < len ? ws.partials + ((p0 + k + 1) * 2 + slot) * S29 : one29);
-        mm29<K, G>(acc, b, acc, M, lds);
-      }
-      done += maxlen ? maxlen - 1 : 0;
+    uint64_t jf;
+    uint32_t r, r1;
+    if (u < solo) {
+      jf = u % ws.total_f;
+      r = (uint32_t)(u / ws.total_f);
+      r1 = r + 1;
+    } else {
+      const uint64_t v = u - solo;
+      jf = v % ws.total_f;
+      r = kFinalSolo + kWaves * (uint32_t)(v / ws.total_f);
+      r1 = r + kWaves;
     }
-    // level d joins run p with run p + d for p a multiple of 2d; only the
-    // even runs (half 0 of a wave) ever join, so a wave joins or not as a whole
-    for (uint32_t d = 1; d < P; d <<= 1) {  // block-uniform
-      if (wave_on) st29<K, G>(lds, acc);
-      __syncthreads();
-      const bool wave_join = (2 * wv) % (2 * d) == 0 && 2 * wv + d < P;
-      uint32_t other[K];
-      if (wave_join) {
-        const uint32_t q = part + d;  // in range for the joining (even) runs
-        const uint32_t qr = (g >> 1) == 0 ? (q >> 1) * GW + ((q & 1u) << 1 | slot) : wv * GW + g;
-        ld29<K, G>(other, lds_all + qr * ROW);
+    const DJob J = ws.jobs[find_job_by_f(ws.jobs, ws.n_jobs, jf)];
+    r1 = min(r1, J.B);
+    if (r >= r1) continue;  // block-uniform
+    const uint64_t fb_f = (jf - J.f_off) * J.B;  // the feature's first entry within the job
+    const uint32_t *bord = ws.border + J.fb_off + fb_f;
+    // entries of 4 or more partials, one at a time, the whole block in runs
+    for (; r < r1; ++r) {
+      const uint32_t bin = bord[r];
+      const uint64_t e = J.fb_off + fb_f + bin;
+      const uint32_t nch = ws.fch[e], first = ws.fitem[e];
+      if (nch < 4) break;  // block-uniform
+      uint32_t P = 2;
+      while (P < (uint32_t)kParts && 4 * P <= nch) P *= 2;
+      const bool mine = part < P;
+      const uint32_t lo = mine ? (uint32_t)((uint64_t)part * nch / P) : 0u;
+      const uint32_t len = mine ? (uint32_t)((uint64_t)(part + 1) * nch / P) - lo : 0u;
+      const uint32_t maxlen = (nch + P - 1) / P;
+      const bool wave_on = 2 * wv < P;  // wave-uniform: the wave holds a run
+      uint64_t done = 0;
+      uint32_t acc[K];
+      if (wave_on) {
+        // past this group's run the multiplier is the Montgomery form of 1;
+        // each partial is loaded one product ahead of its use
+        const uint64_t p0 = (uint64_t)first + lo;
+        uint32_t b[K], nb[K];
+        ld29<K, G>(acc, len ? ws.partials + (p0 * 2 + slot) * S29 : one29);
+        ld29<K, G>(nb, 1 < len ? ws.partials + ((p0 + 1) * 2 + slot) * S29 : one29);
+#pragma unroll 1
+        for (uint32_t k = 1; k < maxlen; ++k) {
+#pragma unroll
+          for (int j = 0; j < K; ++j) b[j] = nb[j];
+          if (k + 1 < maxlen) ld29<K, G>(nb, k + 1 < len ? ws.partials + ((p0 + k + 1) * 2 + slot) * S29 : one29);
+          mm29<K, G>(acc, b, acc, M, lds);
+        }
+        done += maxlen - 1;
       }
-      __syncthreads();
-      if (wave_join) {
-        uint32_t t[K];
-        mm29<K, G>(t, acc, other, M, lds);
-        select(acc, (g >> 1) == 0, t, acc);
+      // level d joins run p with run p + d for p a multiple of 2d; only the
+      // even runs (half 0 of a wave) ever join, so a wave joins or not as a
+      // whole
+      for (uint32_t d = 1; d < P; d <<= 1) {  // block-uniform
+        if (wave_on) st29<K, G>(lds, acc);
+        __syncthreads();
+        const bool wave_join = (2 * wv) % (2 * d) == 0 && 2 * wv + d < P;
+        uint32_t other[K];
+        if (wave_join) {
+          const uint32_t q = part + d;  // in range for the joining (even) runs
+          const uint32_t qr = half == 0 ? (q >> 1) * GW + ((q & 1u) << 1 | slot) : wv * GW + g;
+          ld29<K, G>(other, lds_all + qr * ROW);
+        }
+        __syncthreads();
+        if (wave_join) {
+          uint32_t t[K];
+          mm29<K, G>(t, acc, other, M, lds);
+          select(acc, half == 0, t, acc);
+          ++done;
+        }
+      }
+      if (wv == 0) {
+        final_out<G, K, K32>(acc, M, lds, J.hist + ((fb_f + bin) * 2 + slot) * S, half == 0);
         ++done;
       }
-    }
-    if (wv == 0) {
-      // out of Montgomery form (a product with 1), exact, back to 32-bit limbs
-      uint32_t one[K];
-      set_small<K, G>(one, 1u);
-      mm29<K, G>(acc, acc, one, M, lds);
-      canon29<K, G>(acc, M);
-      uint32_t y[K32];
-      to32<K, K32, G>(y, acc, lds);
-      if ((g >> 1) == 0) st<K32, G>(J.hist + ((fb_f + bin) * 2 + slot) * S, y);
-      ++done;
-    }
-    if (ws.mm_count && glane<G>() == 0) {
-      if (wave_on) atomicAdd(&ws.mm_count[1], (unsigned long long)done);
-      if (wv == 0 && (g >> 1) == 0) {
-        atomicAdd(&ws.mm_count[0], (unsigned long long)(nch ? nch - 1 : 0));
-        atomicAdd(&ws.mm_count[2], 1ull);
+      if (ws.mm_count && glane<G>() == 0) {
+        if (wave_on) atomicAdd(&ws.mm_count[1], (unsigned long long)done);
+        if (wv == 0 && half == 0) {
+          atomicAdd(&ws.mm_count[0], (unsigned long long)(nch - 1));
+          atomicAdd(&ws.mm_count[2], 1ull);
+        }
       }
     }
-    __syncthreads();  // the rows are reused by the block's next entry
+    // the rest, fewer than 4 partials each: one entry per wave
+    if (r + wv < r1) {  // wave-uniform
+      const uint32_t bin = bord[r + wv];
+      const uint64_t e = J.fb_off + fb_f + bin;
+      const uint32_t nch = ws.fch[e], first = ws.fitem[e];
+      const uint32_t n_lo = (nch + 1) >> 1, n_hi = nch >> 1;
+      const uint32_t my_n = half ? n_hi : n_lo;
+      const uint64_t p0 = (uint64_t)first + (half ? n_lo : 0u);
+      uint32_t acc[K];
+      ld29<K, G>(acc, my_n ? ws.partials + (p0 * 2 + slot) * S29 : one29);
+      if (n_lo > 1) {  // wave-uniform
+        uint32_t b[K];
+        ld29<K, G>(b, my_n > 1 ? ws.partials + ((p0 + 1) * 2 + slot) * S29 : one29);
+        mm29<K, G>(acc, b, acc, M, lds);
+      }
+      if (n_hi) {  // wave-uniform: join the halves
+        st29<K, G>(lds, acc);
+        __builtin_amdgcn_wave_barrier();
+        uint32_t other[K];
+        ld29<K, G>(other, lds_all + (wv * GW + (g ^ 2u)) * ROW);
+        __builtin_amdgcn_wave_barrier();
+        uint32_t t[K];
+        mm29<K, G>(t, acc, other, M, lds);
+        select(acc, half == 0, t, acc);
+      }
+      final_out<G, K, K32>(acc, M, lds, J.hist + ((fb_f + bin) * 2 + slot) * S, half == 0);
+      if (ws.mm_count && glane<G>() == 0) {
+        const uint64_t done = (n_lo > 1 ? 1 : 0) + (n_hi ? 1 : 0) + 1;
+        atomicAdd(&ws.mm_count[1], (unsigned long long)done);
+        if (half == 0) {
+          atomicAdd(&ws.mm_count[0], (unsigned long long)(nch ? nch - 1 : 0));
+          atomicAdd(&ws.mm_count[2], 1ull);
+        }
+      }
+    }
   }
 }
 
@@ -1531,7 +1597,8 @@ static hipError_t hist(const DKey &k, const uint32_t *ctm, const DJob *host_jobs
   }
   if (!narrow)
     hipLaunchKernelGGL((k_hist_chunk<KP, kHistGroup>), dim3(l.grid), dim3(kBlockThreads), l.dyn, s, k, ctm, ws);
-  const uint32_t fgrid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(ws.total_f * 256, 1u << 20));
+  const uint64_t final_units = ws.total_f * (kFinalSolo + (256 - kFinalSolo) / 4);
+  const uint32_t fgrid = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(final_units, 1u << 20));
   hipLaunchKernelGGL((k_hist_final<KP, kHistGroup>), dim3(fgrid), dim3(kBlockThreads), 0, s, k, ws);
   return hipGetLastError();
 }

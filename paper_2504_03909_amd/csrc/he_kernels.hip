@@ -1117,22 +1117,21 @@ __device__ __forceinline__ void final_out(uint32_t (&acc)[K], const Mod29<K> &M,
 }
 
 // Ranks (within a feature, by decreasing bin count) that k_hist_final takes
-// one per block; higher ranks go four to a block.
+// one per block; higher ranks go one per wave, four to a block.
 constexpr uint32_t kFinalSolo = 8;
 
 // Final product over the chunks of one (job, feature, bin), conversion out of
 // Montgomery form, and the store into the job's histogram.  A block takes
 // one rank of one (job, feature) among the first kFinalSolo ranks, else four
-// consecutive ranks; the units go rank-major over all (job, feature) pairs,
-// so the heaviest bins start first.  An entry of nch >= 4 partials is taken
-// by the whole block, its 16 groups as (slot g/h) x (8 runs): the partials
-// are cut into P runs of equal length (to one), P the largest power of two
-// that is at most 8 and at most nch / 2, each run's product is one group's
-// chain (about nch / P products instead of nch / 2), and the P products are
-// joined in log2(P) levels through LDS.  Ranks are in decreasing count, so
-// once an entry has fewer than 4 partials so have the block's remaining
-// ones; those are taken one per wave, its 4 groups as (slot) x (first or
-// second half of the partials).
+// consecutive ranks, one per wave; the units go rank-major over all
+// (job, feature) pairs, so the heaviest bins start first.
+//  * A block's own entry: its 16 groups are (slot g/h) x (8 runs); the
+//    entry's nch partials are cut into P runs of equal length (to one), P
+//    the largest power of two that is at most 8 and at most nch / 2, each
+//    run's product is one group's chain (about nch / P products instead of
+//    nch / 2), and the P products are joined in log2(P) levels through LDS.
+//  * A wave's entry: its 4 groups are (slot) x (first or second half of the
+//    partials), the halves joined at the end.
 template <int KP, int G>
 __global__ __launch_bounds__(kBlockThreads, 4) void k_hist_final(DKey key, HistWs ws) {
   static_assert(G == 16, "four groups per wave: two slots x two parts");
@@ -1148,30 +1147,18 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_hist_final(DKey key, HistW
   const uint64_t solo = ws.total_f * kFinalSolo;
   const uint64_t units = solo + ws.total_f * ((256 - kFinalSolo) / kWaves);  // ranks past a job's bins are skipped
   for (uint64_t u = blockIdx.x; u < units; u += gridDim.x) {
-    uint64_t jf;
-    uint32_t r, r1;
-    if (u < solo) {
-      jf = u % ws.total_f;
-      r = (uint32_t)(u / ws.total_f);
-      r1 = r + 1;
-    } else {
-      const uint64_t v = u - solo;
-      jf = v % ws.total_f;
-      r = kFinalSolo + kWaves * (uint32_t)(v / ws.total_f);
-      r1 = r + kWaves;
-    }
+    const bool whole = u < solo;  // block-uniform
+    const uint64_t v = whole ? u : u - solo;
+    const uint64_t jf = v % ws.total_f;
+    const uint32_t r = whole ? (uint32_t)(v / ws.total_f) : kFinalSolo + kWaves * (uint32_t)(v / ws.total_f) + wv;
     const DJob J = ws.jobs[find_job_by_f(ws.jobs, ws.n_jobs, jf)];
-    r1 = min(r1, J.B);
-    if (r >= r1) continue;  // block-uniform
+    if (whole && r >= J.B) continue;  // block-uniform
     const uint64_t fb_f = (jf - J.f_off) * J.B;  // the feature's first entry within the job
-    const uint32_t *bord = ws.border + J.fb_off + fb_f;
-    // entries of 4 or more partials, one at a time, the whole block in runs
-    for (; r < r1; ++r) {
-      const uint32_t bin = bord[r];
+    if (whole) {
+      const uint32_t bin = ws.border[J.fb_off + fb_f + r];
       const uint64_t e = J.fb_off + fb_f + bin;
       const uint32_t nch = ws.fch[e], first = ws.fitem[e];
-      if (nch < 4) break;  // block-uniform
-      uint32_t P = 2;
+      uint32_t P = 1;
       while (P < (uint32_t)kParts && 4 * P <= nch) P *= 2;
       const bool mine = part < P;
       const uint32_t lo = mine ? (uint32_t)((uint64_t)part * nch / P) : 0u;
@@ -1194,7 +1181,7 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_hist_final(DKey key, HistW
           if (k + 1 < maxlen) ld29<K, G>(nb, k + 1 < len ? ws.partials + ((p0 + k + 1) * 2 + slot) * S29 : one29);
           mm29<K, G>(acc, b, acc, M, lds);
         }
-        done += maxlen - 1;
+        done += maxlen ? maxlen - 1 : 0;
       }
       // level d joins run p with run p + d for p a multiple of 2d; only the
       // even runs (half 0 of a wave) ever join, so a wave joins or not as a
@@ -1224,24 +1211,26 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_hist_final(DKey key, HistW
       if (ws.mm_count && glane<G>() == 0) {
         if (wave_on) atomicAdd(&ws.mm_count[1], (unsigned long long)done);
         if (wv == 0 && half == 0) {
-          atomicAdd(&ws.mm_count[0], (unsigned long long)(nch - 1));
+          atomicAdd(&ws.mm_count[0], (unsigned long long)(nch ? nch - 1 : 0));
           atomicAdd(&ws.mm_count[2], 1ull);
         }
       }
-    }
-    // the rest, fewer than 4 partials each: one entry per wave
-    if (r + wv < r1) {  // wave-uniform
-      const uint32_t bin = bord[r + wv];
+      __syncthreads();  // the rows are reused by the block's next unit
+    } else if (r < J.B) {  // wave-uniform
+      const uint32_t bin = ws.border[J.fb_off + fb_f + r];
       const uint64_t e = J.fb_off + fb_f + bin;
       const uint32_t nch = ws.fch[e], first = ws.fitem[e];
       const uint32_t n_lo = (nch + 1) >> 1, n_hi = nch >> 1;
       const uint32_t my_n = half ? n_hi : n_lo;
       const uint64_t p0 = (uint64_t)first + (half ? n_lo : 0u);
-      uint32_t acc[K];
+      uint32_t acc[K], b[K], nb[K];
       ld29<K, G>(acc, my_n ? ws.partials + (p0 * 2 + slot) * S29 : one29);
-      if (n_lo > 1) {  // wave-uniform
-        uint32_t b[K];
-        ld29<K, G>(b, my_n > 1 ? ws.partials + ((p0 + 1) * 2 + slot) * S29 : one29);
+      ld29<K, G>(nb, 1 < my_n ? ws.partials + ((p0 + 1) * 2 + slot) * S29 : one29);
+#pragma unroll 1
+      for (uint32_t k = 1; k < n_lo; ++k) {
+#pragma unroll
+        for (int j = 0; j < K; ++j) b[j] = nb[j];
+        if (k + 1 < n_lo) ld29<K, G>(nb, k + 1 < my_n ? ws.partials + ((p0 + k + 1) * 2 + slot) * S29 : one29);
         mm29<K, G>(acc, b, acc, M, lds);
       }
       if (n_hi) {  // wave-uniform: join the halves
@@ -1256,7 +1245,7 @@ __global__ __launch_bounds__(kBlockThreads, 4) void k_hist_final(DKey key, HistW
       }
       final_out<G, K, K32>(acc, M, lds, J.hist + ((fb_f + bin) * 2 + slot) * S, half == 0);
       if (ws.mm_count && glane<G>() == 0) {
-        const uint64_t done = (n_lo > 1 ? 1 : 0) + (n_hi ? 1 : 0) + 1;
+        const uint64_t done = (n_lo ? n_lo - 1 : 0) + (n_hi ? 1 : 0) + 1;
         atomicAdd(&ws.mm_count[1], (unsigned long long)done);
         if (half == 0) {
           atomicAdd(&ws.mm_count[0], (unsigned long long)(nch ? nch - 1 : 0));

@@ -868,7 +868,8 @@ __global__ __launch_bounds__(256) void k_hist_count(HistWs ws) {
 // in bin order), chunk counts per bin and their local prefix, taken over the
 // bins in decreasing order of their counts (ties: lower bin first), so that
 // consecutive work items have about the same length and the waves that take
-// several items at once pad little; ftot = chunks of this feature.
+// several items at once pad little; ftot = chunks of this feature; border =
+// the feature's bins in that order (k_hist_final's entry order).
 __global__ __launch_bounds__(256) void k_hist_scan(HistWs ws) {
   __shared__ uint32_t sc[256], sh[256], cn[256];
   const uint64_t jf = blockIdx.x;
